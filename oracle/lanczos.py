@@ -1,0 +1,94 @@
+"""Spectral estimates mu_1, mu_nevex, mu_n from a few Lanczos steps
+(Section 4.1; Alg. 3, estimation step).
+
+PARITY UNPINNED: these are heuristics.  They change how many outer
+iterations the solver needs, never what it converges to; tests only bound
+them (mu_1 not far above lambda_1, mu_n >= the largest |lambda|).
+
+Reading taken (the paper defers the variant to Gruning et al. 2011 and only
+states that it uses S-inner products, an even step count and the
+sign flip after the product): Lanczos in the inner product
+``<x, y> = x^H (S H) y``.  H is self-adjoint in it (S H = H^H S) and it is
+positive definite in the definite case, so the recurrence cannot break down
+for a nonzero start.  Per step one product with H:
+
+    alpha_j = w_j^H S w_j                (w_j = H v_j)
+    r       = w_j - alpha_j v_j - beta_j v_{j-1}
+    z       = H r,   beta_{j+1} = sqrt(r^H S z)
+    v_{j+1} = r / beta_{j+1},   w_{j+1} = z / beta_{j+1}
+
+From the Ritz values theta and weights tau = |first eigenvector entry|^2 of
+the tridiagonal T (Section 2, ChASE spectral density):
+mu_1 = min |theta|; mu_n = max |theta| plus the Lanczos residual bound of
+the extreme Ritz value (Zhou 2011 style upper bound); mu_nevex = the
+positive theta at which the accumulated positive-axis weight reaches
+nevex / m (Section 4.1: density integrated over the positive axis only).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .hamiltonian import apply_h
+
+
+def _sdot(x, y):
+    """x^H S y."""
+    m = x.shape[0] // 2
+    return np.vdot(x[:m], y[:m]) - np.vdot(x[m:], y[m:])
+
+
+def lanczos_run(A, B, v0, steps):
+    """One S H - inner-product Lanczos run; returns (alpha, beta) with
+    ``len(alpha) == steps`` and ``beta[j]`` the coupling after step j."""
+    v = np.asarray(v0, dtype=np.complex128)
+    w = apply_h(A, B, v)
+    nrm = np.sqrt(np.real(_sdot(v, w)))
+    v, w = v / nrm, w / nrm
+    v_prev = np.zeros_like(v)
+    beta_prev = 0.0
+    alpha = np.zeros(steps)
+    beta = np.zeros(steps)
+    for j in range(steps):
+        a = np.real(_sdot(w, w))
+        r = w - a * v - beta_prev * v_prev
+        z = apply_h(A, B, r)
+        b = np.sqrt(max(np.real(_sdot(r, z)), 0.0))
+        alpha[j], beta[j] = a, b
+        if b == 0.0:
+            return alpha[: j + 1], beta[: j + 1]
+        v_prev, v, w, beta_prev = v, r / b, z / b, b
+    return alpha, beta
+
+
+def spectral_estimates(A, B, starts, steps, nevex):
+    """(mu_1, mu_nevex, mu_n) from len(starts[0]) Lanczos runs."""
+    m = A.shape[0]
+    thetas, weights = [], []
+    mu1 = np.inf
+    mu_n = 0.0
+    nruns = starts.shape[1]
+    for i in range(nruns):
+        a, b = lanczos_run(A, B, starts[:, i], steps)
+        T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+        th, Y = np.linalg.eigh(T)
+        tau = np.abs(Y[0, :]) ** 2
+        mu1 = min(mu1, float(np.min(np.abs(th))))
+        imax = int(np.argmax(np.abs(th)))
+        mu_n = max(mu_n, float(abs(th[imax]) + abs(b[-1] * Y[-1, imax])))
+        thetas.append(th)
+        weights.append(tau / nruns)
+    th = np.concatenate(thetas)
+    tau = np.concatenate(weights)
+    pos = th > 0
+    th, tau = th[pos], tau[pos]
+    order = np.argsort(th)
+    th, tau = th[order], tau[order]
+    cum = np.cumsum(tau) / np.sum(tau)
+    idx = int(np.searchsorted(cum, nevex / m))
+    idx = min(idx, len(th) - 1)
+    mu_nevex = float(th[idx])
+    if mu_nevex <= mu1:
+        above = th[th > mu1 * (1.0 + 1e-8)]
+        mu_nevex = float(above[0]) if len(above) else 0.5 * (mu1 + mu_n)
+    mu_nevex = min(mu_nevex, 0.99 * mu_n)
+    return mu1, mu_nevex, mu_n

@@ -1,0 +1,103 @@
+"""Pseudo-hermitian ChASE outer loop, plain FP64 (Alg. 3).
+
+Steps per outer iteration, in Alg. 3's order:
+ 1. filter the positive half, W_+ <- p(H^2) W_+                (Section 4.2)
+ 2. recover the negative half W_- = K conj(W_+)                (Thm 4.2)
+ 3. orthonormalise [S Y_+, S Y_-, W_+, W_-], Y_- = K conj(Y_+)  (Section 4.3, eq. 4.5)
+ 4. drop the 2*locked leading columns                          (Alg. 3)
+ 5. oblique Rayleigh-Ritz (Alg. 2)                             (Section 4.4)
+ 6. back-transform and residuals on the positive half only     (Section 4.5)
+ 7. lock converged pairs; mu_nevex <- largest positive Ritz    (Sections 2, 4.1)
+
+Readings (the paper is silent): a contiguous prefix of the wanted pairs
+with residual <= tol is locked each iteration; mu_1 and mu_n stay at their
+Lanczos values; per-vector degrees follow the Chebyshev convergence-factor
+bound ``d_j = ceil(ln(r_j / tol) / ln rho_j)`` clamped to [deg_min, deg_max]
+with ``rho_j = |t_j| + sqrt(t_j^2 - 1)``, ``t_j = (lambda_j^2 - c) / e``
+(Section 6.1 defers the rule to Winkelmann et al. 2019).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .chebyshev import chebyshev_filter, filter_params
+from .hamiltonian import apply_k_conj, apply_s
+from .lanczos import spectral_estimates
+from .qr import cholqr2
+from .rayleigh_ritz import oblique_rr
+from .residuals import back_transform, residual_norms
+
+
+def init_block(w0_raw: np.ndarray, gamma: float) -> np.ndarray:
+    """Alg. 3 first step / Section 4.6: random block with the lower half
+    scaled by gamma, keeping it deep in the S-positive manifold."""
+    m = w0_raw.shape[0] // 2
+    W = np.array(w0_raw, dtype=np.complex128, copy=True)
+    W[m:] *= gamma
+    return W
+
+
+def next_degrees(lam, resid, tol, mu1, mu_nevex, mu_n, deg_min, deg_max):
+    c, e, _ = filter_params(mu1, mu_nevex, mu_n)
+    out = np.empty(len(lam), dtype=int)
+    for j, (l, r) in enumerate(zip(lam, resid)):
+        t = abs((l * l - c) / e)
+        if t <= 1.0 + 1e-12 or r <= tol:
+            out[j] = deg_max if r > tol else deg_min
+            continue
+        rho = t + math.sqrt(t * t - 1.0)
+        d = math.ceil(math.log(r / tol) / math.log(rho))
+        out[j] = min(max(d, deg_min), deg_max)
+    return out
+
+
+def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3,
+          lanczos_steps=26, deg_min=None, deg_max=None, opt_deg=False):
+    """Return ``(lam, V, info)``: the nev smallest positive eigenvalues found
+    (ascending), unit right eigenvectors (n x nev) and an info dict."""
+    A = np.asarray(A, dtype=np.complex128)
+    B = np.asarray(B, dtype=np.complex128)
+    m = A.shape[0]
+    n = 2 * m
+    nevex = nev + nex
+    deg_min = deg if deg_min is None else deg_min
+    deg_max = deg if deg_max is None else deg_max
+    W = init_block(w0_raw, gamma)
+    starts = init_block(lanczos_raw, gamma)
+    mu1, mu_nevex, mu_n = spectral_estimates(A, B, starts, lanczos_steps, nevex)
+    Yp = np.zeros((n, 0), dtype=np.complex128)
+    lam_locked = []
+    degs = np.full(nevex, deg, dtype=int)
+    info = dict(mu1=mu1, mu_nevex0=mu_nevex, mu_n=mu_n, iterations=0,
+                locked_history=[], resid_history=[], shifted_qr=[], converged=False)
+    for it in range(max_iter):
+        locked = Yp.shape[1]
+        W = chebyshev_filter(A, B, W, degs, mu1, mu_nevex, mu_n)
+        X = np.concatenate([apply_s(Yp), apply_s(apply_k_conj(Yp)), W, apply_k_conj(W)], axis=1)
+        Q, _, shifted = cholqr2(X)
+        Q = Q[:, 2 * locked:]
+        lam, Z, _ = oblique_rr(A, B, Q)
+        V = back_transform(Q, Z)
+        r = residual_norms(A, B, V, lam)
+        nlock = 0
+        while nlock < nev - locked and r[nlock] <= tol:
+            nlock += 1
+        Yp = np.concatenate([Yp, V[:, :nlock]], axis=1)
+        lam_locked.extend(lam[:nlock].tolist())
+        W = V[:, nlock:]
+        mu_nevex = float(lam[-1])
+        info["iterations"] = it + 1
+        info["locked_history"].append(Yp.shape[1])
+        info["resid_history"].append(r.copy())
+        info["shifted_qr"].append(shifted)
+        if Yp.shape[1] >= nev:
+            info["converged"] = True
+            break
+        if opt_deg:
+            degs = next_degrees(lam[nlock:], r[nlock:], tol, mu1, mu_nevex, mu_n,
+                                deg_min, deg_max)
+        else:
+            degs = np.full(W.shape[1], deg, dtype=int)
+    return np.asarray(lam_locked), Yp, info

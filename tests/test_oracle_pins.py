@@ -1,0 +1,396 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle
+itself: a general (non-structured) eigensolver, 50-digit brute force,
+closed forms, invariants the paper proves, special cases that reduce to a
+textbook problem.  CPU only.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import adjoint, chebyshev, dense, hamiltonian as ham, lanczos, qr, rayleigh_ritz, residuals, solver
+from synth import make_problem, config_problem, complex_normal
+
+
+def small_problem(m, seed=0, coupling=0.4, lo=1.0, hi=5.0, nev=4, nex=3, deg=10, tol=1e-10):
+    return make_problem(m, lambda rng, mm: rng.uniform(lo, hi, size=mm), coupling,
+                        nev, nex, deg, tol, seed=seed)
+
+
+# ----------------------------------------------------------------- generator
+@pytest.mark.parametrize("cfg,m", [(0, 40), (1, 40), (2, 50), (3, 30), (4, 30)])
+def test_generator_structure(cfg, m):
+    p = config_problem(cfg, m=m)
+    assert np.allclose(p.A, p.A.conj().T, atol=0)
+    assert np.allclose(p.B, p.B.T, atol=0)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(p.A)), np.sort(p.d), atol=1e-12 * p.d.max())
+    nb = scipy.linalg.svdvals(p.B)[0]
+    assert abs(nb - p.coupling * p.d.min()) <= 1e-12 * nb
+    # Weyl: lambda_min(SH) >= (1 - c) min d  (definite case, eq. 1.3)
+    lmin = np.linalg.eigvalsh(ham.assemble_sh(p.A, p.B))[0]
+    assert lmin >= (1 - p.coupling) * p.d.min() - 1e-12
+
+
+def test_generator_clustered_counts():
+    p = config_problem(2, m=100)
+    assert np.sum((p.d >= 1.0) & (p.d <= 1.2)) == 80
+    assert np.sum(p.d > 1.2) == 20
+
+
+def test_generator_large_norm_path():
+    # the Lanczos path of ||B||_2 must agree with dense svd
+    p = make_problem(1300, lambda rng, m: rng.uniform(1, 2, m), 0.3, 2, 2, 4, 1e-8)
+    assert abs(scipy.linalg.svdvals(p.B)[0] - 0.3 * p.d.min()) < 1e-11
+
+
+# ------------------------------------------------ H structure (eq 1.1-1.3)
+def test_pseudo_hermitian_relation():
+    p = small_problem(12)
+    H = ham.assemble_h(p.A, p.B)
+    s = np.concatenate([np.ones(12), -np.ones(12)])
+    SH = s[:, None] * H
+    assert np.allclose(SH, H.conj().T * s[None, :], atol=1e-14)       # S H = H^H S
+    assert np.allclose(SH, ham.assemble_sh(p.A, p.B), atol=0)
+
+
+def test_apply_h_kconj_symmetry():
+    # Thm 3.1 / eq. 3.3: H v = lambda v  <=>  H K conj(v) = -lambda K conj(v)
+    p = small_problem(10)
+    lam, V = dense.dense_ph_eig(p.A, p.B)
+    W = ham.apply_k_conj(V)
+    assert np.allclose(ham.apply_h(p.A, p.B, W), -W * lam[None, :], atol=1e-12)
+
+
+# --------------------------------------------------------- dense oracle
+@pytest.mark.parametrize("m,seed", [(4, 0), (8, 1), (16, 2), (32, 3)])
+def test_dense_vs_general_eig(m, seed):
+    p = small_problem(m, seed=seed)
+    lam, V = dense.dense_ph_eig(p.A, p.B)
+    w = np.linalg.eigvals(ham.assemble_h(p.A, p.B))
+    assert np.max(np.abs(w.imag)) < 1e-10                 # Thm 3.2: real spectrum
+    wr = np.sort(w.real)
+    assert np.allclose(wr[m:], lam, rtol=1e-11, atol=0)  # positive half
+    assert np.allclose(wr[:m], -lam[::-1], rtol=1e-11)    # +/- pairs (Thm 3.1)
+    H = ham.assemble_h(p.A, p.B)
+    assert np.max(np.abs(H @ V - V * lam[None, :])) < 1e-12 * np.abs(lam).max()
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0)
+
+
+@pytest.mark.parametrize("m", [4, 8])
+def test_dense_vs_mpmath_bruteforce(m):
+    p = small_problem(m, seed=7)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    mpmath.mp.dps = 50
+    H = ham.assemble_h(p.A, p.B)
+    Hm = mpmath.matrix([[mpmath.mpc(complex(H[i, j])) for j in range(2 * m)] for i in range(2 * m)])
+    ev = mpmath.eig(Hm, left=False, right=False)
+    ev = sorted(float(mpmath.re(e)) for e in ev)
+    assert max(abs(float(mpmath.im(e))) for e in mpmath.eig(Hm, left=False, right=False)) < 1e-30
+    assert np.allclose(np.array(ev[m:]), lam, rtol=1e-13, atol=0)
+
+
+def test_b_zero_reduces_to_tda():
+    # Section 1.1: B = 0 gives the Hermitian problem A X = X Omega;
+    # spectrum is +/- eig(A), vectors [x; 0].
+    p = small_problem(12)
+    lam, V = dense.dense_ph_eig(p.A, np.zeros_like(p.B))
+    assert np.allclose(lam, np.sort(p.d), rtol=1e-12)
+    assert np.max(np.abs(V[12:])) < 1e-12
+
+
+def test_interval_and_upper_bound():
+    # Lemma 3.3 (|lambda| <= rho(A)) and the Shao bound lambda_i <= omega_i(A)
+    p = small_problem(20, coupling=0.6)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    om = np.sort(p.d)
+    assert np.all(lam <= om + 1e-12)
+    assert lam.max() <= om.max() + 1e-12
+
+
+def test_bi_orthogonality():
+    # eq. 3.5-3.6: D = V^H S V diagonal, D_- = -D_+, V_+^H S V_- = 0
+    p = small_problem(10)
+    lam, Vp = dense.dense_ph_eig(p.A, p.B)
+    Vm = ham.apply_k_conj(Vp)
+    V = np.concatenate([Vp, Vm], axis=1)
+    D = V.conj().T @ ham.apply_s(V)
+    off = D - np.diag(np.diag(D))
+    assert np.max(np.abs(off)) < 1e-12
+    dp = np.real(np.diag(D)[:10])
+    dm = np.real(np.diag(D)[10:])
+    assert np.all(dp > 0) and np.allclose(dm, -dp)
+
+
+def test_condition_numbers_equal():
+    # Thm 3.4: cond(SH) = cond(H)
+    p = small_problem(10)
+    H = ham.assemble_h(p.A, p.B)
+    c1 = np.linalg.cond(H)
+    c2 = np.linalg.cond(ham.assemble_sh(p.A, p.B))
+    assert abs(c1 - c2) < 1e-10 * c1
+
+
+def test_inertia_count_matches():
+    # Hv = lambda v <=> S v = lambda^{-1} (SH) v, a definite pencil, so the
+    # positive inertia of sigma S - SH counts the eigenvalues in (0, sigma).
+    p = small_problem(16)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    s = np.concatenate([np.ones(16), -np.ones(16)])
+    for sigma in [0.5 * (lam[3] + lam[4]), 0.5 * (lam[9] + lam[10])]:
+        M = sigma * np.diag(s) - ham.assemble_sh(p.A, p.B)
+        npos = int(np.sum(np.linalg.eigvalsh(M) > 0))
+        assert npos == int(np.sum((lam > 0) & (lam < sigma)))
+
+
+# ------------------------------------------------------- Chebyshev filter
+def _cheb_T(d, t):
+    """T_d(t) from its trigonometric/hyperbolic closed form."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.empty_like(t)
+    a = np.abs(t) <= 1
+    out[a] = np.cos(d * np.arccos(t[a]))
+    b = t > 1
+    out[b] = np.cosh(d * np.arccosh(t[b]))
+    c = t < -1
+    out[c] = (-1) ** d * np.cosh(d * np.arccosh(-t[c]))
+    return out
+
+
+@pytest.mark.parametrize("deg", [1, 2, 5, 12])
+def test_filter_closed_form_on_eigenvectors(deg):
+    p = small_problem(20)
+    lam, Vp = dense.dense_ph_eig(p.A, p.B)
+    mu1, mu_nevex, mu_n = 0.9 * lam[0], lam[6], 1.05 * lam[-1]
+    V = np.concatenate([Vp[:, :8], ham.apply_k_conj(Vp[:, :3]), Vp[:, -2:]], axis=1)
+    lv = np.concatenate([lam[:8], -lam[:3], lam[-2:]])
+    c = 0.5 * (mu_n ** 2 + mu_nevex ** 2)
+    e = 0.5 * (mu_n ** 2 - mu_nevex ** 2)
+    ratio = _cheb_T(deg, (lv ** 2 - c) / e) / _cheb_T(deg, np.array([(mu1 ** 2 - c) / e]))[0]
+    out = chebyshev.chebyshev_filter(p.A, p.B, V, deg, mu1, mu_nevex, mu_n)
+    expect = V * ratio[None, :]
+    scale = np.maximum(np.abs(ratio), 1.0)
+    assert np.max(np.abs(out - expect) / scale[None, :]) < 1e-10
+
+
+def test_filter_per_column_degrees_closed_form():
+    p = small_problem(16)
+    lam, Vp = dense.dense_ph_eig(p.A, p.B)
+    mu1, mu_nevex, mu_n = lam[0], lam[5], lam[-1]
+    degs = np.array([3, 3, 7, 10, 1, 7])
+    V = Vp[:, :6]
+    out = chebyshev.chebyshev_filter(p.A, p.B, V, degs, mu1, mu_nevex, mu_n)
+    c = 0.5 * (mu_n ** 2 + mu_nevex ** 2)
+    e = 0.5 * (mu_n ** 2 - mu_nevex ** 2)
+    for j in range(6):
+        r = _cheb_T(degs[j], np.array([(lam[j] ** 2 - c) / e]))[0] / \
+            _cheb_T(degs[j], np.array([(mu1 ** 2 - c) / e]))[0]
+        assert np.allclose(out[:, j], r * V[:, j], rtol=0, atol=1e-10 * max(1, abs(r)))
+
+
+def test_filter_kconj_equivariance():
+    # Thm 4.2: p(H^2) K conj(W) = K conj(p(H^2) W)
+    p = small_problem(14)
+    rng = np.random.default_rng(3)
+    W = complex_normal(rng, (28, 5))
+    f = lambda X: chebyshev.chebyshev_filter(p.A, p.B, X, 6, 1.0, 2.0, 5.5)
+    a = f(ham.apply_k_conj(W))
+    b = ham.apply_k_conj(f(W))
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+
+
+# ------------------------------------------------------------------ QR
+def _phase_normalised_qr(X):
+    Qn, Rn = np.linalg.qr(X)
+    ph = np.diag(Rn) / np.abs(np.diag(Rn))
+    return Qn * ph[None, :], Rn * ph.conj()[:, None]
+
+
+def test_cholqr2_matches_householder():
+    rng = np.random.default_rng(0)
+    X = complex_normal(rng, (200, 30))
+    Q, R, shifted = qr.cholqr2(X)
+    assert not shifted
+    Qr, Rr = _phase_normalised_qr(X)
+    assert np.allclose(Q, Qr, atol=1e-12)
+    assert np.allclose(R, Rr, atol=1e-11)
+    assert np.allclose(np.diag(R).imag, 0) and np.all(np.diag(R).real > 0)
+    assert np.allclose(np.triu(R), R)
+
+
+def test_cholqr_shifted_fallback_ill_conditioned():
+    rng = np.random.default_rng(1)
+    n, k = 300, 20
+    U, _ = np.linalg.qr(complex_normal(rng, (n, k)))
+    Vh, _ = np.linalg.qr(complex_normal(rng, (k, k)))
+    s = np.logspace(0, -13, k)
+    X = (U * s[None, :]) @ Vh.conj().T
+    Q, R, shifted = qr.cholqr2(X)
+    assert shifted
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(k))) < 1e-12
+    assert np.max(np.abs(Q @ R - X)) < 1e-13 * np.linalg.norm(X, 2) * 10
+
+
+# -------------------------------------------------------- oblique RR
+def _search_basis(p, k_half, seed=0, gamma=1e-3):
+    rng = np.random.default_rng(seed)
+    W = solver.init_block(complex_normal(rng, (2 * p.m, k_half)), gamma)
+    W = chebyshev.chebyshev_filter(p.A, p.B, W, 4, 0.8, 2.0, 5.5)
+    X = np.concatenate([W, ham.apply_k_conj(W)], axis=1)
+    Q, _, _ = qr.cholqr2(X)
+    return Q
+
+
+def test_rr_matches_explicit_nonhermitian_quotient():
+    p = small_problem(30)
+    Q = _search_basis(p, 6)
+    lam, Z, T = rayleigh_ritz.oblique_rr(p.A, p.B, Q)
+    QSQ = Q.conj().T @ ham.apply_s(Q)
+    QSHQ = Q.conj().T @ ham.apply_s(ham.apply_h(p.A, p.B, Q))
+    G = np.linalg.solve(QSQ, QSHQ)                        # eq. 4.7
+    w, Zg = np.linalg.eig(G)
+    assert np.max(np.abs(w.imag)) < 1e-9
+    wp = np.sort(w.real[w.real > 0])
+    assert np.allclose(lam, wp, rtol=1e-10)
+    assert np.allclose(G @ Z, Z * lam[None, :], atol=1e-9 * np.abs(Z).max())
+    assert np.allclose(T, ham.apply_h(p.A, p.B, Q))
+
+
+def test_rr_plus_minus_symmetry():
+    # Thm 4.5: Ritz values +/- symmetric; Q Z_- = K conj(Q Z_+)
+    p = small_problem(30)
+    Q = _search_basis(p, 5, seed=2)
+    lam, Z, _, allv = rayleigh_ritz.oblique_rr(p.A, p.B, Q, return_all=True)
+    assert np.allclose(np.sort(allv), np.sort(-allv), rtol=1e-10)
+    QSQ = Q.conj().T @ ham.apply_s(Q)
+    QSHQ = Q.conj().T @ ham.apply_s(ham.apply_h(p.A, p.B, Q))
+    w, Zg = np.linalg.eig(np.linalg.solve(QSQ, QSHQ))
+    for j in range(len(lam)):
+        i = int(np.argmin(np.abs(w - (-lam[j]))))
+        vm = Q @ Zg[:, i]
+        vp = ham.apply_k_conj(Q @ Z[:, j])
+        # equal up to a complex scalar
+        c = np.vdot(vp, vm) / np.vdot(vp, vp)
+        assert np.linalg.norm(vm - c * vp) < 1e-8 * np.linalg.norm(vm)
+
+
+def test_rr_exact_invariant_subspace():
+    p = small_problem(24)
+    lam, Vp = dense.dense_ph_eig(p.A, p.B)
+    X = np.concatenate([Vp[:, :5], ham.apply_k_conj(Vp[:, :5])], axis=1)
+    Q, _, _ = qr.cholqr2(X)
+    lr, Z, _ = rayleigh_ritz.oblique_rr(p.A, p.B, Q)
+    assert np.allclose(lr, lam[:5], rtol=1e-12)
+    V = residuals.back_transform(Q, Z)
+    assert np.max(residuals.residual_norms(p.A, p.B, V, lr)) < 1e-12
+
+
+def test_rr_quadratic_convergence():
+    # Lemma 5.5: |lambda - lambda~| = O(sigma_v^2)
+    p = small_problem(30)
+    lam, Vp = dense.dense_ph_eig(p.A, p.B)
+    rng = np.random.default_rng(5)
+    E = complex_normal(rng, (60, 4))
+    errs = []
+    epss = [1e-2, 1e-3, 1e-4]
+    for eps in epss:
+        Wp = Vp[:, :4] + eps * E
+        X = np.concatenate([Wp, ham.apply_k_conj(Wp)], axis=1)
+        Q, _, _ = qr.cholqr2(X)
+        lr, _, _ = rayleigh_ritz.oblique_rr(p.A, p.B, Q)
+        errs.append(np.max(np.abs(lr - lam[:4])))
+    slopes = np.diff(np.log10(errs)) / np.diff(np.log10(epss))
+    assert np.all(slopes > 1.8), slopes
+
+
+def test_rr_ritz_values_in_field_of_values_interval():
+    # Thm 5.6
+    p = small_problem(30)
+    Q = _search_basis(p, 6, seed=4)
+    _, _, _, allv = rayleigh_ritz.oblique_rr(p.A, p.B, Q, return_all=True)
+    QSQ = Q.conj().T @ ham.apply_s(Q)
+    lmin = np.min(np.abs(np.linalg.eigvalsh(0.5 * (QSQ + QSQ.conj().T))))
+    rho = np.max(np.abs(np.linalg.eigvalsh(ham.assemble_sh(p.A, p.B))))
+    assert np.all(np.abs(allv) <= rho / lmin * (1 + 1e-12))
+    assert lmin <= 1.0 + 1e-12
+
+
+# ------------------------------------------------------------- solver
+def test_solver_matches_dense():
+    p = small_problem(60, nev=6, nex=4, deg=10, tol=1e-10)
+    lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, p.deg, p.tol, p.w0_raw, p.lanczos_raw)
+    ref, _ = dense.smallest_positive(p.A, p.B, p.nev)
+    assert info["converged"]
+    assert np.allclose(lam, ref, rtol=1e-10, atol=0)
+    r = residuals.residual_norms(p.A, p.B, V, lam)
+    assert np.all(r <= p.tol)
+    D = V.conj().T @ ham.apply_s(V)                    # S-orthogonality (eq. 3.5)
+    assert np.max(np.abs(D - np.diag(np.diag(D)))) < 1e-9
+    assert np.all(np.real(np.diag(D)) > 0)
+
+
+def test_solver_b_zero_case():
+    p = small_problem(50, nev=5, nex=4, deg=10, tol=1e-10)
+    lam, V, info = solver.solve(p.A, np.zeros_like(p.B), p.nev, p.nex, p.deg, p.tol,
+                                p.w0_raw, p.lanczos_raw)
+    assert np.allclose(lam, np.sort(p.d)[:5], rtol=1e-10)
+    assert np.max(np.abs(V[50:])) < 1e-8
+
+
+def test_solver_per_vector_degrees():
+    p = small_problem(60, nev=6, nex=4, deg=12, tol=1e-10)
+    lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, p.deg, p.tol, p.w0_raw,
+                                p.lanczos_raw, deg_min=4, deg_max=16, opt_deg=True)
+    ref, _ = dense.smallest_positive(p.A, p.B, p.nev)
+    assert np.allclose(lam, ref, rtol=1e-10)
+
+
+def test_solver_max_iter_partial():
+    p = small_problem(60, nev=6, nex=4, deg=2, tol=1e-14)
+    lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, p.deg, p.tol, p.w0_raw,
+                                p.lanczos_raw, max_iter=1)
+    assert not info["converged"] and info["iterations"] == 1
+
+
+def test_lanczos_estimates_bounds():
+    # parity unpinned heuristic: only bounded
+    p = small_problem(80)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    mu1, mu_nevex, mu_n = lanczos.spectral_estimates(
+        p.A, p.B, solver.init_block(p.lanczos_raw, 1e-3), 26, p.nevex)
+    assert mu_n >= lam[-1] * (1 - 1e-10)
+    assert mu1 <= 1.2 * lam[0]
+    assert mu1 < mu_nevex < mu_n
+
+
+# ------------------------------------------------------------ adjoint
+def test_adjoint_central_fd():
+    p = small_problem(20)
+    nev = 5
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(nev)
+    lam, V = dense.smallest_positive(p.A, p.B, nev)
+    GA, GB = adjoint.eigval_grad(V, g)
+    assert np.allclose(GA, GA.conj().T) and np.allclose(GB, GB.T)
+    h = 1e-6
+    for _ in range(4):
+        EA = complex_normal(rng, (20, 20))
+        EA = 0.5 * (EA + EA.conj().T)
+        EB = complex_normal(rng, (20, 20))
+        EB = 0.5 * (EB + EB.T)
+        lp, _ = dense.smallest_positive(p.A + h * EA, p.B + h * EB, nev)
+        lm, _ = dense.smallest_positive(p.A - h * EA, p.B - h * EB, nev)
+        fd = (g @ lp - g @ lm) / (2 * h)
+        an = np.real(np.vdot(GA, EA)) + np.real(np.vdot(GB, EB))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+def test_adjoint_scale_invariance():
+    # the formula is homogeneous of degree 0 in each eigenvector
+    p = small_problem(12)
+    lam, V = dense.smallest_positive(p.A, p.B, 3)
+    g = np.array([1.0, -2.0, 0.5])
+    a1 = adjoint.eigval_grad(V, g)
+    a2 = adjoint.eigval_grad(V * np.array([2.0, 1j, -0.3])[None, :], g)
+    assert np.allclose(a1[0], a2[0]) and np.allclose(a1[1], a2[1])
