@@ -1,0 +1,198 @@
+/*
+ * chase_ph.h -- C ABI of the MI355X (gfx950) pseudo-hermitian ChASE hot path.
+ *
+ * Method: Di Napoli, Richefort, Wu, "Chebyshev Accelerated Subspace
+ * Eigensolver for Pseudo-hermitian Hamiltonians" (arXiv:2601.10557).
+ * Problem (Section 1, eqs. 1.1-1.3): the nev smallest positive eigenpairs of
+ *     H = [[A, B], [-conj(B), -conj(A)]],  A = A^H,  B = B^T  (m x m each),
+ * n = 2m, in the definite case SH = [[A, B], [conj(B), conj(A)]] > 0 with
+ * S = diag(I, -I).  K = [[0, I], [I, 0]] (Thm 3.1).
+ *
+ * Conventions shared by every entry point
+ * --------------------------------------
+ * - Matrices are column-major with an explicit leading dimension (in
+ *   elements).  Complex numbers are interleaved (re, im) pairs: "c128" is
+ *   two doubles (torch.complex128), "c64" two floats (torch.complex64).
+ * - Pointers named d* are device pointers; h* are host pointers.
+ * - Device buffers passed in are borrowed: the caller owns them.  A and B
+ *   given to chase_ph_create must stay valid and unmodified until
+ *   chase_ph_destroy.  All workspace is owned by the handle.
+ * - Every call is ordered on the HIP stream given at create time.  Calls
+ *   that return host values synchronise that stream before returning.
+ * - Errors are reported by status code only; the library never aborts.
+ *   Argument errors are detected before any GPU work is queued.  After a
+ *   CHASE_PH_ERR_HIP the handle is unusable and must be destroyed.
+ *   chase_ph_last_error() returns a handle-owned message for the last error.
+ * - One handle per host thread; calls on one handle must not overlap.
+ * - No entry point falls back to host computation: every step of the
+ *   numerical path runs in the library's own GPU kernels.
+ */
+#ifndef CHASE_PH_H
+#define CHASE_PH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chase_ph_s* chase_ph_t;
+
+typedef enum {
+  CHASE_PH_OK = 0,
+  CHASE_PH_ERR_ARG = 1,           /* bad pointer, size, leading dimension or parameter      */
+  CHASE_PH_ERR_ALLOC = 2,         /* device or host allocation failed                       */
+  CHASE_PH_ERR_HIP = 3,           /* a HIP runtime call or kernel launch failed (sticky)    */
+  CHASE_PH_ERR_NOT_DEFINITE = 4,  /* Cholesky of Q^H S H Q failed: SH not HPD on range(Q)   */
+  CHASE_PH_ERR_QR = 5,            /* CholeskyQR2 and its shifted fallback both failed       */
+  CHASE_PH_ERR_SINGULAR_QSQ = 6,  /* Q^H S Q numerically singular (Section 4.4)             */
+  CHASE_PH_ERR_NO_CONVERGENCE = 7 /* max_iter reached; info->locked pairs are valid         */
+} chase_ph_status;
+
+typedef enum {
+  CHASE_PH_FP64 = 0,  /* filter in complex FP64 (c128)                                       */
+  CHASE_PH_MIXED = 1, /* filter in complex FP32 (c64) until the switch residual, then FP64;  */
+                      /* QR, Rayleigh-Ritz, residuals and locking always in FP64            */
+  CHASE_PH_FP32 = 2   /* stage calls only: run one apply_h / filter in c64                   */
+} chase_ph_precision;
+
+/* Solver parameters (Alg. 3 inputs plus the paper's defaults).  Fill with
+ * chase_ph_default_params() and override. */
+typedef struct {
+  int64_t m;            /* block size; n = 2m                                               */
+  int32_t nev;          /* wanted smallest positive eigenpairs                              */
+  int32_t nex;          /* extra search vectors; nevex = nev + nex <= m                    */
+  int32_t deg;          /* Chebyshev degree in H^2 (applications of H^2 per filter)         */
+  int32_t deg_min;      /* per-vector degree range (Section 6.1: 8..20)                     */
+  int32_t deg_max;
+  int32_t opt_deg;      /* 1: per-vector degrees from the convergence-factor bound          */
+  int32_t max_iter;     /* outer iterations (Section 6.1: 25)                               */
+  double tol;           /* absolute residual ||H v - lambda v||_2 on unit v                 */
+  int32_t precision;    /* chase_ph_precision: FP64 or MIXED                                */
+  double switch_tol;    /* MIXED: residual below which columns are filtered in FP64;        */
+                        /* <= 0 selects 1e-5 * mu_n                                          */
+  double gamma;         /* lower-half scaling of the initial block (Section 4.6: 1e-3)      */
+  int32_t lanczos_steps;/* per run, even (Section 4.1; 26)                                  */
+  int32_t lanczos_vecs; /* independent Lanczos runs (4)                                     */
+  int32_t a_conj;       /* 1: the buffer dA holds conj(A) column-major (= A row-major)      */
+} chase_ph_params;
+
+typedef struct {
+  int32_t iterations;      /* outer iterations run                                          */
+  int32_t locked;          /* converged pairs returned                                      */
+  int32_t shifted_qr_used; /* times the shifted CholeskyQR fallback was taken               */
+  int32_t switch_iter;     /* MIXED: first iteration with an FP64 filter (-1: never)        */
+  double mu1, mu_nevex0, mu_n; /* Lanczos spectral estimates                                */
+  double t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds (stream-timed)       */
+  double filter_flops;     /* 16 n^2 per active column per degree                           */
+  double rr_flops;         /* 8 n^2 k + 12 n k^2 + CholeskyQR2 16 n k^2 per iteration        */
+  double filter_flops_fp32;/* part of filter_flops done in c64                              */
+  double* resid_history;   /* optional host array (caller-owned) of max_iter * nevex        */
+  int32_t resid_history_len; /* capacity of resid_history in doubles (0 if NULL)           */
+} chase_ph_info;
+
+/* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos
+ * steps x 4 runs, FP64, tol 1e-10, opt_deg 0. */
+void chase_ph_default_params(chase_ph_params* p);
+
+/* Create a solver handle for H built from the m x m blocks at dA, dB
+ * (device, c128, column-major, leading dimension ld >= m).  dA must be
+ * Hermitian, dB complex symmetric.  hip_stream may be NULL (default
+ * stream).  Allocates all workspace for nevex = nev + nex columns, plus
+ * the c64 copies of A and B when precision is MIXED.  Section 1, eq. 1.1. */
+chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const void* dB,
+                                int64_t ld, void* hip_stream, chase_ph_t* out);
+
+/* Free all handle-owned memory.  Accepts NULL. */
+chase_ph_status chase_ph_destroy(chase_ph_t h);
+
+const char* chase_ph_last_error(chase_ph_t h);
+
+/* Y = H X for an n x k block (Section 1, eq. 1.1; the product behind every
+ * GEMM of Alg. 2 and eq. 4.1).  prec: CHASE_PH_FP64 -> dX, dY are c128 and
+ * the c128 A, B are used; CHASE_PH_FP32 -> dX, dY are c64 and the c64
+ * copies of A, B are used (created on first use).  dX and dY must not
+ * overlap.  0 <= k; ldx, ldy >= n. */
+chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_t ldx,
+                                 void* dY, int64_t ldy, int32_t prec);
+
+/* In place W <- p(H^2) W for an n x k block through the scaled three-term
+ * Chebyshev recurrence of eq. 4.1 (Section 4.2, Thm 4.2: only the positive
+ * half is filtered).  degs: host array of k degrees, non-decreasing, each
+ * >= 1 (NULL: every column gets p->deg).  The filter damps
+ * [mu_nevex^2, mu_n^2] and is normalised at mu1^2 (0 < mu1 < mu_nevex < mu_n).
+ * prec as in chase_ph_apply_h: FP64 -> dW c128, FP32 -> dW c64. */
+chase_ph_status chase_ph_filter(chase_ph_t h, int32_t k, void* dW, int64_t ldw,
+                                const int32_t* degs, double mu1, double mu_nevex,
+                                double mu_n, int32_t prec);
+
+/* In place CholeskyQR2 of an n x k c128 block dX (Section 2: Cholesky QR
+ * orthonormalisation; shifted CholeskyQR3 fallback when the first
+ * factorisation breaks down).  On return dX holds Q with Q^H Q = I and,
+ * if dR is non-NULL, dR (k x k c128, ldr >= k) holds the upper-triangular
+ * R with positive real diagonal and X = Q R.  *used_shift (host, may be
+ * NULL) is set to 1 if the fallback ran.  CHASE_PH_ERR_QR if both fail.
+ * k <= 2 * nevex. */
+chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void* dR,
+                            int64_t ldr, int32_t* used_shift);
+
+/* Oblique Rayleigh-Ritz of Alg. 2 on an orthonormal n x k c128 block dQ
+ * (k even, k <= 2 * nevex; Section 4.4, Thm 4.4, Thm 4.5):
+ *   T = H Q; M = Q^H S T; L = chol(M); N = I - 2 Q2^H Q2;
+ *   G = L^{-1} N L^{-H}; G Y = Y Theta; lambda = 1/theta; Z = L^{-H} Y.
+ * Outputs the k/2 positive Ritz values ascending (hRitz, host), the
+ * matching k x k/2 coefficient block dZpos (c128, ldz >= k; Ritz vectors
+ * are Q Z, not normalised), and dT = H Q (n x k c128, ldt >= n) for reuse
+ * by chase_ph_residuals.  CHASE_PH_ERR_NOT_DEFINITE if chol(M) fails,
+ * CHASE_PH_ERR_SINGULAR_QSQ if fewer than k/2 positive or k/2 negative
+ * eigenvalues of G are resolved away from zero. */
+chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq,
+                                    double* hRitz, void* dZpos, int64_t ldz, void* dT,
+                                    int64_t ldt);
+
+/* Half back-transform and residuals (Section 4.5): for the first kk
+ * columns of dZpos, V = Q Z (normalised to unit 2-norm, written to dV,
+ * n x kk c128) and resid_j = ||H v_j - lambda_j v_j||_2 computed from the
+ * T = H Q of chase_ph_oblique_rr as ||T z_j / nu_j - lambda_j v_j||_2.
+ * hRitz: host, kk values; hResid: host out, kk values. */
+chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const void* dQ,
+                                   int64_t ldq, const void* dT, int64_t ldt,
+                                   const void* dZpos, int64_t ldz, const double* hRitz,
+                                   void* dV, int64_t ldv, double* hResid);
+
+/* Run Alg. 3 to completion: Lanczos estimates, then filter / QR /
+ * Rayleigh-Ritz / residuals / locking until nev pairs are locked or
+ * max_iter.  The random initial block (n x nevex) and Lanczos starts
+ * (n x lanczos_vecs) are inputs: dW0 and dLz are device c128 buffers with
+ * unscaled complex Gaussian entries (the library applies the gamma
+ * scaling of Section 4.6); they are not modified.  Outputs: hEvals (host,
+ * nev, ascending), dV (device c128 n x nev, ldv >= n, unit columns),
+ * hResid (host, nev, may be NULL), info (may be NULL).  Returns
+ * CHASE_PH_ERR_NO_CONVERGENCE with info->locked valid pairs if max_iter is
+ * reached first. */
+chase_ph_status chase_ph_solve(chase_ph_t h, const void* dW0, int64_t ldw0, const void* dLz,
+                               int64_t ldlz, double* hEvals, void* dV, int64_t ldv,
+                               double* hResid, chase_ph_info* info);
+
+/* Eigenvalue adjoint for L = sum_i g_i lambda_i over converged pairs (not
+ * in the paper; derived from Thm 3.2, u = S v, and eq. 3.5):
+ *   G_A = sum_i gt_i (x_i x_i^H + conj(y_i) conj(y_i)^H),
+ *   G_B = sum_i gt_i (x_i y_i^H + conj(y_i) x_i^T),
+ *   gt_i = g_i / (x_i^H x_i - y_i^H y_i),   v_i = [x_i; y_i] = column i of dV,
+ * in the convention grad = dL/dRe + i dL/dIm, projected on Hermitian dA and
+ * symmetric dB.  dV: n x nev c128; hG: host nev; dGA, dGB: m x m c128
+ * outputs with leading dimension ldg >= m (overwritten). */
+chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* dV,
+                                         int64_t ldv, const double* hG, void* dGA,
+                                         void* dGB, int64_t ldg);
+
+/* Timing of the most recent chase_ph_apply_h / chase_ph_filter launch
+ * sequence in milliseconds (HIP events on the handle's stream) and the
+ * number of apply_h kernel launches it contained. */
+chase_ph_status chase_ph_last_timing(chase_ph_t h, double* ms, int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHASE_PH_H */

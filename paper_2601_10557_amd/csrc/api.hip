@@ -1,0 +1,890 @@
+// Host side of libchase_ph: handle, workspace, stage entry points and the
+// outer loop of the pseudo-hermitian ChASE solver (Alg. 3).  Every numerical
+// step is a kernel of this library; the host only sequences launches, keeps
+// O(k) scalars (Ritz values, residuals, degrees, spectral estimates) and
+// diagonalises the tiny Lanczos tridiagonals.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "dense.h"
+#include "vec.h"
+
+using namespace chase;
+
+struct chase_ph_s {
+  chase_ph_params p{};
+  const c128* A = nullptr;
+  const c128* B = nullptr;
+  int64_t ld = 0;
+  hipStream_t st = nullptr;
+  int64_t m = 0, n = 0;
+  int nevex = 0, kmax = 0, kp = 0;
+  // c64 copies of A and B (mixed / FP32 filter)
+  c64* A32 = nullptr;
+  c64* B32 = nullptr;
+  int64_t ld32 = 0;
+  // filter work buffers (n x nevex)
+  c128* F1 = nullptr;
+  c128* FT = nullptr;
+  c64* W32 = nullptr;
+  c64* F1_32 = nullptr;
+  c64* FT_32 = nullptr;
+  // QR / RR (n x kmax)
+  c128* Xs = nullptr;
+  c128* Xt = nullptr;
+  c128* Tq = nullptr;
+  c128* Vt = nullptr;
+  c128* TZ = nullptr;
+  // small padded (kp x kp)
+  c128* G = nullptr;
+  c128* L1 = nullptr;
+  c128* L2 = nullptr;
+  c128* L3 = nullptr;
+  c128* Li = nullptr;
+  c128* Nb = nullptr;
+  c128* Tk = nullptr;
+  c128* Ev = nullptr;
+  c128* Ys = nullptr;
+  c128* Zp = nullptr;  // kmax x kmax/2
+  // solver state
+  c128* Ylock = nullptr;  // n x nev
+  c128* Wk = nullptr;     // n x nevex
+  double* dlam = nullptr;
+  double* dres = nullptr;
+  int* dperm = nullptr;
+  // Lanczos (n x lanczos_vecs each)
+  c128 *lv = nullptr, *lvp = nullptr, *lw = nullptr, *lr = nullptr, *lz = nullptr;
+  double* dab = nullptr;  // 2 * steps * vecs
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  DenseWs dws;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double last_ms = 0;
+  int last_launches = 0;
+  std::string err;
+  bool dead = false;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+constexpr double U_ROUND = 1.1102230246251565e-16;
+
+chase_ph_status finish(chase_ph_t h, const Err& e) {
+  if (e) {
+    if (h) {
+      h->err = e.msg;
+      if (e.st == CHASE_PH_ERR_HIP) h->dead = true;
+    }
+    return e.st;
+  }
+  return CHASE_PH_OK;
+}
+
+template <typename T>
+Err dalloc(chase_ph_t h, T** p, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(CHASE_PH_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return ok();
+}
+
+Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alpha, const c128* A, int64_t lda,
+         const c128* B, int64_t ldb, c128 beta, c128* C, int64_t ldc, int64_t kneg = -1, bool split = true) {
+  ZgemmArgs g{};
+  g.transA = ta; g.transB = tb;
+  g.M = M; g.N = N; g.K = K;
+  g.alpha = alpha; g.beta = beta;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.kneg = kneg < 0 ? K : kneg;
+  g.batch = 1;
+  return zgemm(g, split ? h->ws : nullptr, split ? h->ws_bytes : 0, h->st);
+}
+
+Err ensure_shadow(chase_ph_t h) {
+  if (h->A32) return ok();
+  h->ld32 = (h->m + 63) / 64 * 64;
+  CHASE_TRY(dalloc(h, &h->A32, (size_t)h->ld32 * h->m));
+  CHASE_TRY(dalloc(h, &h->B32, (size_t)h->ld32 * h->m));
+  CHASE_TRY(dalloc(h, &h->W32, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->F1_32, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->FT_32, (size_t)h->n * h->nevex));
+  return make_shadow(h->A, h->B, h->ld, h->p.a_conj, h->A32, h->B32, h->ld32, h->m, h->st);
+}
+
+// Y = alpha H X + beta P + gamma Q on k columns
+Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ldy, double alpha = 1,
+            const c128* P = nullptr, int64_t ldp = 0, double beta = 0, const c128* Q = nullptr, int64_t ldq = 0,
+            double gamma = 0) {
+  ApplyHArgs<double> a{};
+  a.A = h->A; a.B = h->B; a.lda = h->ld; a.a_conj = h->p.a_conj; a.m = h->m; a.k = k;
+  a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
+  a.alpha = alpha; a.beta = beta; a.gamma = gamma;
+  return launch_apply_h_f64(a, h->st);
+}
+
+Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy, float alpha = 1,
+            const c64* P = nullptr, int64_t ldp = 0, float beta = 0, const c64* Q = nullptr, int64_t ldq = 0,
+            float gamma = 0) {
+  ApplyHArgs<float> a{};
+  a.A = h->A32; a.B = h->B32; a.lda = h->ld32; a.a_conj = 0; a.m = h->m; a.k = k;
+  a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
+  a.alpha = alpha; a.beta = beta; a.gamma = gamma;
+  return launch_apply_h_f32(a, h->st);
+}
+
+// Scaled Chebyshev recurrence on H^2 (eq. 4.1, Zhou-Saad scaling); see
+// chase_ph_filter.  Buffers: W (user, ldw), F1 and FT (ld n).  W_s lives in
+// W for even s and in F1 for odd s; the second product of each degree
+// writes W_{s} in place over W_{s-2}.
+template <typename R, typename C>
+Err filter_impl(chase_ph_t h, int k, C* W, int64_t ldw, const std::vector<int>& d, double mu1, double mu_nevex,
+                double mu_n, C* F1, C* FT, int* launches, double* flops) {
+  const int64_t n = h->n;
+  const double c = 0.5 * (mu_n * mu_n + mu_nevex * mu_nevex);
+  const double e = 0.5 * (mu_n * mu_n - mu_nevex * mu_nevex);
+  const double sigma1 = e / (mu1 * mu1 - c);
+  double sigma = sigma1;
+  const int maxd = d[k - 1];
+  int j0 = 0;
+  auto app = [&](int kc, const C* X, int64_t ldx, C* Y, int64_t ldy, double al, const C* P, int64_t ldp, double be,
+                 const C* Q, int64_t ldq, double ga) -> Err {
+    ++*launches;
+    *flops += 8.0 * (double)n * (double)n * kc;
+    if constexpr (sizeof(R) == 4)
+      return apply32(h, kc, X, ldx, Y, ldy, (float)al, P, ldp, (float)be, Q, ldq, (float)ga);
+    else
+      return apply64(h, kc, X, ldx, Y, ldy, al, P, ldp, be, Q, ldq, ga);
+  };
+  for (int s = 1; s <= maxd; ++s) {
+    while (j0 < k && d[j0] < s) ++j0;
+    const int kc = k - j0;
+    C* cur = ((s - 1) % 2 == 0) ? W + (int64_t)j0 * ldw : F1 + (int64_t)j0 * n;
+    const int64_t ldc = ((s - 1) % 2 == 0) ? ldw : n;
+    C* prev = ((s - 1) % 2 == 0) ? F1 + (int64_t)j0 * n : W + (int64_t)j0 * ldw;
+    const int64_t ldpv = ((s - 1) % 2 == 0) ? n : ldw;
+    C* T = FT + (int64_t)j0 * n;
+    CHASE_TRY(app(kc, cur, ldc, T, n, 1.0, nullptr, 0, 0.0, nullptr, 0, 0.0));
+    if (s == 1) {
+      CHASE_TRY(app(kc, T, n, prev, ldpv, sigma1 / e, cur, ldc, -sigma1 * c / e, nullptr, 0, 0.0));
+    } else {
+      const double sn = 1.0 / (2.0 / sigma1 - sigma);
+      CHASE_TRY(app(kc, T, n, prev, ldpv, 2.0 * sn / e, cur, ldc, -2.0 * sn * c / e, prev, ldpv, -sigma * sn));
+      sigma = sn;
+    }
+  }
+  // odd degrees ended in F1: copy those column groups back into W
+  int j = 0;
+  while (j < k) {
+    int j2 = j;
+    while (j2 < k && d[j2] == d[j]) ++j2;
+    if (d[j] % 2 == 1) {
+      CHASE_HIP(hipMemcpy2DAsync(W + (int64_t)j * ldw, ldw * sizeof(C), F1 + (int64_t)j * n, n * sizeof(C),
+                                 n * sizeof(C), j2 - j, hipMemcpyDeviceToDevice, h->st));
+    }
+    j = j2;
+  }
+  return ok();
+}
+
+Err check_filter_args(chase_ph_t h, int k, int64_t ldw, const int32_t* degs, double mu1, double mu_nevex, double mu_n,
+                      std::vector<int>& d) {
+  if (k < 0 || k > h->nevex) return fail(CHASE_PH_ERR_ARG, "filter: k out of range [0, nevex]");
+  if (ldw < h->n) return fail(CHASE_PH_ERR_ARG, "filter: ldw < n");
+  if (!(mu1 > 0) || !(mu_nevex > mu1) || !(mu_n > mu_nevex))
+    return fail(CHASE_PH_ERR_ARG, "filter: need 0 < mu1 < mu_nevex < mu_n");
+  d.assign(k, h->p.deg);
+  if (degs)
+    for (int i = 0; i < k; ++i) d[i] = degs[i];
+  for (int i = 0; i < k; ++i) {
+    if (d[i] < 1) return fail(CHASE_PH_ERR_ARG, "filter: degree < 1");
+    if (i && d[i] < d[i - 1]) return fail(CHASE_PH_ERR_ARG, "filter: degrees must be non-decreasing");
+  }
+  return ok();
+}
+
+Err filter_any(chase_ph_t h, int k, void* dW, int64_t ldw, const std::vector<int>& d, double mu1, double mu_nevex,
+               double mu_n, int prec, double* flops) {
+  if (k == 0) return ok();
+  int launches = 0;
+  double fl = 0;
+  CHASE_HIP(hipEventRecord(h->e0, h->st));
+  if (prec == CHASE_PH_FP32) {
+    CHASE_TRY(ensure_shadow(h));
+    CHASE_TRY((filter_impl<float, c64>(h, k, (c64*)dW, ldw, d, mu1, mu_nevex, mu_n, h->F1_32, h->FT_32, &launches, &fl)));
+  } else {
+    CHASE_TRY((filter_impl<double, c128>(h, k, (c128*)dW, ldw, d, mu1, mu_nevex, mu_n, h->F1, h->FT, &launches, &fl)));
+  }
+  CHASE_HIP(hipEventRecord(h->e1, h->st));
+  CHASE_HIP(hipEventSynchronize(h->e1));
+  float ms = 0;
+  CHASE_HIP(hipEventElapsedTime(&ms, h->e0, h->e1));
+  h->last_ms = ms;
+  h->last_launches = launches;
+  if (flops) *flops = fl;
+  return ok();
+}
+
+// One Cholesky-QR pass: Xout = Xin L^{-H} with L L^H = Xin^H Xin + shift I.
+Err cholqr_pass(chase_ph_t h, int k, int kp, const c128* Xin, int64_t ldin, c128* Xout, int64_t ldout, c128* Lbuf,
+                double shift, bool* failed) {
+  CHASE_TRY(fill_padded(Lbuf, kp, k, 0.0, 1.0, true, h->st));
+  CHASE_TRY(gemm(h, 1, 0, k, k, h->n, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp));
+  if (shift != 0.0) CHASE_TRY(add_diag(Lbuf, kp, k, shift, h->st));
+  CHASE_TRY(cholesky_lower(Lbuf, kp, h->dws, h->st, failed));
+  if (*failed) return ok();
+  CHASE_TRY(tri_inverse_lower(Lbuf, h->Li, kp, h->dws, h->st));
+  return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout);
+}
+
+Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift) {
+  if (used_shift) *used_shift = 0;
+  if (k == 0) return ok();
+  const int kp = pad64(k);
+  const int64_t n = h->n;
+  bool failed = false;
+  CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, 0.0, &failed));
+  int nf = 2;
+  if (!failed) {
+    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
+    if (failed) return fail(CHASE_PH_ERR_QR, "CholeskyQR2: second factorisation failed");
+  } else {
+    // shifted CholeskyQR3: s = 11 (n k + k (k + 1)) u ||X||_F^2
+    CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
+    CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, X, ldx, X, ldx, {0, 0}, h->G, kp));
+    CHASE_TRY(trace(h->G, kp, k, h->dws.dscalar, h->st));
+    double fro2 = 0;
+    CHASE_HIP(hipMemcpyAsync(&fro2, h->dws.dscalar, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    CHASE_HIP(hipStreamSynchronize(h->st));
+    const double shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * U_ROUND * fro2;
+    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed));
+    if (failed) return fail(CHASE_PH_ERR_QR, "shifted CholeskyQR: factorisation failed");
+    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
+    if (failed) return fail(CHASE_PH_ERR_QR, "shifted CholeskyQR3: second factorisation failed");
+    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L3, 0.0, &failed));
+    if (failed) return fail(CHASE_PH_ERR_QR, "shifted CholeskyQR3: third factorisation failed");
+    CHASE_HIP(hipMemcpy2DAsync(X, ldx * sizeof(c128), h->Xt, n * sizeof(c128), n * sizeof(c128), k,
+                               hipMemcpyDeviceToDevice, h->st));
+    nf = 3;
+    if (used_shift) *used_shift = 1;
+  }
+  if (R) {
+    // R = L_nf^H ... L_1^H
+    if (nf == 2) {
+      CHASE_TRY(gemm(h, 1, 1, k, k, k, {1, 0}, h->L2, kp, h->L1, kp, {0, 0}, R, ldr, -1, false));
+    } else {
+      CHASE_TRY(gemm(h, 1, 1, k, k, k, {1, 0}, h->L3, kp, h->L2, kp, {0, 0}, h->Tk, kp, -1, false));
+      CHASE_TRY(gemm(h, 0, 1, k, k, k, {1, 0}, h->Tk, kp, h->L1, kp, {0, 0}, R, ldr, -1, false));
+    }
+  }
+  return ok();
+}
+
+// Alg. 2 (inverse Rayleigh quotient); see chase_ph_oblique_rr.
+Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128* Zpos, int64_t ldz, c128* T,
+            int64_t ldt) {
+  const int kp = pad64(k);
+  const int64_t m = h->m, n = h->n;
+  CHASE_TRY(apply64(h, k, Q, ldq, T, ldt));                                   // T = H Q
+  CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m));  // M = Q^H S T
+  bool failed = false;
+  CHASE_TRY(cholesky_lower(h->G, kp, h->dws, h->st, &failed));                // L L^H = M
+  if (failed) return fail(CHASE_PH_ERR_NOT_DEFINITE, "Cholesky of Q^H S H Q failed (SH not positive definite on range(Q))");
+  CHASE_TRY(tri_inverse_lower(h->G, h->Li, kp, h->dws, h->st));
+  CHASE_TRY(fill_padded(h->Nb, kp, k, 1.0, 0.0, true, h->st));              // N = I - 2 Q2^H Q2
+  CHASE_TRY(gemm(h, 1, 0, k, k, m, {-2, 0}, Q + m, ldq, Q + m, ldq, {1, 0}, h->Nb, kp));
+  CHASE_TRY(gemm(h, 0, 1, kp, kp, kp, {1, 0}, h->Nb, kp, h->Li, kp, {0, 0}, h->Tk, kp, -1, false));  // N L^{-H}
+  CHASE_TRY(gemm(h, 0, 0, kp, kp, kp, {1, 0}, h->Li, kp, h->Tk, kp, {0, 0}, h->G, kp, -1, false));   // L^{-1} N L^{-H}
+  int sweeps = 0;
+  CHASE_TRY(jacobi_eigh(h->G, h->Ev, kp, h->dws, h->st, 40, &sweeps));
+  int npos = 0, nneg = 0;
+  CHASE_TRY(select_positive(h->G, h->Ev, k, kp, h->Ys, h->dlam, h->dws, h->st, &npos, &nneg));
+  if (npos != k / 2 || nneg != k / 2)
+    return fail(CHASE_PH_ERR_SINGULAR_QSQ, "Q^H S Q numerically singular: " + std::to_string(npos) + " positive / " +
+                                               std::to_string(nneg) + " negative resolved Ritz values for k = " +
+                                               std::to_string(k));
+  CHASE_TRY(gemm(h, 1, 0, k, k / 2, k, {1, 0}, h->Li, kp, h->Ys, kp, {0, 0}, Zpos, ldz, -1, false));  // Z = L^{-H} Y
+  if (ritz) {
+    CHASE_HIP(hipMemcpyAsync(ritz, h->dlam, sizeof(double) * (k / 2), hipMemcpyDeviceToHost, h->st));
+    CHASE_HIP(hipStreamSynchronize(h->st));
+  }
+  return ok();
+}
+
+Err resid_impl(chase_ph_t h, int k, int kk, const c128* Q, int64_t ldq, const c128* T, int64_t ldt, const c128* Zpos,
+               int64_t ldz, const double* ritz_host, c128* V, int64_t ldv, double* resid) {
+  if (kk == 0) return ok();
+  const int64_t n = h->n;
+  CHASE_TRY(gemm(h, 0, 0, n, kk, k, {1, 0}, Q, ldq, Zpos, ldz, {0, 0}, V, ldv, -1, false));
+  CHASE_TRY(gemm(h, 0, 0, n, kk, k, {1, 0}, T, ldt, Zpos, ldz, {0, 0}, h->TZ, n, -1, false));
+  if (ritz_host)
+    CHASE_HIP(hipMemcpyAsync(h->dlam, ritz_host, sizeof(double) * kk, hipMemcpyHostToDevice, h->st));
+  CHASE_TRY(residual_norms(V, ldv, h->TZ, n, h->dlam, n, kk, h->dres, h->st));
+  CHASE_HIP(hipMemcpyAsync(resid, h->dres, sizeof(double) * kk, hipMemcpyDeviceToHost, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  return ok();
+}
+
+// Symmetric tridiagonal eigenproblem of Lanczos (tiny): cyclic Jacobi on
+// the dense matrix; returns eigenvalues and the first and last rows of the
+// eigenvector matrix.
+void tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, std::vector<double>& th,
+                 std::vector<double>& first, std::vector<double>& last) {
+  const int s = (int)a.size();
+  std::vector<double> M(s * s, 0.0), V(s * s, 0.0);
+  for (int i = 0; i < s; ++i) {
+    M[i * s + i] = a[i];
+    V[i * s + i] = 1.0;
+    if (i + 1 < s) M[i * s + i + 1] = M[(i + 1) * s + i] = b[i];
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        tot += M[i * s + j] * M[i * s + j];
+        if (i != j) off += M[i * s + j] * M[i * s + j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < s; ++p)
+      for (int q = p + 1; q < s; ++q) {
+        const double apq = M[p * s + q];
+        if (apq == 0.0) continue;
+        const double tau = (M[q * s + q] - M[p * s + p]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        for (int r = 0; r < s; ++r) {  // columns
+          const double mp = M[r * s + p], mq = M[r * s + q];
+          M[r * s + p] = c * mp - sn * mq;
+          M[r * s + q] = sn * mp + c * mq;
+        }
+        for (int r = 0; r < s; ++r) {  // rows
+          const double mp = M[p * s + r], mq = M[q * s + r];
+          M[p * s + r] = c * mp - sn * mq;
+          M[q * s + r] = sn * mp + c * mq;
+        }
+        for (int r = 0; r < s; ++r) {
+          const double vp = V[r * s + p], vq = V[r * s + q];
+          V[r * s + p] = c * vp - sn * vq;
+          V[r * s + q] = sn * vp + c * vq;
+        }
+      }
+  }
+  th.resize(s);
+  first.resize(s);
+  last.resize(s);
+  for (int i = 0; i < s; ++i) {
+    th[i] = M[i * s + i];
+    first[i] = V[0 * s + i];
+    last[i] = V[(s - 1) * s + i];
+  }
+}
+
+// Spectral estimates mu_1, mu_nevex, mu_n (Section 4.1) from Lanczos runs in
+// the S H inner product, one product with H per step; start vectors are the
+// gamma-scaled caller draws.
+Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, double* mu_nevex, double* mu_n) {
+  const int nv = h->p.lanczos_vecs, steps = h->p.lanczos_steps;
+  const int64_t n = h->n, m = h->m;
+  double* alpha = h->dab;
+  double* bsq = h->dab + (size_t)steps * nv;
+  double* b0 = h->dab + (size_t)2 * steps * nv;
+  CHASE_TRY(scale_lower_half(dLz, ldlz, h->lv, n, m, nv, h->p.gamma, h->st));
+  CHASE_HIP(hipMemsetAsync(h->lvp, 0, sizeof(c128) * n * nv, h->st));
+  CHASE_TRY(apply64(h, nv, h->lv, n, h->lw, n));
+  CHASE_TRY(s_dots(h->lv, n, h->lw, n, m, nv, b0, h->st));
+  CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lv, h->lw, n, n, nv, b0, false, h->st));
+  for (int j = 0; j < steps; ++j) {
+    CHASE_TRY(s_dots(h->lw, n, h->lw, n, m, nv, alpha + (size_t)j * nv, h->st));
+    CHASE_TRY(lanczos_residual(h->lw, h->lv, h->lvp, h->lr, n, n, nv, alpha + (size_t)j * nv,
+                               j ? bsq + (size_t)(j - 1) * nv : nullptr, h->st));
+    CHASE_TRY(apply64(h, nv, h->lr, n, h->lz, n));
+    CHASE_TRY(s_dots(h->lr, n, h->lz, n, m, nv, bsq + (size_t)j * nv, h->st));
+    if (j + 1 < steps) CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lr, h->lz, n, n, nv, bsq + (size_t)j * nv, true, h->st));
+  }
+  std::vector<double> ha((size_t)steps * nv), hb((size_t)steps * nv);
+  CHASE_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * ha.size(), hipMemcpyDeviceToHost, h->st));
+  CHASE_HIP(hipMemcpyAsync(hb.data(), bsq, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  double m1 = 1e300, mn = 0;
+  std::vector<std::pair<double, double>> pos;  // (theta, weight)
+  for (int r = 0; r < nv; ++r) {
+    std::vector<double> a(steps), b(steps);
+    for (int j = 0; j < steps; ++j) {
+      a[j] = ha[(size_t)j * nv + r];
+      b[j] = std::sqrt(std::max(hb[(size_t)j * nv + r], 0.0));
+    }
+    std::vector<double> th, f, l;
+    tridiag_eig(a, b, th, f, l);
+    int imax = 0;
+    for (int i = 0; i < steps; ++i) {
+      m1 = std::min(m1, std::fabs(th[i]));
+      if (std::fabs(th[i]) > std::fabs(th[imax])) imax = i;
+    }
+    mn = std::max(mn, std::fabs(th[imax]) + std::fabs(b[steps - 1] * l[imax]));
+    for (int i = 0; i < steps; ++i)
+      if (th[i] > 0) pos.push_back({th[i], f[i] * f[i] / nv});
+  }
+  std::sort(pos.begin(), pos.end());
+  double tot = 0;
+  for (auto& pw : pos) tot += pw.second;
+  double cum = 0, mnev = pos.empty() ? 0.5 * (m1 + mn) : pos.back().first;
+  const double target = (double)h->nevex / (double)h->m;
+  for (auto& pw : pos) {
+    cum += pw.second / tot;
+    if (cum >= target) {
+      mnev = pw.first;
+      break;
+    }
+  }
+  if (mnev <= m1) {
+    mnev = 0.5 * (m1 + mn);
+    for (auto& pw : pos)
+      if (pw.first > m1 * (1.0 + 1e-8)) {
+        mnev = pw.first;
+        break;
+      }
+  }
+  mnev = std::min(mnev, 0.99 * mn);
+  *mu1 = m1;
+  *mu_nevex = mnev;
+  *mu_n = mn;
+  return ok();
+}
+
+struct Timer {
+  chase_ph_t h;
+  explicit Timer(chase_ph_t hh) : h(hh) {}
+  Err start() {
+    CHASE_HIP(hipEventRecord(h->e0, h->st));
+    return ok();
+  }
+  Err stop(double* acc) {
+    CHASE_HIP(hipEventRecord(h->e1, h->st));
+    CHASE_HIP(hipEventSynchronize(h->e1));
+    float ms = 0;
+    CHASE_HIP(hipEventElapsedTime(&ms, h->e0, h->e1));
+    *acc += ms * 1e-3;
+    return ok();
+  }
+};
+
+Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64_t ldlz, double* evals, c128* V,
+               int64_t ldv, double* resid_out, chase_ph_info* info, bool* converged) {
+  const chase_ph_params& p = h->p;
+  const int64_t n = h->n, m = h->m;
+  const int nev = p.nev, nevex = h->nevex;
+  chase_ph_info inf{};
+  if (info) {
+    inf.resid_history = info->resid_history;
+    inf.resid_history_len = info->resid_history_len;
+  }
+  inf.switch_iter = -1;
+  Timer tm(h);
+  hipEvent_t t0, t1;
+  CHASE_HIP(hipEventCreate(&t0));
+  CHASE_HIP(hipEventCreate(&t1));
+  CHASE_HIP(hipEventRecord(t0, h->st));
+
+  CHASE_TRY(scale_lower_half(W0, ldw0, h->Wk, n, m, nevex, p.gamma, h->st));  // Alg. 3, line 1 / Section 4.6
+  double mu1, mu_nevex, mu_n;
+  CHASE_TRY(tm.start());
+  CHASE_TRY(lanczos_impl(h, Lz, ldlz, &mu1, &mu_nevex, &mu_n));
+  CHASE_TRY(tm.stop(&inf.t_lanczos));
+  inf.mu1 = mu1;
+  inf.mu_nevex0 = mu_nevex;
+  inf.mu_n = mu_n;
+  const bool verbose = std::getenv("CHASE_PH_VERBOSE") != nullptr;
+  if (verbose) std::fprintf(stderr, "[chase_ph] lanczos mu1=%.6g mu_nevex=%.6g mu_n=%.6g\n", mu1, mu_nevex, mu_n);
+  if (!std::isfinite(mu1) || !std::isfinite(mu_n) || !std::isfinite(mu_nevex) || !(mu1 > 0) || !(mu_nevex > mu1) ||
+      !(mu_n > mu_nevex))
+    return fail(CHASE_PH_ERR_NOT_DEFINITE, "Lanczos spectral estimates invalid (SH not positive definite?)");
+  const double switch_tol = p.switch_tol > 0 ? p.switch_tol : 1e-5 * mu_n;
+  bool fp64_filter = p.precision != CHASE_PH_MIXED;
+  if (p.precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
+
+  int locked = 0;
+  std::vector<double> lam_locked, res_locked;
+  std::vector<int> degs(nevex, p.deg);
+  std::vector<double> ritz(nevex), res(nevex);
+  int hist_pos = 0;
+  *converged = false;
+  for (int it = 0; it < p.max_iter; ++it) {
+    const int kw = nevex - locked;
+    // filter the positive half (Alg. 3; Thm 4.2)
+    double fl = 0;
+    CHASE_TRY(tm.start());
+    if (fp64_filter) {
+      CHASE_TRY(filter_any(h, kw, h->Wk, n, degs, mu1, mu_nevex, mu_n, CHASE_PH_FP64, &fl));
+    } else {
+      CHASE_TRY(convert_to_c64(h->Wk, n, h->W32, n, n, kw, h->st));
+      CHASE_TRY(filter_any(h, kw, h->W32, n, degs, mu1, mu_nevex, mu_n, CHASE_PH_FP32, &fl));
+      CHASE_TRY(convert_to_c128(h->W32, n, h->Wk, n, n, kw, h->st));
+      inf.filter_flops_fp32 += fl;
+    }
+    CHASE_TRY(tm.stop(&inf.t_filter));
+    inf.filter_flops += fl;
+    // assemble [S Y+, S K conj(Y+), W+, K conj(W+)] and orthonormalise (eq. 4.5)
+    const int kx = 2 * nevex;
+    CHASE_TRY(tm.start());
+    CHASE_TRY(build_search_block(h->Ylock, n, locked, h->Wk, n, kw, h->Xs, n, m, h->st));
+    int used = 0;
+    CHASE_TRY(qr_impl(h, kx, h->Xs, n, nullptr, 0, &used));
+    inf.shifted_qr_used += used;
+    CHASE_TRY(tm.stop(&inf.t_qr));
+    // oblique RR on the non-locked part (Alg. 2)
+    const c128* Q = h->Xs + (int64_t)2 * locked * n;
+    const int kq = 2 * kw;
+    CHASE_TRY(tm.start());
+    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n));
+    CHASE_TRY(tm.stop(&inf.t_rr));
+    // half back-transform and residuals (Section 4.5)
+    CHASE_TRY(tm.start());
+    CHASE_TRY(resid_impl(h, kq, kw, Q, n, h->Tq, n, h->Zp, h->kmax, nullptr, h->Vt, n, res.data()));
+    CHASE_TRY(tm.stop(&inf.t_resid));
+    inf.rr_flops += 8.0 * n * n * kq + 12.0 * n * (double)kq * kq + 16.0 * n * (double)kx * kx;
+    if (inf.resid_history && hist_pos + kw <= inf.resid_history_len) {
+      std::copy(res.begin(), res.begin() + kw, inf.resid_history + hist_pos);
+      hist_pos += kw;
+    }
+    // locking: contiguous prefix of the wanted pairs with residual <= tol
+    int nlock = 0;
+    while (nlock < nev - locked && res[nlock] <= p.tol) ++nlock;
+    if (nlock > 0)
+      CHASE_HIP(hipMemcpy2DAsync(h->Ylock + (int64_t)locked * n, n * sizeof(c128), h->Vt, n * sizeof(c128),
+                                 n * sizeof(c128), nlock, hipMemcpyDeviceToDevice, h->st));
+    for (int i = 0; i < nlock; ++i) {
+      lam_locked.push_back(ritz[i]);
+      res_locked.push_back(res[i]);
+    }
+    if (verbose) {
+      std::fprintf(stderr, "[chase_ph] it=%d locked=%d kw=%d prec=%s nlock=%d ritz[0]=%.12g res[0]=%.3e res[kw-1]=%.3e mu_nevex=%.6g shifted=%d\n",
+                   it, locked, kw, fp64_filter ? "fp64" : "fp32", nlock, ritz[0], res[0], res[kw - 1], ritz[kw - 1], used);
+    }
+    const int wanted_left = nev - locked;
+    locked += nlock;
+    mu_nevex = ritz[kw - 1];  // largest non-converged positive Ritz value (Section 4.1)
+    inf.iterations = it + 1;
+    if (locked >= nev) {
+      *converged = true;
+      break;
+    }
+    const int kn = kw - nlock;
+    // next search block W+ <- unconverged Ritz vectors, ordered by degree
+    std::vector<int> nd(kn, p.deg);
+    std::vector<int> perm(kn);
+    std::iota(perm.begin(), perm.end(), 0);
+    if (p.opt_deg) {
+      const double c = 0.5 * (mu_n * mu_n + mu_nevex * mu_nevex);
+      const double e = 0.5 * (mu_n * mu_n - mu_nevex * mu_nevex);
+      for (int j = 0; j < kn; ++j) {
+        const double l = ritz[nlock + j], r = res[nlock + j];
+        const double t = std::fabs((l * l - c) / e);
+        int d;
+        if (t <= 1.0 + 1e-12 || r <= p.tol) {
+          d = r > p.tol ? p.deg_max : p.deg_min;
+        } else {
+          const double rho = t + std::sqrt(t * t - 1.0);
+          d = (int)std::ceil(std::log(r / p.tol) / std::log(rho));
+          d = std::min(std::max(d, p.deg_min), p.deg_max);
+        }
+        nd[j] = d;
+      }
+      std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return nd[a] < nd[b]; });
+    }
+    std::vector<int> src(kn);
+    degs.assign(kn, p.deg);
+    for (int j = 0; j < kn; ++j) {
+      src[j] = nlock + perm[j];
+      degs[j] = nd[perm[j]];
+    }
+    CHASE_HIP(hipMemcpyAsync(h->dperm, src.data(), sizeof(int) * kn, hipMemcpyHostToDevice, h->st));
+    CHASE_TRY(gather_columns(h->Vt, n, h->Wk, n, n, kn, h->dperm, h->st));
+    // mixed precision: move the filter to FP64 once the wanted residuals
+    // are within reach of the c64 rounding floor
+    if (!fp64_filter) {
+      const int nw = std::max(1, wanted_left - nlock);
+      std::vector<double> wr(res.begin() + nlock, res.begin() + nlock + std::min(nw, kn));
+      std::nth_element(wr.begin(), wr.begin() + wr.size() / 2, wr.end());
+      if (wr[wr.size() / 2] <= switch_tol) {
+        fp64_filter = true;
+        inf.switch_iter = it + 1;
+      }
+    }
+  }
+  CHASE_HIP(hipEventRecord(t1, h->st));
+  CHASE_HIP(hipEventSynchronize(t1));
+  float ms = 0;
+  CHASE_HIP(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  inf.t_total = ms * 1e-3;
+  inf.locked = locked;
+  const int nout = std::min(locked, nev);
+  for (int i = 0; i < nout; ++i) {
+    evals[i] = lam_locked[i];
+    if (resid_out) resid_out[i] = res_locked[i];
+  }
+  if (nout > 0)
+    CHASE_HIP(hipMemcpy2DAsync(V, ldv * sizeof(c128), h->Ylock, n * sizeof(c128), n * sizeof(c128), nout,
+                               hipMemcpyDeviceToDevice, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  if (info) *info = inf;
+  return ok();
+}
+
+Err backward_impl(chase_ph_t h, int nev, const c128* V, int64_t ldv, const double* g, c128* GA, c128* GB, int64_t ldg) {
+  const int64_t m = h->m;
+  c128 *P = nullptr, *P2 = nullptr, *Pg = nullptr;
+  double* dg = nullptr;
+  const size_t sz = (size_t)m * 2 * nev;
+  CHASE_HIP(hipMalloc(&P, sz * sizeof(c128)));
+  CHASE_HIP(hipMalloc(&P2, sz * sizeof(c128)));
+  CHASE_HIP(hipMalloc(&Pg, sz * sizeof(c128)));
+  CHASE_HIP(hipMalloc(&dg, nev * sizeof(double)));
+  Err e = ok();
+  do {
+    if (hipMemcpyAsync(dg, g, nev * sizeof(double), hipMemcpyHostToDevice, h->st) != hipSuccess) {
+      e = fail(CHASE_PH_ERR_HIP, "backward: upload g");
+      break;
+    }
+    e = adjoint_operands(V, ldv, m, nev, dg, P, P2, Pg, m, h->st);
+    if (e) break;
+    e = gemm(h, 0, 1, m, m, 2 * nev, {1, 0}, Pg, m, P, m, {0, 0}, GA, ldg, -1, false);   // G_A = Pg P^H
+    if (e) break;
+    e = gemm(h, 0, 1, m, m, 2 * nev, {1, 0}, Pg, m, P2, m, {0, 0}, GB, ldg, -1, false);  // G_B = Pg P2^H
+    if (e) break;
+    if (hipStreamSynchronize(h->st) != hipSuccess) e = fail(CHASE_PH_ERR_HIP, "backward: sync");
+  } while (0);
+  (void)hipFree(P);
+  (void)hipFree(P2);
+  (void)hipFree(Pg);
+  (void)hipFree(dg);
+  return e;
+}
+
+Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_t ld, void* stream, chase_ph_t h) {
+  h->p = *p;
+  h->A = (const c128*)dA;
+  h->B = (const c128*)dB;
+  h->ld = ld;
+  h->st = (hipStream_t)stream;
+  h->m = p->m;
+  h->n = 2 * p->m;
+  h->nevex = p->nev + p->nex;
+  h->kmax = 2 * h->nevex;
+  h->kp = pad64(h->kmax);
+  const int64_t n = h->n;
+  const size_t kp2 = (size_t)h->kp * h->kp;
+  CHASE_HIP(hipEventCreate(&h->e0));
+  CHASE_HIP(hipEventCreate(&h->e1));
+  CHASE_TRY(dalloc(h, &h->F1, (size_t)n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->FT, (size_t)n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->Xs, (size_t)n * h->kmax));
+  CHASE_TRY(dalloc(h, &h->Xt, (size_t)n * h->kmax));
+  CHASE_TRY(dalloc(h, &h->Tq, (size_t)n * h->kmax));
+  CHASE_TRY(dalloc(h, &h->Vt, (size_t)n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->TZ, (size_t)n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->G, kp2));
+  CHASE_TRY(dalloc(h, &h->L1, kp2));
+  CHASE_TRY(dalloc(h, &h->L2, kp2));
+  CHASE_TRY(dalloc(h, &h->L3, kp2));
+  CHASE_TRY(dalloc(h, &h->Li, kp2));
+  CHASE_TRY(dalloc(h, &h->Nb, kp2));
+  CHASE_TRY(dalloc(h, &h->Tk, kp2));
+  CHASE_TRY(dalloc(h, &h->Ev, kp2));
+  CHASE_TRY(dalloc(h, &h->Ys, kp2));
+  CHASE_TRY(dalloc(h, &h->Zp, (size_t)h->kmax * h->nevex));
+  CHASE_TRY(dalloc(h, &h->Ylock, (size_t)n * std::max(1, p->nev)));
+  CHASE_TRY(dalloc(h, &h->Wk, (size_t)n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->dlam, (size_t)h->kmax));
+  CHASE_TRY(dalloc(h, &h->dres, (size_t)h->kmax));
+  CHASE_TRY(dalloc(h, &h->dperm, (size_t)h->kmax));
+  const int nv = std::max(1, p->lanczos_vecs);
+  CHASE_TRY(dalloc(h, &h->lv, (size_t)n * nv));
+  CHASE_TRY(dalloc(h, &h->lvp, (size_t)n * nv));
+  CHASE_TRY(dalloc(h, &h->lw, (size_t)n * nv));
+  CHASE_TRY(dalloc(h, &h->lr, (size_t)n * nv));
+  CHASE_TRY(dalloc(h, &h->lz, (size_t)n * nv));
+  CHASE_TRY(dalloc(h, &h->dab, (size_t)(2 * std::max(1, p->lanczos_steps) + 1) * nv));
+  CHASE_TRY(dalloc(h, &h->dws.small, 64 * 64));
+  CHASE_TRY(dalloc(h, &h->dws.panel, (size_t)h->kp * 64));
+  CHASE_TRY(dalloc(h, &h->dws.tmp, (size_t)h->kp * 64));
+  CHASE_TRY(dalloc(h, &h->dws.U, (size_t)h->kp * 64));
+  CHASE_TRY(dalloc(h, &h->dws.flag, 4));
+  CHASE_TRY(dalloc(h, &h->dws.dscalar, 4));
+  h->ws_bytes = std::min<size_t>((size_t)256 << 20, std::max<size_t>((size_t)16 << 20, kp2 * sizeof(c128) * 8));
+  CHASE_TRY(dalloc(h, (char**)&h->ws, h->ws_bytes));
+  if (p->precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+void chase_ph_default_params(chase_ph_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->deg = 20;
+  p->deg_min = 8;
+  p->deg_max = 20;
+  p->opt_deg = 0;
+  p->max_iter = 25;
+  p->tol = 1e-10;
+  p->precision = CHASE_PH_FP64;
+  p->switch_tol = 0.0;
+  p->gamma = 1e-3;
+  p->lanczos_steps = 26;
+  p->lanczos_vecs = 4;
+  p->a_conj = 0;
+}
+
+chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const void* dB, int64_t ld, void* hip_stream,
+                                chase_ph_t* out) {
+  if (!out) return CHASE_PH_ERR_ARG;
+  *out = nullptr;
+  if (!p || !dA || !dB || p->m <= 0 || ld < p->m || p->nev <= 0 || p->nex < 0 || p->nev + p->nex > p->m ||
+      p->deg < 1 || p->max_iter < 1 || !(p->tol > 0) || p->lanczos_steps < 2 || p->lanczos_steps % 2 != 0 ||
+      p->lanczos_vecs < 1 || (p->precision != CHASE_PH_FP64 && p->precision != CHASE_PH_MIXED) ||
+      (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)))
+    return CHASE_PH_ERR_ARG;
+  chase_ph_t h = new (std::nothrow) chase_ph_s;
+  if (!h) return CHASE_PH_ERR_ALLOC;
+  Err e = create_impl(p, dA, dB, ld, hip_stream, h);
+  if (e) {
+    chase_ph_destroy(h);
+    return e.st;
+  }
+  *out = h;
+  return CHASE_PH_OK;
+}
+
+chase_ph_status chase_ph_destroy(chase_ph_t h) {
+  if (!h) return CHASE_PH_OK;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  else (void)hipDeviceSynchronize();
+  for (void* q : h->allocs) (void)hipFree(q);
+  if (h->e0) (void)hipEventDestroy(h->e0);
+  if (h->e1) (void)hipEventDestroy(h->e1);
+  delete h;
+  return CHASE_PH_OK;
+}
+
+const char* chase_ph_last_error(chase_ph_t h) { return h ? h->err.c_str() : "null handle"; }
+
+#define CHECK_HANDLE(h)                                   \
+  do {                                                    \
+    if (!(h)) return CHASE_PH_ERR_ARG;                    \
+    if ((h)->dead) {                                      \
+      (h)->err = "handle unusable after a HIP error";     \
+      return CHASE_PH_ERR_HIP;                            \
+    }                                                     \
+  } while (0)
+
+chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_t ldx, void* dY, int64_t ldy,
+                                 int32_t prec) {
+  CHECK_HANDLE(h);
+  if (k < 0 || (k > 0 && (!dX || !dY)) || ldx < h->n || ldy < h->n ||
+      (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32))
+    return finish(h, fail(CHASE_PH_ERR_ARG, "apply_h: bad arguments"));
+  if (k == 0) return CHASE_PH_OK;
+  Err e = ok();
+  if (hipEventRecord(h->e0, h->st) != hipSuccess) return finish(h, fail(CHASE_PH_ERR_HIP, "event record"));
+  if (prec == CHASE_PH_FP32) {
+    e = ensure_shadow(h);
+    if (!e) e = apply32(h, k, (const c64*)dX, ldx, (c64*)dY, ldy);
+  } else {
+    e = apply64(h, k, (const c128*)dX, ldx, (c128*)dY, ldy);
+  }
+  if (e) return finish(h, e);
+  float ms = 0;
+  if (hipEventRecord(h->e1, h->st) != hipSuccess || hipEventSynchronize(h->e1) != hipSuccess ||
+      hipEventElapsedTime(&ms, h->e0, h->e1) != hipSuccess)
+    return finish(h, fail(CHASE_PH_ERR_HIP, "apply_h: kernel failed"));
+  h->last_ms = ms;
+  h->last_launches = 1;
+  return CHASE_PH_OK;
+}
+
+chase_ph_status chase_ph_filter(chase_ph_t h, int32_t k, void* dW, int64_t ldw, const int32_t* degs, double mu1,
+                                double mu_nevex, double mu_n, int32_t prec) {
+  CHECK_HANDLE(h);
+  std::vector<int> d;
+  Err e = check_filter_args(h, k, ldw, degs, mu1, mu_nevex, mu_n, d);
+  if (!e && (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32)) e = fail(CHASE_PH_ERR_ARG, "filter: bad precision");
+  if (!e && k > 0 && !dW) e = fail(CHASE_PH_ERR_ARG, "filter: null W");
+  if (e) return finish(h, e);
+  return finish(h, filter_any(h, k, dW, ldw, d, mu1, mu_nevex, mu_n, prec, nullptr));
+}
+
+chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void* dR, int64_t ldr, int32_t* used_shift) {
+  CHECK_HANDLE(h);
+  if (k < 0 || k > h->kmax || (k > 0 && !dX) || ldx < h->n || (dR && ldr < k))
+    return finish(h, fail(CHASE_PH_ERR_ARG, "qr: bad arguments"));
+  int us = 0;
+  Err e = qr_impl(h, k, (c128*)dX, ldx, (c128*)dR, ldr, &us);
+  if (!e) {
+    if (hipStreamSynchronize(h->st) != hipSuccess) e = fail(CHASE_PH_ERR_HIP, "qr: sync");
+  }
+  if (used_shift) *used_shift = us;
+  return finish(h, e);
+}
+
+chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq, double* hRitz, void* dZpos,
+                                    int64_t ldz, void* dT, int64_t ldt) {
+  CHECK_HANDLE(h);
+  if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
+    return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr: bad arguments"));
+  return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt));
+}
+
+chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const void* dQ, int64_t ldq, const void* dT,
+                                   int64_t ldt, const void* dZpos, int64_t ldz, const double* hRitz, void* dV,
+                                   int64_t ldv, double* hResid) {
+  CHECK_HANDLE(h);
+  if (k <= 0 || k > h->kmax || kk < 0 || kk > k / 2 || kk > h->nevex || !dQ || !dT || !dZpos || !hRitz || !dV ||
+      !hResid || ldq < h->n || ldt < h->n || ldz < k || ldv < h->n)
+    return finish(h, fail(CHASE_PH_ERR_ARG, "residuals: bad arguments"));
+  return finish(h, resid_impl(h, k, kk, (const c128*)dQ, ldq, (const c128*)dT, ldt, (const c128*)dZpos, ldz, hRitz,
+                              (c128*)dV, ldv, hResid));
+}
+
+chase_ph_status chase_ph_solve(chase_ph_t h, const void* dW0, int64_t ldw0, const void* dLz, int64_t ldlz,
+                               double* hEvals, void* dV, int64_t ldv, double* hResid, chase_ph_info* info) {
+  CHECK_HANDLE(h);
+  if (!dW0 || !dLz || !hEvals || !dV || ldw0 < h->n || ldlz < h->n || ldv < h->n)
+    return finish(h, fail(CHASE_PH_ERR_ARG, "solve: bad arguments"));
+  bool conv = false;
+  Err e = solve_impl(h, (const c128*)dW0, ldw0, (const c128*)dLz, ldlz, hEvals, (c128*)dV, ldv, hResid, info, &conv);
+  if (e) return finish(h, e);
+  if (!conv) return finish(h, fail(CHASE_PH_ERR_NO_CONVERGENCE, "max_iter reached before nev pairs converged"));
+  return CHASE_PH_OK;
+}
+
+chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* dV, int64_t ldv, const double* hG,
+                                         void* dGA, void* dGB, int64_t ldg) {
+  CHECK_HANDLE(h);
+  if (nev <= 0 || !dV || !hG || !dGA || !dGB || ldv < h->n || ldg < h->m)
+    return finish(h, fail(CHASE_PH_ERR_ARG, "eigval_backward: bad arguments"));
+  return finish(h, backward_impl(h, nev, (const c128*)dV, ldv, hG, (c128*)dGA, (c128*)dGB, ldg));
+}
+
+chase_ph_status chase_ph_last_timing(chase_ph_t h, double* ms, int32_t* launches) {
+  if (!h) return CHASE_PH_ERR_ARG;
+  if (ms) *ms = h->last_ms;
+  if (launches) *launches = h->last_launches;
+  return CHASE_PH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal definitions shared by the HIP translation units of libchase_ph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/chase_ph.h"
+
+namespace chase {
+
+struct c64 {
+  float re, im;
+};
+struct c128 {
+  double re, im;
+};
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct Cplx;
+template <>
+struct Cplx<float> {
+  using T = c64;
+};
+template <>
+struct Cplx<double> {
+  using T = c128;
+};
+
+// Status with message, returned by internal helpers.
+struct Err {
+  chase_ph_status st = CHASE_PH_OK;
+  std::string msg;
+  explicit operator bool() const { return st != CHASE_PH_OK; }
+};
+
+inline Err ok() { return Err{}; }
+inline Err fail(chase_ph_status st, const std::string& m) { return Err{st, m}; }
+
+#define CHASE_HIP(call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::chase::fail(CHASE_PH_ERR_HIP,                                             \
+                           std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define CHASE_TRY(expr)          \
+  do {                           \
+    ::chase::Err e_ = (expr);    \
+    if (e_) return e_;           \
+  } while (0)
+
+#define CHASE_LAUNCH_CHECK()                                                             \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess)                                                                \
+      return ::chase::fail(CHASE_PH_ERR_HIP,                                             \
+                           std::string("kernel launch: ") + hipGetErrorString(e_));      \
+  } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------------------------
+// Block-structured operator H X from the blocks A, B (apply_h.hip).
+//
+// Computes, for the active columns of an n x k block X,
+//   R = [A B] * [X, K conj(X)]          (m x 2k GEMM, K-dim 2m)
+//   (H X)_top = R[:, :k],  (H X)_bot = -conj(R[:, k:])
+// and writes  Y = alpha (H X) + beta P + gamma Q  (P, Q optional, real scalars).
+// Y may alias Q (element-wise read-before-write in the same thread).
+// ----------------------------------------------------------------------------
+template <typename R>
+struct ApplyHArgs {
+  using C = typename Cplx<R>::T;
+  const C* A;       // m x m, column-major, lda
+  const C* B;       // m x m, column-major, lda
+  int64_t lda;
+  int a_conj;       // buffer A holds conj(A)
+  int64_t m;
+  int k;            // active columns
+  const C* X;       // n x k, ldx (already offset to the first active column)
+  int64_t ldx;
+  C* Y;
+  int64_t ldy;
+  const C* P;       // may be null
+  int64_t ldp;
+  const C* Q;       // may be null
+  int64_t ldq;
+  R alpha, beta, gamma;
+};
+
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, hipStream_t s);
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// Generic complex FP64 GEMM (zgemm.hip):
+//   C = alpha * op(A) * diag_k(sgn) * op(B) + beta * C
+// op(X) = X or X^H.  sgn_k = -1 for k >= kneg (folds S into a product), +1
+// otherwise.  Batched with element strides; split-K through a workspace.
+// ----------------------------------------------------------------------------
+struct ZgemmArgs {
+  int transA, transB;  // 0: N, 1: C (conjugate transpose)
+  int64_t M, N, K;
+  c128 alpha, beta;
+  const c128* A;
+  int64_t lda, strideA;
+  const c128* B;
+  int64_t ldb, strideB;
+  c128* C;
+  int64_t ldc, strideC;
+  int64_t kneg;  // K index from which the sign flips (K for none)
+  int batch;
+};
+// workspace: device buffer of ws_bytes (may be 0 => no split-K)
+Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
+
+}  // namespace chase

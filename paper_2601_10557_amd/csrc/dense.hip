@@ -1,0 +1,541 @@
+// Small dense FP64 kernels of the QR and Rayleigh-Ritz steps (Section 2:
+// Cholesky QR; Alg. 2: POTRF, TRSM, HEEVD).  All operate on k x k Hermitian
+// or triangular matrices stored in a padded kp x kp buffer (kp a multiple of
+// 64, leading dimension kp) so that every blocked step has uniform sizes:
+//  * Cholesky  M = L L^H, right-looking, 64-column panels;
+//  * triangular inverse L^{-1}, by block diagonals of batched GEMMs;
+//  * Hermitian eigensolver: block Jacobi with 32-column blocks; each pair of
+//    blocks (a 64 x 64 subproblem) is diagonalised by cyclic Jacobi in LDS
+//    and the block rotations are applied to the matrix and the eigenvectors
+//    with 64 x 64 complex products.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "dense.h"
+
+namespace chase {
+namespace {
+
+constexpr int NB = 64;   // panel / padding granularity
+constexpr int JB = 32;   // Jacobi block (subproblem is 2*JB)
+constexpr int SP = 2 * JB;
+
+__device__ __forceinline__ c128 cmul(c128 a, c128 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ c128 cconj(c128 a) { return {a.re, -a.im}; }
+__device__ __forceinline__ c128 cadd(c128 a, c128 b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ c128 csub(c128 a, c128 b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ c128 cscale(double s, c128 a) { return {s * a.re, s * a.im}; }
+
+// ---------------------------------------------------------------- fills
+__global__ void fill_diag_kernel(c128* M, int64_t ld, int kp, int k, double inner, double pad, int zero_all) {
+  const int64_t total = (int64_t)kp * kp;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / kp), i = (int)(t % kp);
+    c128* p = M + (int64_t)j * ld + i;
+    if (i == j) {
+      *p = c128{i < k ? inner : pad, 0.0};
+    } else if (zero_all || i >= k || j >= k) {
+      *p = c128{0.0, 0.0};
+    }
+  }
+}
+
+// Zero the strict upper triangle (used after the blocked Cholesky, whose
+// trailing updates also touch the upper part).
+__global__ void zero_upper_kernel(c128* M, int64_t ld, int kp) {
+  const int64_t total = (int64_t)kp * kp;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / kp), i = (int)(t % kp);
+    if (i < j) M[(int64_t)j * ld + i] = c128{0.0, 0.0};
+  }
+}
+
+// ------------------------------------------------------- Cholesky block
+// Factor the 64 x 64 diagonal block at (p, p) in LDS; on a non-positive or
+// non-finite pivot set *fail and continue with a unit pivot (the result is
+// then discarded by the host).  Writes L_pp (lower, upper zeroed) and
+// its inverse into inv (64 x 64, ld 64).
+__global__ __launch_bounds__(256) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
+  __shared__ c128 S[NB][NB + 1];
+  __shared__ c128 I[NB][NB + 1];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < NB * NB; t += 256) {
+    const int j = t / NB, i = t % NB;
+    S[i][j] = M[(int64_t)(p + j) * ld + p + i];
+  }
+  __syncthreads();
+  __shared__ double piv;
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      double d = S[j][j].re;
+      if (!(d > 0.0) || !isfinite(d)) {
+        atomicOr(fail, 1);
+        d = 1.0;
+      }
+      piv = sqrt(d);
+      S[j][j] = c128{piv, 0.0};
+    }
+    __syncthreads();
+    const double rp = 1.0 / piv;
+    for (int i = j + 1 + tid; i < NB; i += 256) S[i][j] = cscale(rp, S[i][j]);
+    __syncthreads();
+    // trailing update of the lower part: S[i][l] -= L[i][j] conj(L[l][j]), i >= l > j
+    const int w = NB - j - 1;
+    for (int t = tid; t < w * w; t += 256) {
+      const int l = j + 1 + t / w, i = j + 1 + t % w;
+      if (i >= l) S[i][l] = csub(S[i][l], cmul(S[i][j], cconj(S[l][j])));
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular block: column c solves L x = e_c
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < NB; ++i) {
+      c128 s = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+      for (int l = c; l < i; ++l) s = csub(s, cmul(S[i][l], I[l][c]));
+      I[i][c] = (i < c) ? c128{0.0, 0.0} : cscale(1.0 / S[i][i].re, s);
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += 256) {
+    const int j = t / NB, i = t % NB;
+    M[(int64_t)(p + j) * ld + p + i] = (i >= j) ? S[i][j] : c128{0.0, 0.0};
+    inv[(int64_t)j * NB + i] = (i >= j) ? I[i][j] : c128{0.0, 0.0};
+  }
+}
+
+__global__ void copy_block_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int rows, int cols) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / rows, i = t % rows;
+    dst[j * ldd + i] = src[j * lds + i];
+  }
+}
+
+// Invert each 64 x 64 diagonal block of a lower-triangular L (padded) and
+// write it into the diagonal of Linv; zero the strict upper part of Linv.
+__global__ __launch_bounds__(256) void trinv_diag_kernel(const c128* L, c128* X, int64_t ld) {
+  __shared__ c128 S[NB][NB + 1];
+  __shared__ c128 I[NB][NB + 1];
+  const int p = blockIdx.x * NB;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < NB * NB; t += 256) {
+    const int j = t / NB, i = t % NB;
+    S[i][j] = L[(int64_t)(p + j) * ld + p + i];
+  }
+  __syncthreads();
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < NB; ++i) {
+      c128 s = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+      for (int l = c; l < i; ++l) s = csub(s, cmul(S[i][l], I[l][c]));
+      I[i][c] = (i < c) ? c128{0.0, 0.0} : cscale(1.0 / S[i][i].re, s);
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += 256) {
+    const int j = t / NB, i = t % NB;
+    X[(int64_t)(p + j) * ld + p + i] = I[i][j];
+  }
+}
+
+// ------------------------------------------------------------- Jacobi
+// Complex Jacobi rotation J = [[c, s], [-conj(s), c]] that diagonalises
+// [[a, b], [conj(b), d]] (a, d real):  with b = |b| e^{i phi},
+// tau = (d - a) / (2 |b|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// c = 1 / sqrt(1 + t^2), s = t c e^{i phi}  (Golub & Van Loan, symmetric
+// Schur 2x2, conjugated by diag(1, e^{-i phi})).
+__device__ __forceinline__ void jacobi_rot(double a, double d, c128 b, double thr, double& c, c128& s, double& t_out, int& did) {
+  const double ab = hypot(b.re, b.im);
+  if (!(ab > thr)) {
+    c = 1.0; s = c128{0.0, 0.0}; t_out = 0.0; did = 0;
+    return;
+  }
+  const double tau = (d - a) / (2.0 * ab);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  const double sr = t * c;
+  s = c128{sr * b.re / ab, sr * b.im / ab};
+  t_out = t * ab;
+  did = 1;
+}
+
+// Round-robin pairing of n players (n even), round r: position i plays
+// position n-1-i; position 0 is fixed, positions 1..n-1 rotate.
+__device__ __forceinline__ int rr_player(int pos, int r, int n) {
+  if (pos == 0) return 0;
+  return ((pos - 1 + r) % (n - 1)) + 1;
+}
+
+// Solve one 64 x 64 subproblem [[G_pp, G_pq], [G_qp, G_qq]] to convergence
+// by cyclic Jacobi in LDS; write the accumulated unitary U (64 x 64) to
+// Uw[pair] and count significant rotations in *count.
+__global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t ld, int nbj, int round,
+                                                         c128* Uw, double thr, int max_sweeps, int* count) {
+  __shared__ c128 S[SP][SP + 1];
+  __shared__ c128 U[SP][SP + 1];
+  __shared__ double rc[SP / 2];
+  __shared__ c128 rs[SP / 2];
+  __shared__ double rt[SP / 2];
+  __shared__ int any;
+  const int pair = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int bp = rr_player(pair, round, nbj), bq = rr_player(nbj - 1 - pair, round, nbj);
+  const int P = min(bp, bq) * JB, Q = max(bp, bq) * JB;
+  for (int t = tid; t < SP * SP; t += 256) {
+    const int j = t / SP, i = t % SP;
+    const int gi = i < JB ? P + i : Q + i - JB;
+    const int gj = j < JB ? P + j : Q + j - JB;
+    S[i][j] = G[(int64_t)gj * ld + gi];
+    U[i][j] = (i == j) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+  }
+  __syncthreads();
+  int total = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) any = 0;
+    __syncthreads();
+    for (int r = 0; r < SP - 1; ++r) {
+      if (tid < SP / 2) {
+        const int p = rr_player(tid, r, SP), q = rr_player(SP - 1 - tid, r, SP);
+        const int lo = min(p, q), hi = max(p, q);
+        double c, t;
+        c128 s;
+        int did;
+        jacobi_rot(S[lo][lo].re, S[hi][hi].re, S[lo][hi], thr, c, s, t, did);
+        rc[tid] = c;
+        rs[tid] = s;
+        rt[tid] = t;
+        if (did) any = 1;
+      }
+      __syncthreads();
+      // S <- J^H S J on 2x2 blocks (pair a rows, pair b cols)
+      for (int t = tid; t < (SP / 2) * (SP / 2); t += 256) {
+        const int a = t / (SP / 2), b = t % (SP / 2);
+        const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
+        const int pb0 = rr_player(b, r, SP), qb0 = rr_player(SP - 1 - b, r, SP);
+        const int pa = min(pa0, qa0), qa = max(pa0, qa0), pb = min(pb0, qb0), qb = max(pb0, qb0);
+        const double ca = rc[a], cb = rc[b];
+        const c128 sa = rs[a], sb = rs[b];
+        c128 x00 = S[pa][pb], x01 = S[pa][qb], x10 = S[qa][pb], x11 = S[qa][qb];
+        // rows: row_p' = c row_p - s row_q ; row_q' = conj(s) row_p + c row_q
+        c128 y00 = csub(cscale(ca, x00), cmul(sa, x10));
+        c128 y01 = csub(cscale(ca, x01), cmul(sa, x11));
+        c128 y10 = cadd(cmul(cconj(sa), x00), cscale(ca, x10));
+        c128 y11 = cadd(cmul(cconj(sa), x01), cscale(ca, x11));
+        // cols: col_p' = c col_p - conj(s) col_q ; col_q' = s col_p + c col_q
+        c128 z00 = csub(cscale(cb, y00), cmul(cconj(sb), y01));
+        c128 z01 = cadd(cmul(sb, y00), cscale(cb, y01));
+        c128 z10 = csub(cscale(cb, y10), cmul(cconj(sb), y11));
+        c128 z11 = cadd(cmul(sb, y10), cscale(cb, y11));
+        if (a == b) {
+          if (rt[a] != 0.0) {
+            z00 = c128{S[pa][pa].re - rt[a], 0.0};
+            z11 = c128{S[qa][qa].re + rt[a], 0.0};
+            z01 = c128{0.0, 0.0};
+            z10 = c128{0.0, 0.0};
+          } else {
+            z00.im = 0.0;
+            z11.im = 0.0;
+          }
+        }
+        S[pa][pb] = z00; S[pa][qb] = z01; S[qa][pb] = z10; S[qa][qb] = z11;
+      }
+      // U <- U J
+      for (int t = tid; t < SP * (SP / 2); t += 256) {
+        const int a = t / SP, i = t % SP;
+        const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
+        const int pa = min(pa0, qa0), qa = max(pa0, qa0);
+        const double ca = rc[a];
+        const c128 sa = rs[a];
+        const c128 up = U[i][pa], uq = U[i][qa];
+        U[i][pa] = csub(cscale(ca, up), cmul(cconj(sa), uq));
+        U[i][qa] = cadd(cmul(sa, up), cscale(ca, uq));
+      }
+      __syncthreads();
+    }
+    const int any_now = any;
+    __syncthreads();
+    if (!any_now) break;
+    ++total;
+  }
+  if (tid == 0 && total > 0) atomicAdd(count, 1);
+  c128* Uo = Uw + (int64_t)pair * SP * SP;
+  for (int t = tid; t < SP * SP; t += 256) {
+    const int j = t / SP, i = t % SP;
+    Uo[(int64_t)j * SP + i] = U[i][j];
+  }
+}
+
+// Index of row/col i (0..63) of the subproblem of pair `pair` in round `round`.
+__device__ __forceinline__ int sub_index(int pair, int round, int nbj, int i) {
+  const int bp = rr_player(pair, round, nbj), bq = rr_player(nbj - 1 - pair, round, nbj);
+  const int P = min(bp, bq) * JB, Q = max(bp, bq) * JB;
+  return i < JB ? P + i : Q + i - JB;
+}
+
+// G <- J^H G J with J block-diagonal (one 64 x 64 U per pair, in the pair's
+// index set); block (a, b) of pairs is U_a^H G_ab U_b.  Also V <- V J on
+// row chunks of 64.  blockIdx.x < npair^2: G blocks; the rest: V blocks.
+__global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int64_t ld, int kp, int nbj, int round,
+                                                           const c128* Uw) {
+  __shared__ c128 X[SP][SP + 1];
+  __shared__ c128 Y[SP][SP + 1];
+  const int npair = nbj / 2;
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;  // 4x4 outputs per thread: rows ti*4.., cols tj*4..
+  int blk = blockIdx.x;
+  if (blk < npair * npair) {
+    const int a = blk / npair, b = blk % npair;
+    const c128* Ua = Uw + (int64_t)a * SP * SP;
+    const c128* Ub = Uw + (int64_t)b * SP * SP;
+    for (int t = tid; t < SP * SP; t += 256) {
+      const int j = t / SP, i = t % SP;
+      X[i][j] = G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)];
+    }
+    __syncthreads();
+    // Y = X Ub
+    c128 acc[4][4];
+    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+    for (int l = 0; l < SP; ++l) {
+      c128 u[4];
+      for (int c = 0; c < 4; ++c) u[c] = Ub[(int64_t)(tj * 4 + c) * SP + l];
+      for (int r = 0; r < 4; ++r) {
+        const c128 x = X[ti * 4 + r][l];
+        for (int c = 0; c < 4; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
+      }
+    }
+    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) Y[ti * 4 + r][tj * 4 + c] = acc[r][c];
+    __syncthreads();
+    // out = Ua^H Y
+    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+    for (int l = 0; l < SP; ++l) {
+      c128 u[4];
+      for (int r = 0; r < 4; ++r) u[r] = cconj(Ua[(int64_t)(ti * 4 + r) * SP + l]);
+      for (int c = 0; c < 4; ++c) {
+        const c128 y = Y[l][tj * 4 + c];
+        for (int r = 0; r < 4; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
+      }
+    }
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        const int i = ti * 4 + r, j = tj * 4 + c;
+        c128 v = acc[r][c];
+        if (a == b && i == j) v.im = 0.0;
+        G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)] = v;
+      }
+  } else {
+    blk -= npair * npair;
+    const int a = blk % npair, rb = blk / npair;  // pair, row chunk
+    const c128* Ua = Uw + (int64_t)a * SP * SP;
+    const int r0 = rb * SP;
+    for (int t = tid; t < SP * SP; t += 256) {
+      const int j = t / SP, i = t % SP;
+      X[i][j] = V[(int64_t)sub_index(a, round, nbj, j) * ld + r0 + i];
+    }
+    __syncthreads();
+    c128 acc[4][4];
+    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+    for (int l = 0; l < SP; ++l) {
+      c128 u[4];
+      for (int c = 0; c < 4; ++c) u[c] = Ua[(int64_t)(tj * 4 + c) * SP + l];
+      for (int r = 0; r < 4; ++r) {
+        const c128 x = X[ti * 4 + r][l];
+        for (int c = 0; c < 4; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
+      }
+    }
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c)
+        V[(int64_t)sub_index(a, round, nbj, tj * 4 + c) * ld + r0 + ti * 4 + r] = acc[r][c];
+  }
+}
+
+__global__ void frob_kernel(const c128* G, int64_t ld, int kp, double* out) {
+  __shared__ double red[256];
+  double s = 0;
+  const int64_t total = (int64_t)kp * kp;
+  for (int64_t t = threadIdx.x; t < total; t += 256) {
+    const c128 z = G[(t / kp) * ld + t % kp];
+    s += z.re * z.re + z.im * z.im;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+// Select eigenvalues theta > 0 of the first k diagonal entries, order them
+// descending (ascending 1/theta), gather the matching eigenvector columns
+// (first kp rows) into Ysel and write lambda = 1/theta.  Counts positives and
+// negatives that are resolved away from zero.
+__global__ void select_kernel(const c128* G, const c128* V, int64_t ld, int k, int kp, double tiny,
+                              c128* Ysel, double* lam, int* npos, int* nneg) {
+  const int i = blockIdx.x;
+  if (i >= k) return;
+  const double ti = G[(int64_t)i * ld + i].re;
+  if (threadIdx.x == 0) {
+    if (ti > tiny) atomicAdd(npos, 1);
+    if (ti < -tiny) atomicAdd(nneg, 1);
+  }
+  if (!(ti > tiny)) return;
+  __shared__ int rank;
+  if (threadIdx.x == 0) rank = 0;
+  __syncthreads();
+  int cnt = 0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const double tj = G[(int64_t)j * ld + j].re;
+    if (tj > ti || (tj == ti && j < i)) ++cnt;
+  }
+  atomicAdd(&rank, cnt);
+  __syncthreads();
+  const int r = rank;
+  if (r >= k / 2) return;
+  if (threadIdx.x == 0) lam[r] = 1.0 / ti;
+  for (int row = threadIdx.x; row < kp; row += blockDim.x) Ysel[(int64_t)r * kp + row] = V[(int64_t)i * ld + row];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048)); }
+
+Err fill_padded(c128* M, int kp, int k, double inner, double pad, bool zero_all, hipStream_t s) {
+  hipLaunchKernelGGL(fill_diag_kernel, dim3(grid_for((int64_t)kp * kp)), dim3(256), 0, s, M, (int64_t)kp, kp, k,
+                     inner, pad, zero_all ? 1 : 0);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err cholesky_lower(c128* M, int kp, DenseWs& ws, hipStream_t s, bool* failed) {
+  CHASE_HIP(hipMemsetAsync(ws.flag, 0, sizeof(int), s));
+  const int nblk = kp / NB;
+  for (int b = 0; b < nblk; ++b) {
+    const int p = b * NB;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, M, (int64_t)kp, p, ws.small, ws.flag);
+    CHASE_LAUNCH_CHECK();
+    const int rest = kp - p - NB;
+    if (rest <= 0) break;
+    // panel: L_ip = A_ip * L_pp^{-H}
+    hipLaunchKernelGGL(copy_block_kernel, dim3(grid_for((int64_t)rest * NB)), dim3(256), 0, s,
+                       (const c128*)(M + (int64_t)p * kp + p + NB), (int64_t)kp, ws.panel, (int64_t)rest, rest, NB);
+    CHASE_LAUNCH_CHECK();
+    ZgemmArgs g{};
+    g.transA = 0; g.transB = 1;
+    g.M = rest; g.N = NB; g.K = NB;
+    g.alpha = {1, 0}; g.beta = {0, 0};
+    g.A = ws.panel; g.lda = rest; g.B = ws.small; g.ldb = NB;
+    g.C = M + (int64_t)p * kp + p + NB; g.ldc = kp;
+    g.kneg = NB; g.batch = 1;
+    CHASE_TRY(zgemm(g, nullptr, 0, s));
+    // trailing update: A22 -= L_ip L_ip^H
+    ZgemmArgs u{};
+    u.transA = 0; u.transB = 1;
+    u.M = rest; u.N = rest; u.K = NB;
+    u.alpha = {-1, 0}; u.beta = {1, 0};
+    u.A = M + (int64_t)p * kp + p + NB; u.lda = kp;
+    u.B = M + (int64_t)p * kp + p + NB; u.ldb = kp;
+    u.C = M + (int64_t)(p + NB) * kp + p + NB; u.ldc = kp;
+    u.kneg = NB; u.batch = 1;
+    CHASE_TRY(zgemm(u, nullptr, 0, s));
+  }
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(grid_for((int64_t)kp * kp)), dim3(256), 0, s, M, (int64_t)kp, kp);
+  CHASE_LAUNCH_CHECK();
+  int f = 0;
+  CHASE_HIP(hipMemcpyAsync(&f, ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  *failed = f != 0;
+  return ok();
+}
+
+Err tri_inverse_lower(const c128* L, c128* X, int kp, DenseWs& ws, hipStream_t s) {
+  const int nblk = kp / NB;
+  CHASE_TRY(fill_padded(X, kp, kp, 0.0, 0.0, true, s));
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(256), 0, s, L, X, (int64_t)kp);
+  CHASE_LAUNCH_CHECK();
+  const int64_t stride = (int64_t)NB * (kp + 1);
+  for (int d = 1; d < nblk; ++d) {
+    const int batch = nblk - d;
+    // T_j = L[j+d, j..j+d-1] * X[j..j+d-1, j]
+    ZgemmArgs g{};
+    g.transA = 0; g.transB = 0;
+    g.M = NB; g.N = NB; g.K = (int64_t)d * NB;
+    g.alpha = {1, 0}; g.beta = {0, 0};
+    g.A = L + (int64_t)d * NB; g.lda = kp; g.strideA = stride;
+    g.B = X; g.ldb = kp; g.strideB = stride;
+    g.C = ws.tmp; g.ldc = NB; g.strideC = (int64_t)NB * NB;
+    g.kneg = g.K; g.batch = batch;
+    CHASE_TRY(zgemm(g, nullptr, 0, s));
+    // X[j+d, j] = -X[j+d, j+d] * T_j
+    ZgemmArgs h{};
+    h.transA = 0; h.transB = 0;
+    h.M = NB; h.N = NB; h.K = NB;
+    h.alpha = {-1, 0}; h.beta = {0, 0};
+    h.A = X + (int64_t)d * NB * (kp + 1); h.lda = kp; h.strideA = stride;
+    h.B = ws.tmp; h.ldb = NB; h.strideB = (int64_t)NB * NB;
+    h.C = X + (int64_t)d * NB; h.ldc = kp; h.strideC = stride;
+    h.kneg = NB; h.batch = batch;
+    CHASE_TRY(zgemm(h, nullptr, 0, s));
+  }
+  return ok();
+}
+
+Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sweeps, int* sweeps_out) {
+  const int nbj = kp / JB;  // even since kp % 64 == 0
+  const int npair = nbj / 2;
+  CHASE_TRY(fill_padded(V, kp, kp, 1.0, 1.0, true, s));
+  hipLaunchKernelGGL(frob_kernel, dim3(1), dim3(256), 0, s, (const c128*)G, (int64_t)kp, kp, ws.dscalar);
+  CHASE_LAUNCH_CHECK();
+  double fro = 0;
+  CHASE_HIP(hipMemcpyAsync(&fro, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  const double thr = 1e-16 * std::max(fro, 1e-300);
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    CHASE_HIP(hipMemsetAsync(ws.flag, 0, sizeof(int), s));
+    for (int r = 0; r < nbj - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_sub_kernel, dim3(npair), dim3(256), 0, s, (const c128*)G, (int64_t)kp, nbj, r,
+                         ws.U, thr, 30, ws.flag);
+      CHASE_LAUNCH_CHECK();
+      const int blocks = npair * npair + npair * (kp / SP);
+      hipLaunchKernelGGL(jacobi_apply_kernel, dim3(blocks), dim3(256), 0, s, G, V, (int64_t)kp, kp, nbj, r,
+                         (const c128*)ws.U);
+      CHASE_LAUNCH_CHECK();
+    }
+    int cnt = 0;
+    CHASE_HIP(hipMemcpyAsync(&cnt, ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHASE_HIP(hipStreamSynchronize(s));
+    if (cnt == 0) break;
+  }
+  if (sweeps_out) *sweeps_out = sweep;
+  return ok();
+}
+
+Err select_positive(const c128* G, const c128* V, int k, int kp, c128* Ysel, double* dlam, DenseWs& ws,
+                    hipStream_t s, int* npos, int* nneg) {
+  // tiny: 1e3 * u * max|theta| bounded by the Frobenius norm
+  hipLaunchKernelGGL(frob_kernel, dim3(1), dim3(256), 0, s, G, (int64_t)kp, kp, ws.dscalar);
+  CHASE_LAUNCH_CHECK();
+  double fro = 0;
+  CHASE_HIP(hipMemcpyAsync(&fro, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  const double tiny = 1e3 * 1.1102230246251565e-16 * fro;
+  CHASE_HIP(hipMemsetAsync(ws.flag, 0, 2 * sizeof(int), s));
+  CHASE_HIP(hipMemsetAsync(Ysel, 0, (size_t)kp * (k / 2) * sizeof(c128), s));
+  hipLaunchKernelGGL(select_kernel, dim3(k), dim3(256), 0, s, G, V, (int64_t)kp, k, kp, tiny, Ysel, dlam, ws.flag,
+                     ws.flag + 1);
+  CHASE_LAUNCH_CHECK();
+  int h[2] = {0, 0};
+  CHASE_HIP(hipMemcpyAsync(h, ws.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  *npos = h[0];
+  *nneg = h[1];
+  return ok();
+}
+
+int pad64(int k) { return (int)ceil_div(std::max(k, 1), NB) * NB; }
+
+}  // namespace chase

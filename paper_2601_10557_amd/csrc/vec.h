@@ -1,0 +1,29 @@
+// Elementwise / column-reduction kernels (vec.hip).
+#pragma once
+#include "common.h"
+
+namespace chase {
+
+Err build_search_block(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx,
+                       int64_t m, hipStream_t s);
+Err convert_to_c64(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s);
+Err convert_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s);
+Err make_shadow(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32, int64_t m,
+                hipStream_t s);
+Err scale_lower_half(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g,
+                     hipStream_t s);
+Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* dlam, int64_t n, int kk,
+                   double* dres, hipStream_t s);
+Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s);
+Err lanczos_residual(const c128* w, const c128* v, const c128* vp, c128* r, int64_t ld, int64_t n, int nv,
+                     const double* alpha, const double* beta_prev, hipStream_t s);
+Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, int64_t ld, int64_t n, int nv,
+                    const double* bsq, bool shift_prev, hipStream_t s);
+Err adjoint_operands(const c128* V, int64_t ldv, int64_t m, int nev, const double* dg, c128* P, c128* P2, c128* Pg,
+                     int64_t ldp, hipStream_t s);
+Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s);
+Err add_diag(c128* G, int64_t ld, int k, double v, hipStream_t s);
+Err gather_columns(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t n, int k, const int* dperm,
+                   hipStream_t s);
+
+}  // namespace chase

@@ -1,0 +1,316 @@
+// Elementwise and column-reduction kernels of the solver loop: assembling
+// the search block with the S / K conj structure folded in (Section 4.3,
+// eq. 4.5; Thm 4.2), c128 <-> c64 conversion of the filter block, the fused
+// residual / normalisation of the half back-transform (Section 4.5),
+// S-inner products of the Lanczos estimates (Section 4.1) and the operand
+// build of the eigenvalue adjoint.
+#include <algorithm>
+
+#include "common.h"
+#include "vec.h"
+
+namespace chase {
+namespace {
+
+inline int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 8192)); }
+
+// X = [S Y, S K conj(Y), W, K conj(W)]   (Y: n x L, W: n x kw)
+__global__ void build_x_kernel(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X,
+                               int64_t ldx, int64_t m) {
+  const int64_t n = 2 * m;
+  const int cols = 2 * L + 2 * kw;
+  const int64_t total = n * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t / n);
+    const int64_t i = t % n;
+    c128 z;
+    if (c < L) {
+      z = Y[(int64_t)c * ldy + i];
+      if (i >= m) { z.re = -z.re; z.im = -z.im; }
+    } else if (c < 2 * L) {
+      const int64_t src = i < m ? i + m : i - m;
+      z = Y[(int64_t)(c - L) * ldy + src];
+      z.im = -z.im;
+      if (i >= m) { z.re = -z.re; z.im = -z.im; }
+    } else if (c < 2 * L + kw) {
+      z = W[(int64_t)(c - 2 * L) * ldw + i];
+    } else {
+      const int64_t src = i < m ? i + m : i - m;
+      z = W[(int64_t)(c - 2 * L - kw) * ldw + src];
+      z.im = -z.im;
+    }
+    X[(int64_t)c * ldx + i] = z;
+  }
+}
+
+__global__ void to_c64_kernel(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols) {
+  const int64_t total = rows * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / rows, i = t % rows;
+    const c128 z = src[j * lds + i];
+    dst[j * ldd + i] = c64{(float)z.re, (float)z.im};
+  }
+}
+
+__global__ void to_c128_kernel(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int cols) {
+  const int64_t total = rows * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / rows, i = t % rows;
+    const c64 z = src[j * lds + i];
+    dst[j * ldd + i] = c128{(double)z.re, (double)z.im};
+  }
+}
+
+// conj(A) and B (c128, ld) -> c64 copies with leading dimension ld32
+__global__ void shadow_kernel(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32,
+                              int64_t m) {
+  const int64_t total = m * m;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / m, i = t % m;
+    const c128 a = A[j * ld + i];
+    const c128 b = B[j * ld + i];
+    A32[j * ld32 + i] = c64{(float)a.re, (float)(a_conj ? -a.im : a.im)};
+    B32[j * ld32 + i] = c64{(float)b.re, (float)b.im};
+  }
+}
+
+__global__ void scale_lower_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g) {
+  const int64_t n = 2 * m;
+  const int64_t total = n * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / n, i = t % n;
+    c128 z = src[j * lds + i];
+    if (i >= m) { z.re *= g; z.im *= g; }
+    dst[j * ldd + i] = z;
+  }
+}
+
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Per column j: nu = ||V_j||, r_j = ||TZ_j - lam_j V_j|| / nu, V_j /= nu.
+__global__ __launch_bounds__(256) void resid_kernel(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* lam,
+                                                    int64_t n, double* resid) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  c128* v = V + (int64_t)j * ldv;
+  const c128* tz = TZ + (int64_t)j * ldt;
+  const double l = lam[j];
+  double s1 = 0, s2 = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const c128 a = v[i], b = tz[i];
+    s1 += a.re * a.re + a.im * a.im;
+    const double dr = b.re - l * a.re, di = b.im - l * a.im;
+    s2 += dr * dr + di * di;
+  }
+  const double nu2 = block_sum(s1, red);
+  const double rr2 = block_sum(s2, red);
+  const double nu = sqrt(nu2);
+  const double inv = nu > 0 ? 1.0 / nu : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    c128 a = v[i];
+    v[i] = c128{a.re * inv, a.im * inv};
+  }
+  if (threadIdx.x == 0) resid[j] = sqrt(rr2) * inv;
+}
+
+// out[j] = Re(x_j^H S y_j)
+__global__ __launch_bounds__(256) void sdot_kernel(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m,
+                                                   double* out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const c128* x = X + (int64_t)j * ldx;
+  const c128* y = Y + (int64_t)j * ldy;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < 2 * m; i += 256) {
+    const double p = x[i].re * y[i].re + x[i].im * y[i].im;
+    s += i < m ? p : -p;
+  }
+  const double r = block_sum(s, red);
+  if (threadIdx.x == 0) out[j] = r;
+}
+
+// r = w - alpha v - beta v_prev  (per column scalars; beta_prev holds beta^2)
+__global__ void lanczos_r_kernel(const c128* w, const c128* v, const c128* vp, c128* r, int64_t ld, int64_t n, int nv,
+                                 const double* alpha, const double* beta_prev) {
+  const int64_t total = n * nv;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / n);
+    const int64_t o = (int64_t)j * ld + t % n;
+    const double a = alpha[j], b = beta_prev ? sqrt(fmax(beta_prev[j], 0.0)) : 0.0;
+    r[o] = c128{w[o].re - a * v[o].re - b * vp[o].re, w[o].im - a * v[o].im - b * vp[o].im};
+  }
+}
+
+// vp <- v; v <- r / sqrt(bsq); w <- z / sqrt(bsq); beta <- sqrt(max(bsq, 0))
+__global__ void lanczos_next_kernel(c128* vp, c128* v, c128* w, const c128* r, const c128* z, int64_t ld, int64_t n,
+                                    int nv, const double* bsq, int shift_prev) {
+  const int64_t total = n * nv;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / n);
+    const int64_t o = (int64_t)j * ld + t % n;
+    const double b = sqrt(fmax(bsq[j], 0.0));
+    const double ib = b > 0 ? 1.0 / b : 0.0;
+    if (shift_prev) vp[o] = v[o];
+    v[o] = c128{r[o].re * ib, r[o].im * ib};
+    w[o] = c128{z[o].re * ib, z[o].im * ib};
+  }
+}
+
+// Adjoint operands from V (n x nev) and g: P = [x_i, conj(y_i)],
+// P2 = [y_i, conj(x_i)], Pg = P * diag(gt, gt), gt_i = g_i / (|x_i|^2 - |y_i|^2).
+__global__ __launch_bounds__(256) void adjoint_prep_kernel(const c128* V, int64_t ldv, int64_t m, int nev,
+                                                           const double* g, c128* P, c128* P2, c128* Pg, int64_t ldp) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const c128* v = V + (int64_t)j * ldv;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < 2 * m; i += 256) {
+    const double p = v[i].re * v[i].re + v[i].im * v[i].im;
+    s += i < m ? p : -p;
+  }
+  const double d = block_sum(s, red);
+  const double gt = g[j] / d;
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    const c128 x = v[i], y = v[m + i];
+    const c128 yb{y.re, -y.im}, xb{x.re, -x.im};
+    P[(int64_t)j * ldp + i] = x;
+    P[(int64_t)(nev + j) * ldp + i] = yb;
+    P2[(int64_t)j * ldp + i] = y;
+    P2[(int64_t)(nev + j) * ldp + i] = xb;
+    Pg[(int64_t)j * ldp + i] = c128{gt * x.re, gt * x.im};
+    Pg[(int64_t)(nev + j) * ldp + i] = c128{gt * yb.re, gt * yb.im};
+  }
+}
+
+__global__ void trace_kernel(const c128* G, int64_t ld, int k, double* out) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int i = threadIdx.x; i < k; i += 256) s += G[(int64_t)i * ld + i].re;
+  const double r = block_sum(s, red);
+  if (threadIdx.x == 0) *out = r;
+}
+
+__global__ void add_diag_kernel(c128* G, int64_t ld, int k, double s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) G[(int64_t)i * ld + i].re += s;
+}
+
+// dst[:, j] = src[:, perm[j]]
+__global__ void gather_cols_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t n, int k,
+                                   const int* perm) {
+  const int64_t total = n * k;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / n);
+    const int64_t i = t % n;
+    dst[(int64_t)j * ldd + i] = src[(int64_t)perm[j] * lds + i];
+  }
+}
+
+}  // namespace
+
+Err build_search_block(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx,
+                       int64_t m, hipStream_t s) {
+  const int64_t total = 2 * m * (2 * L + 2 * kw);
+  if (total == 0) return ok();
+  hipLaunchKernelGGL(build_x_kernel, dim3(grid_for(total)), dim3(256), 0, s, Y, ldy, L, W, ldw, kw, X, ldx, m);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err convert_to_c64(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s) {
+  if (rows * cols == 0) return ok();
+  hipLaunchKernelGGL(to_c64_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err convert_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s) {
+  if (rows * cols == 0) return ok();
+  hipLaunchKernelGGL(to_c128_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err make_shadow(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32, int64_t m,
+                hipStream_t s) {
+  hipLaunchKernelGGL(shadow_kernel, dim3(grid_for(m * m)), dim3(256), 0, s, A, B, ld, a_conj, A32, B32, ld32, m);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err scale_lower_half(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g,
+                     hipStream_t s) {
+  if (cols == 0) return ok();
+  hipLaunchKernelGGL(scale_lower_kernel, dim3(grid_for(2 * m * cols)), dim3(256), 0, s, src, lds, dst, ldd, m, cols, g);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* dlam, int64_t n, int kk,
+                   double* dres, hipStream_t s) {
+  if (kk == 0) return ok();
+  hipLaunchKernelGGL(resid_kernel, dim3(kk), dim3(256), 0, s, V, ldv, TZ, ldt, dlam, n, dres);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, m, out);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err lanczos_residual(const c128* w, const c128* v, const c128* vp, c128* r, int64_t ld, int64_t n, int nv,
+                     const double* alpha, const double* beta_prev, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_r_kernel, dim3(grid_for(n * nv)), dim3(256), 0, s, w, v, vp, r, ld, n, nv, alpha,
+                     beta_prev);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, int64_t ld, int64_t n, int nv,
+                    const double* bsq, bool shift_prev, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_next_kernel, dim3(grid_for(n * nv)), dim3(256), 0, s, vp, v, w, r, z, ld, n, nv, bsq,
+                     shift_prev ? 1 : 0);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err adjoint_operands(const c128* V, int64_t ldv, int64_t m, int nev, const double* dg, c128* P, c128* P2, c128* Pg,
+                     int64_t ldp, hipStream_t s) {
+  hipLaunchKernelGGL(adjoint_prep_kernel, dim3(nev), dim3(256), 0, s, V, ldv, m, nev, dg, P, P2, Pg, ldp);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
+  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, s, G, ld, k, dout);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err add_diag(c128* G, int64_t ld, int k, double v, hipStream_t s) {
+  hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, G, ld, k, v);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err gather_columns(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t n, int k, const int* dperm,
+                   hipStream_t s) {
+  if (k == 0) return ok();
+  hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_for(n * k)), dim3(256), 0, s, src, lds, dst, ldd, n, k, dperm);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+}  // namespace chase

@@ -1,0 +1,244 @@
+// Complex FP64 GEMM on v_mfma_f64_16x16x4_f64:
+//   C = alpha * op(A) * diag(s) * op(B) + beta * C,   s_k = -1 for k >= kneg
+// op(X) in {X, X^H}.  Used for the Gram matrices of CholeskyQR2 (X^H X), the
+// Rayleigh quotient pieces of Alg. 2 (Q^H S T folds S through kneg = m,
+// Q2^H Q2), the back-transforms Q Z and T Z, the triangular products of the
+// Cholesky / inverse / Jacobi kernels (batched) and the adjoint contraction.
+// Tall-skinny inner products (K >> M, N) are split along K into a workspace
+// and reduced in a fixed order (deterministic).
+#include "common.h"
+
+namespace chase {
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int LDS_A = BM + 2, LDS_B = BN + 2;
+
+__device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct ZgemmDev {
+  int transA, transB;
+  int64_t M, N, K;
+  double ar, ai, br, bi;  // alpha, beta
+  const c128* A;
+  int64_t lda, strideA;
+  const c128* B;
+  int64_t ldb, strideB;
+  c128* C;
+  int64_t ldc, strideC;
+  int64_t kneg;
+  int splits;
+  int64_t kchunk;  // K range per split (multiple of BK)
+  c128* ws;        // splits * batch * M * N partials (split-K only)
+};
+
+__global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
+  __shared__ double As[2][2][BK][LDS_A];
+  __shared__ double Bs[2][2][BK][LDS_B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int TN = (int)((g.N + BN - 1) / BN);
+  const int64_t m0 = (int64_t)(blockIdx.x / TN) * BM;
+  const int64_t n0 = (int64_t)(blockIdx.x % TN) * BN;
+  const int bt = blockIdx.y, sp = blockIdx.z;
+  const c128* A = g.A + (int64_t)bt * g.strideA;
+  const c128* B = g.B + (int64_t)bt * g.strideB;
+  const int64_t kbeg = (int64_t)sp * g.kchunk;
+  const int64_t kend = min(g.K, kbeg + g.kchunk);
+  const int KT = (int)((kend - kbeg + BK - 1) / BK);
+  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+
+  constexpr int PER = BM * BK / NT;  // 4 elements of each operand per thread
+  double ar[PER], ai[PER], br[PER], bi[PER];
+
+  auto load = [&](int kt) {
+    const int64_t k0 = kbeg + (int64_t)kt * BK;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int el = tid + e * NT;
+      int i, kk;
+      if (g.transA == 0) { kk = el / BM; i = el % BM; } else { i = el / BK; kk = el % BK; }
+      const int64_t gi = m0 + i, gk = k0 + kk;
+      double vr = 0, vi = 0;
+      if (gi < g.M && gk < kend) {
+        if (g.transA == 0) { c128 z = A[gk * g.lda + gi]; vr = z.re; vi = z.im; }
+        else { c128 z = A[gi * g.lda + gk]; vr = z.re; vi = -z.im; }
+      }
+      ar[e] = vr; ai[e] = vi;
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int el = tid + e * NT;
+      int j, kk;
+      if (g.transB == 0) { j = el / BK; kk = el % BK; } else { kk = el / BN; j = el % BN; }
+      const int64_t gj = n0 + j, gk = k0 + kk;
+      double vr = 0, vi = 0;
+      if (gj < g.N && gk < kend) {
+        if (g.transB == 0) { c128 z = B[gj * g.ldb + gk]; vr = z.re; vi = z.im; }
+        else { c128 z = B[gk * g.ldb + gj]; vr = z.re; vi = -z.im; }
+        if (gk >= g.kneg) { vr = -vr; vi = -vi; }
+      }
+      br[e] = vr; bi[e] = vi;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int el = tid + e * NT;
+      int i, kk;
+      if (g.transA == 0) { kk = el / BM; i = el % BM; } else { i = el / BK; kk = el % BK; }
+      As[buf][0][kk][i] = ar[e];
+      As[buf][1][kk][i] = ai[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int el = tid + e * NT;
+      int j, kk;
+      if (g.transB == 0) { j = el / BK; kk = el % BK; } else { kk = el / BN; j = el % BN; }
+      Bs[buf][0][kk][j] = br[e];
+      Bs[buf][1][kk][j] = bi[e];
+    }
+  };
+
+  doublex4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { cr[i][j][r] = 0; ci[i][j][r] = 0; }
+
+  if (KT > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < KT) load(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double fa_r[2], fa_i[2], fb_r[2], fb_i[2], fb_n[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        fa_r[i] = As[buf][0][ks + lk][wm0 + 16 * i + lr];
+        fa_i[i] = As[buf][1][ks + lk][wm0 + 16 * i + lr];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        fb_r[j] = Bs[buf][0][ks + lk][wn0 + 16 * j + lr];
+        fb_i[j] = Bs[buf][1][ks + lk][wn0 + 16 * j + lr];
+        fb_n[j] = -fb_i[j];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
+          ci[i][j] = mfma64(fa_r[i], fb_i[j], ci[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = mfma64(fa_i[i], fb_n[j], cr[i][j]);
+          ci[i][j] = mfma64(fa_i[i], fb_r[j], ci[i][j]);
+        }
+    }
+    if (kt + 1 < KT) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const int batch = gridDim.y;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = m0 + wm0 + 16 * i + (lane >> 4) + 4 * r;
+        const int64_t gj = n0 + wn0 + 16 * j + (lane & 15);
+        if (gi < g.M && gj < g.N) {
+          const double xr = cr[i][j][r], xi = ci[i][j][r];
+          const double yr = g.ar * xr - g.ai * xi, yi = g.ar * xi + g.ai * xr;
+          if (g.splits > 1) {
+            c128* w = g.ws + ((int64_t)sp * batch + bt) * g.M * g.N;
+            w[gj * g.M + gi] = c128{yr, yi};
+          } else {
+            c128* Cp = g.C + (int64_t)bt * g.strideC + gj * g.ldc + gi;
+            double outr = yr, outi = yi;
+            if (g.br != 0.0 || g.bi != 0.0) {
+              c128 c = *Cp;
+              outr += g.br * c.re - g.bi * c.im;
+              outi += g.br * c.im + g.bi * c.re;
+            }
+            *Cp = c128{outr, outi};
+          }
+        }
+      }
+}
+
+__global__ void zgemm_reduce(const ZgemmDev g, int batch) {
+  const int64_t total = (int64_t)batch * g.M * g.N;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bt = t / (g.M * g.N), rem = t % (g.M * g.N);
+    const int64_t gj = rem / g.M, gi = rem % g.M;
+    double sr = 0, si = 0;
+    for (int s = 0; s < g.splits; ++s) {
+      c128 w = g.ws[((int64_t)s * batch + bt) * g.M * g.N + rem];
+      sr += w.re;
+      si += w.im;
+    }
+    c128* Cp = g.C + bt * g.strideC + gj * g.ldc + gi;
+    if (g.br != 0.0 || g.bi != 0.0) {
+      c128 c = *Cp;
+      sr += g.br * c.re - g.bi * c.im;
+      si += g.br * c.im + g.bi * c.re;
+    }
+    *Cp = c128{sr, si};
+  }
+}
+
+}  // namespace
+
+Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return ok();
+  ZgemmDev g;
+  g.transA = a.transA; g.transB = a.transB;
+  g.M = a.M; g.N = a.N; g.K = a.K;
+  g.ar = a.alpha.re; g.ai = a.alpha.im; g.br = a.beta.re; g.bi = a.beta.im;
+  g.A = a.A; g.lda = a.lda; g.strideA = a.strideA;
+  g.B = a.B; g.ldb = a.ldb; g.strideB = a.strideB;
+  g.C = a.C; g.ldc = a.ldc; g.strideC = a.strideC;
+  g.kneg = a.kneg;
+  const int64_t tiles = ceil_div(a.M, BM) * ceil_div(a.N, BN);
+  int splits = 1;
+  if (a.K > 0 && ws && tiles * a.batch < 512) {
+    const int64_t want = ceil_div(1024, tiles * a.batch);
+    const int64_t maxk = std::max<int64_t>(1, a.K / (8 * BK));
+    int64_t sp = std::min(want, maxk);
+    const int64_t per = a.M * a.N * a.batch * (int64_t)sizeof(c128);
+    sp = std::min<int64_t>(sp, (int64_t)(ws_bytes / per));
+    splits = (int)std::max<int64_t>(1, std::min<int64_t>(sp, 64));
+  }
+  g.splits = splits;
+  g.kchunk = ceil_div(ceil_div(std::max<int64_t>(a.K, 1), splits), BK) * BK;
+  splits = (int)ceil_div(std::max<int64_t>(a.K, 1), g.kchunk);
+  g.splits = splits;
+  g.ws = (c128*)ws;
+  hipLaunchKernelGGL(zgemm_kernel, dim3((unsigned)tiles, (unsigned)a.batch, (unsigned)splits),
+                     dim3(NT), 0, s, g);
+  CHASE_LAUNCH_CHECK();
+  if (splits > 1) {
+    const int64_t total = (int64_t)a.batch * a.M * a.N;
+    const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 4096);
+    hipLaunchKernelGGL(zgemm_reduce, dim3(blocks), dim3(256), 0, s, g, a.batch);
+    CHASE_LAUNCH_CHECK();
+  }
+  return ok();
+}
+
+}  // namespace chase

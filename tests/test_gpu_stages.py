@@ -1,0 +1,233 @@
+"""GPU parity of each stage of the C ABI against the CPU oracle.
+
+Sizes span several kernel tiles with ragged tails (m = 300: 128-row tiles
+end at 44 rows; 2k = 74 output columns end mid-tile).  Tolerances:
+FP64 stages ~1e-12 relative (rounding of an O(n) inner product), c64
+stages 1e-5 relative (unit roundoff 6e-8 times the inner-product length).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import chebyshev, dense, hamiltonian as ham, qr as oqr, rayleigh_ritz, residuals as ores, solver as osolver
+from paper_2601_10557_amd import FP32, FP64, ChasePHError, PHSolver, empty_cm
+from paper_2601_10557_amd import _lib
+from synth import make_problem, complex_normal
+from gpu_helpers import align_columns, dev_blocks, print_case, to_dev, to_host
+
+
+def problem(m=300, seed=0, coupling=0.4, nev=12, nex=8):
+    return make_problem(m, lambda rng, mm: rng.uniform(1.0, 5.0, mm), coupling, nev, nex, 10, 1e-10, seed=seed)
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return problem()
+
+
+@pytest.fixture(scope="module")
+def solver(prob):
+    A, B = dev_blocks(prob)
+    return PHSolver(A, B, prob.nev, prob.nex)
+
+
+@pytest.mark.parametrize("k", [1, 5, 37])
+def test_apply_h_fp64(prob, solver, k):
+    print_case("apply_h_fp64", m=prob.m, k=k)
+    rng = np.random.default_rng(k)
+    X = complex_normal(rng, (prob.n, k))
+    Y = to_host(solver.apply_h(to_dev(X)))
+    ref = ham.apply_h(prob.A, prob.B, X)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_apply_h_empty(solver):
+    X = empty_cm(solver.n, 0)
+    Y = solver.apply_h(X)
+    assert Y.shape == (solver.n, 0)
+
+
+@pytest.mark.parametrize("k", [3, 37])
+def test_apply_h_fp32(prob, solver, k):
+    print_case("apply_h_fp32", m=prob.m, k=k)
+    rng = np.random.default_rng(100 + k)
+    X = complex_normal(rng, (prob.n, k))
+    Y = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
+    ref = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
+    assert np.max(np.abs(Y - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def _mus(prob):
+    lam, _ = dense.dense_ph_eig(prob.A, prob.B)
+    return 0.95 * lam[0], lam[prob.nevex - 1], 1.02 * lam[-1]
+
+
+@pytest.mark.parametrize("degs", [[1] * 6, [4] * 7, [7] * 5, [1, 2, 2, 3, 7, 7, 10, 11]])
+def test_filter_fp64(prob, solver, degs):
+    print_case("filter_fp64", m=prob.m, degs=degs)
+    mu1, mu_nevex, mu_n = _mus(prob)
+    rng = np.random.default_rng(len(degs) + sum(degs))
+    W = osolver.init_block(complex_normal(rng, (prob.n, len(degs))), 1e-3)
+    Wd = to_dev(W)
+    solver.filter(Wd, mu1, mu_nevex, mu_n, degs=degs, prec=FP64)
+    ref = chebyshev.chebyshev_filter(prob.A, prob.B, W, np.array(degs), mu1, mu_nevex, mu_n)
+    got = to_host(Wd)
+    err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.max(err) < 1e-11, err
+
+
+def test_filter_fp32(prob, solver):
+    print_case("filter_fp32", m=prob.m)
+    mu1, mu_nevex, mu_n = _mus(prob)
+    rng = np.random.default_rng(7)
+    degs = [2, 5, 5, 9, 12]
+    W = osolver.init_block(complex_normal(rng, (prob.n, len(degs))), 1e-3)
+    Wd = to_dev(W, torch.complex64)
+    solver.filter(Wd, mu1, mu_nevex, mu_n, degs=degs, prec=FP32)
+    ref = chebyshev.chebyshev_filter(prob.A, prob.B, W, np.array(degs), mu1, mu_nevex, mu_n)
+    got = to_host(Wd).astype(np.complex128)
+    err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.max(err) < 1e-4, err
+
+
+def test_filter_kconj_equivariance(prob, solver):
+    # Thm 4.2 on the device path
+    mu1, mu_nevex, mu_n = _mus(prob)
+    rng = np.random.default_rng(3)
+    W = complex_normal(rng, (prob.n, 4))
+    a = to_dev(W)
+    b = to_dev(ham.apply_k_conj(W))
+    solver.filter(a, mu1, mu_nevex, mu_n, degs=[6] * 4)
+    solver.filter(b, mu1, mu_nevex, mu_n, degs=[6] * 4)
+    x, y = to_host(a), to_host(b)
+    assert np.max(np.abs(ham.apply_k_conj(x) - y)) <= 1e-11 * np.max(np.abs(y))
+
+
+def _search_block(prob, kh, seed=0):
+    rng = np.random.default_rng(seed)
+    mu1, mu_nevex, mu_n = _mus(prob)
+    W = osolver.init_block(complex_normal(rng, (prob.n, kh)), 1e-3)
+    W = chebyshev.chebyshev_filter(prob.A, prob.B, W, 6, mu1, mu_nevex, mu_n)
+    return np.concatenate([W, ham.apply_k_conj(W)], axis=1)
+
+
+@pytest.mark.parametrize("kh", [3, 20])
+def test_qr(prob, solver, kh):
+    print_case("qr", m=prob.m, k=2 * kh)
+    X = _search_block(prob, kh)
+    Xd = to_dev(X)
+    R, shifted = solver.qr(Xd)
+    Q, R = to_host(Xd), to_host(R)
+    Qr, Rr, sh = oqr.cholqr2(X)
+    assert not shifted and not sh
+    k = X.shape[1]
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(k))) < 1e-12
+    assert np.max(np.abs(Q @ R - X)) < 1e-12 * np.max(np.abs(X))
+    assert np.max(np.abs(np.tril(R, -1))) == 0.0
+    assert np.allclose(np.diag(R).imag, 0) and np.all(np.diag(R).real > 0)
+    assert np.max(np.abs(Q - Qr)) < 1e-9
+    assert np.max(np.abs(R - Rr)) < 1e-9 * np.max(np.abs(Rr))
+
+
+def test_qr_shifted_fallback(solver, prob):
+    print_case("qr_shifted", m=prob.m)
+    rng = np.random.default_rng(1)
+    n, k = prob.n, 24
+    U, _ = np.linalg.qr(complex_normal(rng, (n, k)))
+    Vh, _ = np.linalg.qr(complex_normal(rng, (k, k)))
+    X = (U * np.logspace(0, -13, k)[None, :]) @ Vh.conj().T
+    Xd = to_dev(X)
+    R, shifted = solver.qr(Xd)
+    Q, R = to_host(Xd), to_host(R)
+    assert shifted
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(k))) < 1e-12
+    assert np.max(np.abs(Q @ R - X)) < 1e-12
+
+
+@pytest.mark.parametrize("kh", [2, 20])
+def test_oblique_rr_and_residuals(prob, solver, kh):
+    print_case("oblique_rr", m=prob.m, k=2 * kh)
+    X = _search_block(prob, kh, seed=5)
+    Q, _, _ = oqr.cholqr2(X)
+    lam_ref, Z_ref, T_ref = rayleigh_ritz.oblique_rr(prob.A, prob.B, Q)
+    Qd = to_dev(Q)
+    ritz, Z, T = solver.oblique_rr(Qd)
+    assert np.allclose(ritz, lam_ref, rtol=1e-11, atol=0)
+    assert np.max(np.abs(to_host(T) - T_ref)) < 1e-12 * np.max(np.abs(T_ref))
+    Vref = ores.back_transform(Q, Z_ref)
+    rref = ores.residual_norms(prob.A, prob.B, Vref, lam_ref)
+    V, res = solver.residuals(Qd, T, Z, ritz)
+    V = align_columns(to_host(V), Vref)
+    assert np.max(np.abs(V - Vref)) < 1e-8
+    assert np.allclose(res, rref, rtol=1e-6, atol=1e-12)
+    # Thm 4.5 consequence: the positive Ritz pairs satisfy the Galerkin
+    # condition with the dual basis S Q
+    Vh = to_host(solver.residuals(Qd, T, Z, ritz)[0])
+    R = ham.apply_h(prob.A, prob.B, Vh) - Vh * ritz[None, :]
+    assert np.max(np.abs(Q.conj().T @ ham.apply_s(R))) < 1e-11
+
+
+def test_rr_exact_invariant_subspace(prob, solver):
+    lam, Vp = dense.dense_ph_eig(prob.A, prob.B)
+    X = np.concatenate([Vp[:, :6], ham.apply_k_conj(Vp[:, :6])], axis=1)
+    Q, _, _ = oqr.cholqr2(X)
+    ritz, Z, T = solver.oblique_rr(to_dev(Q))
+    assert np.allclose(ritz, lam[:6], rtol=1e-12)
+
+
+def test_backward_matches_oracle(prob, solver):
+    from oracle import adjoint
+    lam, V = dense.smallest_positive(prob.A, prob.B, 7)
+    g = np.random.default_rng(2).standard_normal(7)
+    GA_ref, GB_ref = adjoint.eigval_grad(V, g)
+    GA, GB = solver.eigval_backward(to_dev(V), g)
+    GA, GB = to_host(GA), to_host(GB)
+    assert np.max(np.abs(GA - GA_ref)) < 1e-12 * np.max(np.abs(GA_ref))
+    assert np.max(np.abs(GB - GB_ref)) < 1e-12 * np.max(np.abs(GB_ref))
+
+
+# ------------------------------------------------------------ error paths
+def test_argument_errors(solver, prob):
+    X = to_dev(np.zeros((prob.n, 3)))
+    with pytest.raises(ChasePHError) as e:
+        solver.oblique_rr(X)          # odd k
+    assert e.value.status == _lib.ERR_ARG
+    W = to_dev(np.ones((prob.n, 3)))
+    with pytest.raises(ChasePHError) as e:
+        solver.filter(W, 1.0, 2.0, 5.0, degs=[3, 2, 4])   # not sorted
+    assert e.value.status == _lib.ERR_ARG
+    with pytest.raises(ChasePHError) as e:
+        solver.filter(W, 2.0, 1.0, 5.0)                   # mu order
+    assert e.value.status == _lib.ERR_ARG
+
+
+def test_not_definite_detected():
+    # SH indefinite: ||B||_2 = 2 min d.  A block containing an eigenvector of
+    # SH with a negative eigenvalue makes Q^H S H Q indefinite.
+    p = make_problem(64, lambda rng, mm: rng.uniform(1.0, 2.0, mm), 2.0, 2, 2, 4, 1e-8)
+    SH = ham.assemble_sh(p.A, p.B)
+    w, U = np.linalg.eigh(SH)
+    assert w[0] < 0
+    X = np.concatenate([U[:, :1], ham.apply_k_conj(U[:, :1])], axis=1)
+    Q, _, _ = oqr.cholqr2(X)
+    A, B = dev_blocks(p)
+    s = PHSolver(A, B, 2, 2)
+    with pytest.raises(ChasePHError) as e:
+        s.oblique_rr(to_dev(Q))
+    assert e.value.status == _lib.ERR_NOT_DEFINITE
+
+
+def test_singular_qsq_detected(prob, solver):
+    # S-neutral basis (Section 4.6): Q^H S Q = 0
+    m, k = prob.m, 4
+    Q = np.zeros((prob.n, k), dtype=np.complex128)
+    for j in range(k):
+        Q[j, j] = Q[m + j, j] = 1 / np.sqrt(2)
+    with pytest.raises(ChasePHError) as e:
+        solver.oblique_rr(to_dev(Q))
+    assert e.value.status == _lib.ERR_SINGULAR_QSQ
