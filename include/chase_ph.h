@@ -191,6 +191,22 @@ chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* 
  * number of apply_h kernel launches it contained. */
 chase_ph_status chase_ph_last_timing(chase_ph_t h, double* ms, int32_t* launches);
 
+/* Per-launch timing of the H X kernels, for roofline reporting.  With
+ * enable = 1 every subsequent apply_h kernel launch on this handle (stage
+ * calls, the filter, Lanczos and the Rayleigh-Ritz product inside solve) is
+ * bracketed by a pair of HIP events on the handle's stream; enable = 0 stops
+ * recording.  Either call resets the counters.  At most 65536 launches are
+ * recorded per enable. */
+chase_ph_status chase_ph_profile(chase_ph_t h, int32_t enable);
+
+/* Sum over the recorded launches of precision prec (CHASE_PH_FP64 or
+ * CHASE_PH_FP32) of: kernel time (ms, from the event pairs), algorithmic
+ * flops (8 n^2 per column) and algorithmic HBM bytes (A and B read once,
+ * X read once, Y written once, P and Q read once if present).
+ * Synchronises the stream. */
+chase_ph_status chase_ph_profile_read(chase_ph_t h, int32_t prec, double* total_ms, double* flops,
+                                      double* bytes, int32_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,14 @@ struct chase_ph_s {
   std::string err;
   bool dead = false;
   std::vector<void*> allocs;
+  // apply_h launch profiling (chase_ph_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  struct Launch {
+    int prec;
+    double flops, bytes;
+  };
+  std::vector<Launch> launches;
 };
 
 namespace {
@@ -122,6 +130,30 @@ Err ensure_shadow(chase_ph_t h) {
   return make_shadow(h->A, h->B, h->ld, h->p.a_conj, h->A32, h->B32, h->ld32, h->m, h->st);
 }
 
+constexpr size_t PROF_MAX = 65536;
+
+Err prof_begin(chase_ph_t h) {
+  if (!h->prof || h->launches.size() >= PROF_MAX) return ok();
+  const size_t i = 2 * h->launches.size();
+  while (h->evpool.size() < i + 2) {
+    hipEvent_t e;
+    CHASE_HIP(hipEventCreate(&e));
+    h->evpool.push_back(e);
+  }
+  CHASE_HIP(hipEventRecord(h->evpool[i], h->st));
+  return ok();
+}
+
+Err prof_end(chase_ph_t h, int prec, int k, size_t elem, bool has_p, bool has_q) {
+  if (!h->prof || h->launches.size() >= PROF_MAX) return ok();
+  const size_t i = 2 * h->launches.size();
+  CHASE_HIP(hipEventRecord(h->evpool[i + 1], h->st));
+  const double n = (double)h->n, m = (double)h->m;
+  const double bytes = (2.0 * m * m + (2.0 + (has_p ? 1 : 0) + (has_q ? 1 : 0)) * n * k) * elem;
+  h->launches.push_back({prec, 8.0 * n * n * k, bytes});
+  return ok();
+}
+
 // Y = alpha H X + beta P + gamma Q on k columns
 Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ldy, double alpha = 1,
             const c128* P = nullptr, int64_t ldp = 0, double beta = 0, const c128* Q = nullptr, int64_t ldq = 0,
@@ -130,7 +162,10 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
   a.A = h->A; a.B = h->B; a.lda = h->ld; a.a_conj = h->p.a_conj; a.m = h->m; a.k = k;
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
-  return launch_apply_h_f64(a, h->st);
+  if (k <= 0) return ok();
+  CHASE_TRY(prof_begin(h));
+  CHASE_TRY(launch_apply_h_f64(a, h->st));
+  return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr);
 }
 
 Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy, float alpha = 1,
@@ -140,7 +175,10 @@ Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy,
   a.A = h->A32; a.B = h->B32; a.lda = h->ld32; a.a_conj = 0; a.m = h->m; a.k = k;
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
-  return launch_apply_h_f32(a, h->st);
+  if (k <= 0) return ok();
+  CHASE_TRY(prof_begin(h));
+  CHASE_TRY(launch_apply_h_f32(a, h->st));
+  return prof_end(h, CHASE_PH_FP32, k, sizeof(c64), P != nullptr, Q != nullptr);
 }
 
 // Scaled Chebyshev recurrence on H^2 (eq. 4.1, Zhou-Saad scaling); see
@@ -573,7 +611,8 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     }
     const int wanted_left = nev - locked;
     locked += nlock;
-    mu_nevex = ritz[kw - 1];  // largest non-converged positive Ritz value (Section 4.1)
+    // largest non-converged positive Ritz value; the interval only narrows (Section 4.1)
+    mu_nevex = std::min(mu_nevex, ritz[kw - 1]);
     inf.iterations = it + 1;
     if (locked >= nev) {
       *converged = true;
@@ -775,6 +814,7 @@ chase_ph_status chase_ph_destroy(chase_ph_t h) {
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
   for (void* q : h->allocs) (void)hipFree(q);
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->e0) (void)hipEventDestroy(h->e0);
   if (h->e1) (void)hipEventDestroy(h->e1);
   delete h;
@@ -878,6 +918,36 @@ chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* 
   if (nev <= 0 || !dV || !hG || !dGA || !dGB || ldv < h->n || ldg < h->m)
     return finish(h, fail(CHASE_PH_ERR_ARG, "eigval_backward: bad arguments"));
   return finish(h, backward_impl(h, nev, (const c128*)dV, ldv, hG, (c128*)dGA, (c128*)dGB, ldg));
+}
+
+chase_ph_status chase_ph_profile(chase_ph_t h, int32_t enable) {
+  CHECK_HANDLE(h);
+  h->prof = enable != 0;
+  h->launches.clear();
+  return CHASE_PH_OK;
+}
+
+chase_ph_status chase_ph_profile_read(chase_ph_t h, int32_t prec, double* total_ms, double* flops, double* bytes,
+                                      int32_t* launches) {
+  CHECK_HANDLE(h);
+  if (hipStreamSynchronize(h->st) != hipSuccess) return finish(h, fail(CHASE_PH_ERR_HIP, "profile_read: sync"));
+  double ms = 0, fl = 0, by = 0;
+  int cnt = 0;
+  for (size_t i = 0; i < h->launches.size(); ++i) {
+    if (h->launches[i].prec != prec) continue;
+    float t = 0;
+    if (hipEventElapsedTime(&t, h->evpool[2 * i], h->evpool[2 * i + 1]) != hipSuccess)
+      return finish(h, fail(CHASE_PH_ERR_HIP, "profile_read: elapsed time"));
+    ms += t;
+    fl += h->launches[i].flops;
+    by += h->launches[i].bytes;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = ms;
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  if (launches) *launches = cnt;
+  return CHASE_PH_OK;
 }
 
 chase_ph_status chase_ph_last_timing(chase_ph_t h, double* ms, int32_t* launches) {

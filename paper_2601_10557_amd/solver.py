@@ -145,6 +145,17 @@ class PHSolver:
         lib().chase_ph_last_timing(self._h, C.byref(ms), C.byref(n))
         return ms.value, n.value
 
+    def profile(self, enable: bool = True):
+        """Bracket every apply_h launch with HIP events (resets counters)."""
+        self._check(lib().chase_ph_profile(self._h, int(enable)))
+
+    def profile_read(self, prec: int):
+        """(total_ms, flops, bytes, launches) of the recorded apply_h launches."""
+        ms, fl, by, n = C.c_double(), C.c_double(), C.c_double(), C.c_int32()
+        self._check(lib().chase_ph_profile_read(self._h, prec, C.byref(ms), C.byref(fl), C.byref(by),
+                                                C.byref(n)))
+        return ms.value, fl.value, by.value, n.value
+
     # ---------------------------------------------------------------- stages
     def apply_h(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, prec: int = _lib.FP64):
         """Y = H X; X is n x k (c128 for FP64, c64 for FP32)."""
