@@ -164,7 +164,7 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
-  CHASE_TRY(launch_apply_h_f64(a, h->st));
+  CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st));
   return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr);
 }
 
@@ -177,7 +177,7 @@ Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy,
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
-  CHASE_TRY(launch_apply_h_f32(a, h->st));
+  CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st));
   return prof_end(h, CHASE_PH_FP32, k, sizeof(c64), P != nullptr, Q != nullptr);
 }
 
@@ -762,7 +762,10 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, &h->dws.U, (size_t)h->kp * 64));
   CHASE_TRY(dalloc(h, &h->dws.flag, 4));
   CHASE_TRY(dalloc(h, &h->dws.dscalar, 4));
-  h->ws_bytes = std::min<size_t>((size_t)256 << 20, std::max<size_t>((size_t)16 << 20, kp2 * sizeof(c128) * 8));
+  // zgemm split-K partials (up to 8 k x k blocks) and apply_h split-K
+  // partials (up to 8 x m x 2 nevex complex), within [16 MiB, 1 GiB]
+  h->ws_bytes = std::max(kp2 * sizeof(c128) * 8, (size_t)8 * h->m * h->kmax * sizeof(c128));
+  h->ws_bytes = std::min<size_t>((size_t)1 << 30, std::max<size_t>((size_t)16 << 20, h->ws_bytes));
   CHASE_TRY(dalloc(h, (char**)&h->ws, h->ws_bytes));
   if (p->precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
   return ok();

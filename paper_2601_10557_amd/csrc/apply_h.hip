@@ -13,13 +13,22 @@
 //
 // Complex products run on real MFMA tiles: Re += Ar Br - Ai Bi,
 // Im += Ar Bi + Ai Br (four MFMAs per complex k-slice, two accumulators).
-//   c64 : v_mfma_f32_32x32x2_f32, block tile 128 x 128, 4 waves of 64 x 64
-//   c128: v_mfma_f64_16x16x4_f64, block tile 128 x 64,  4 waves of 64 x 32
-// Tiles of the operand strip are staged through LDS (double buffered, split
-// real/imaginary planes, k-major so MFMA fragment reads are unit-stride).
+//   c64 : v_mfma_f32_32x32x2_f32, waves of 64 x 64 outputs
+//   c128: v_mfma_f64_16x16x4_f64, waves of 64 x 32 outputs
+// Operand tiles are staged through LDS (double buffered, split real and
+// imaginary planes, k-major so MFMA fragment reads are unit-stride).  Global
+// loads are branch-free (clamped address + select) so that a whole tile is in
+// flight at once while the MFMAs of the previous tile run.
+//
 // Tile order is XCD-aware: workgroups dispatched to the same XCD take
-// consecutive tiles along N, i.e. they share one row strip of [A B] in that
-// XCD's L2.
+// consecutive tiles along N of one K range, i.e. they share one row strip of
+// [A B] in that XCD's L2.  When the tile grid alone cannot fill the 256 CUs
+// the K range is split; partial products go to a workspace and a second
+// kernel sums them in a fixed order and applies the fused epilogue.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace chase {
@@ -53,34 +62,38 @@ struct TF64 {
   }
 };
 
-// 16-byte vector of the complex type: two c64 or one c128.
-template <typename R>
-struct Vec16;
+// Raw 16- or 8-byte vectors of V consecutive complex elements: loaded in
+// one instruction, consumed only when the tile is written to LDS (after the
+// MFMAs of the previous tile), so the loads stay in flight meanwhile.
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+template <typename R, int V>
+struct Raw;
 template <>
-struct Vec16<float> {
-  static constexpr int N = 2;
+struct Raw<float, 2> {
   using T = floatx4;
 };
 template <>
-struct Vec16<double> {
-  static constexpr int N = 1;
-  using T = doublex4;  // unused for loads; c128 is itself 16 bytes
+struct Raw<float, 1> {
+  using T = floatx2;
+};
+template <>
+struct Raw<double, 1> {
+  using T = doublex2;
 };
 
-template <typename Tr, int BM, int BN, int BK, int WGM, int WGN>
+template <typename Tr, int BM, int BN, int BK, int WGM, int WGN, int VB>
 struct Cfg {
   using R = typename Tr::R;
-  using C = typename Tr::C;
   static constexpr int NT = 64 * WGM * WGN;
   static constexpr int WTM = BM / WGM, WTN = BN / WGN;
   static constexpr int FM = WTM / Tr::MB, FN = WTN / Tr::NB;
-  static constexpr int VEC = Vec16<R>::N;            // complex per 16-byte A load
-  static constexpr int ACHUNK = BM * BK / VEC / NT;  // A loads per thread
-  static constexpr int BELEM = BK * BN / NT;         // B loads per thread
-  static constexpr int PADA = 4, PADB = 4;
-  static constexpr int LDA_S = BM + PADA, LDB_S = BN + PADB;
+  static constexpr int VEC = sizeof(R) == 4 ? 2 : 1;   // complex per A load
+  static constexpr int ACHUNK = BM * BK / VEC / NT;     // A loads per thread
+  static constexpr int BCHUNK = BK * BN / VB / NT;      // B loads per thread
+  static constexpr int LDA_S = BM + 4, LDB_S = BN + 4;
   static_assert(BM * BK % (VEC * NT) == 0, "A tile split");
-  static_assert(BK * BN % NT == 0, "B tile split");
+  static_assert(BK * BN % (VB * NT) == 0, "B tile split");
   static_assert(BK % Tr::KB == 0, "BK");
   static_assert(WTM % Tr::MB == 0 && WTN % Tr::NB == 0, "wave tile");
 };
@@ -93,12 +106,40 @@ __device__ __forceinline__ int xcd_remap(int w, int T) {
   return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
-template <typename Tr, int BM, int BN, int BK, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs<typename Tr::R> a) {
-  using CF = Cfg<Tr, BM, BN, BK, WGM, WGN>;
+template <typename R, typename C>
+__device__ __forceinline__ void epilogue_store(const ApplyHArgs<R>& a, int gr, int gc, R hr, R hi) {
+  int64_t orow = gr;
+  int ocol = gc;
+  if (gc >= a.k) {  // bottom half: -conj(R)
+    hr = -hr;
+    orow += a.m;
+    ocol -= a.k;
+  }
+  R yr = a.alpha * hr, yi = a.alpha * hi;
+  if (a.P) {
+    const C p = a.P[(int64_t)ocol * a.ldp + orow];
+    yr += a.beta * p.re;
+    yi += a.beta * p.im;
+  }
+  if (a.Q) {
+    const C q = a.Q[(int64_t)ocol * a.ldq + orow];
+    yr += a.gamma * q.re;
+    yi += a.gamma * q.im;
+  }
+  C out;
+  out.re = yr;
+  out.im = yi;
+  a.Y[(int64_t)ocol * a.ldy + orow] = out;
+}
+
+template <typename Tr, int BM, int BN, int BK, int WGM, int WGN, int VB>
+__global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs<typename Tr::R> a, int splits,
+                                                                 int kps, typename Tr::C* ws) {
+  using CF = Cfg<Tr, BM, BN, BK, WGM, WGN, VB>;
   using R = typename Tr::R;
   using C = typename Tr::C;
   constexpr int NT = CF::NT;
+  constexpr int VEC = CF::VEC;
 
   __shared__ R As[2][2][BK][CF::LDA_S];
   __shared__ R Bs[2][2][BK][CF::LDB_S];
@@ -108,100 +149,96 @@ __global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs
   const int N2 = 2 * kc;
   const int TM = (m + BM - 1) / BM;
   const int TN = (N2 + BN - 1) / BN;
+  const int T = TM * TN;
   const int tid = threadIdx.x;
-  const int nid = xcd_remap(blockIdx.x, TM * TN);
-  const int m0 = (nid / TN) * BM;
-  const int n0 = (nid % TN) * BN;
+  const int nid = xcd_remap(blockIdx.x, T * splits);
+  const int sp = nid / T;
+  const int t = nid - sp * T;
+  const int m0 = (t / TN) * BM;
+  const int n0 = (t % TN) * BN;
   const int nkt = (m + BK - 1) / BK;
-  const int KT = 2 * nkt;
+  const int kt_beg = sp * kps;
+  const int kt_end = min(2 * nkt, kt_beg + kps);
 
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm0 = (wave / WGN) * CF::WTM;
   const int wn0 = (wave % WGN) * CF::WTN;
 
-  // prefetch registers
-  R ar[CF::ACHUNK][CF::VEC], ai[CF::ACHUNK][CF::VEC];
-  R br[CF::BELEM], bi[CF::BELEM];
+  // prefetch registers: raw vectors plus validity bits
+  using RawA = typename Raw<R, VEC>::T;
+  using RawB = typename Raw<R, VB>::T;
+  RawA ra[CF::ACHUNK];
+  RawB rb[CF::BCHUNK];
+  unsigned mask_a = 0, mask_b = 0, bot_b = 0;  // bit per (chunk, element)
+  static_assert(CF::ACHUNK * VEC <= 32 && CF::BCHUNK * VB <= 32, "mask width");
 
   auto load_tiles = [&](int kt) {
     const int phase = kt >= nkt;
     const int kk0 = (kt - phase * nkt) * BK;
     const C* Mat = phase ? a.B : a.A;
+    mask_a = 0;
+    mask_b = 0;
+    bot_b = 0;
+#pragma unroll
+    for (int c = 0; c < CF::ACHUNK; ++c) {
+      const int ch = tid + c * NT;
+      const int kk = ch / (BM / VEC);
+      const int r = (ch % (BM / VEC)) * VEC;
+      const int gr = m0 + r, gk = kk0 + kk;
+      const bool okk = gk < m;
+      const int64_t idx = (okk && gr < m) ? (int64_t)gk * a.lda + gr : 0;
+      ra[c] = *reinterpret_cast<const RawA*>(Mat + idx);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+        if (okk && gr + v < m) mask_a |= 1u << (c * VEC + v);
+    }
+#pragma unroll
+    for (int e = 0; e < CF::BCHUNK; ++e) {
+      const int el = tid + e * NT;
+      const int j = el / (BK / VB);
+      const int kk = (el % (BK / VB)) * VB;
+      const int gj = n0 + j, gk = kk0 + kk;
+      const bool ok = gj < N2 && gk < m;
+      const bool bot = gj >= kc;
+      const int64_t col = bot ? gj - kc : gj;
+      const int64_t row = (int64_t)(bot ? 1 - phase : phase) * m + gk;
+      const int64_t idx = ok ? col * a.ldx + row : 0;
+      rb[e] = *reinterpret_cast<const RawB*>(a.X + idx);
+#pragma unroll
+      for (int v = 0; v < VB; ++v)
+        if (ok && gk + v < m) mask_b |= 1u << (e * VB + v);
+      if (bot) bot_b |= 1u << e;
+    }
+  };
+
+  auto store_tiles = [&](int buf, int kt) {
+    const int phase = kt >= nkt;
     const R csgn = (!phase && a.a_conj) ? R(-1) : R(1);
 #pragma unroll
     for (int c = 0; c < CF::ACHUNK; ++c) {
       const int ch = tid + c * NT;
-      const int kk = ch / (BM / CF::VEC);
-      const int r = (ch % (BM / CF::VEC)) * CF::VEC;
-      const int gr = m0 + r, gk = kk0 + kk;
-      const C* src = Mat + (int64_t)gk * a.lda + gr;
-      if (gk < m && gr + CF::VEC <= m) {
-        if constexpr (CF::VEC == 2) {
-          floatx4 v = *reinterpret_cast<const floatx4*>(src);
-          ar[c][0] = v[0];
-          ai[c][0] = v[1] * csgn;
-          ar[c][1] = v[2];
-          ai[c][1] = v[3] * csgn;
-        } else {
-          C v = src[0];
-          ar[c][0] = v.re;
-          ai[c][0] = v.im * csgn;
-        }
-      } else {
+      const int kk = ch / (BM / VEC);
+      const int r = (ch % (BM / VEC)) * VEC;
 #pragma unroll
-        for (int v = 0; v < CF::VEC; ++v) {
-          if (gk < m && gr + v < m) {
-            C z = src[v];
-            ar[c][v] = z.re;
-            ai[c][v] = z.im * csgn;
-          } else {
-            ar[c][v] = R(0);
-            ai[c][v] = R(0);
-          }
-        }
+      for (int v = 0; v < VEC; ++v) {
+        const bool okv = (mask_a >> (c * VEC + v)) & 1u;
+        As[buf][0][kk][r + v] = okv ? ra[c][2 * v] : R(0);
+        As[buf][1][kk][r + v] = okv ? ra[c][2 * v + 1] * csgn : R(0);
       }
     }
 #pragma unroll
-    for (int e = 0; e < CF::BELEM; ++e) {
+    for (int e = 0; e < CF::BCHUNK; ++e) {
       const int el = tid + e * NT;
-      const int j = el / BK, kk = el % BK;
-      const int gj = n0 + j, gk = kk0 + kk;
-      R vr = R(0), vi = R(0);
-      if (gj < N2 && gk < m) {
-        if (gj < kc) {
-          C z = a.X[(int64_t)gj * a.ldx + (int64_t)phase * m + gk];
-          vr = z.re;
-          vi = z.im;
-        } else {
-          C z = a.X[(int64_t)(gj - kc) * a.ldx + (int64_t)(1 - phase) * m + gk];
-          vr = z.re;
-          vi = -z.im;
-        }
+      const int j = el / (BK / VB);
+      const int kk = (el % (BK / VB)) * VB;
+      const R isgn = ((bot_b >> e) & 1u) ? R(-1) : R(1);
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        const bool okv = (mask_b >> (e * VB + v)) & 1u;
+        Bs[buf][0][kk + v][j] = okv ? rb[e][2 * v] : R(0);
+        Bs[buf][1][kk + v][j] = okv ? rb[e][2 * v + 1] * isgn : R(0);
       }
-      br[e] = vr;
-      bi[e] = vi;
-    }
-  };
-
-  auto store_tiles = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < CF::ACHUNK; ++c) {
-      const int ch = tid + c * NT;
-      const int kk = ch / (BM / CF::VEC);
-      const int r = (ch % (BM / CF::VEC)) * CF::VEC;
-#pragma unroll
-      for (int v = 0; v < CF::VEC; ++v) {
-        As[buf][0][kk][r + v] = ar[c][v];
-        As[buf][1][kk][r + v] = ai[c][v];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < CF::BELEM; ++e) {
-      const int el = tid + e * NT;
-      const int j = el / BK, kk = el % BK;
-      Bs[buf][0][kk][j] = br[e];
-      Bs[buf][1][kk][j] = bi[e];
     }
   };
 
@@ -216,14 +253,16 @@ __global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs
         acci[i][j][r] = R(0);
       }
 
-  load_tiles(0);
-  store_tiles(0);
+  if (kt_beg < kt_end) {
+    load_tiles(kt_beg);
+    store_tiles(0, kt_beg);
+  }
   __syncthreads();
 
   const int ak = Tr::a_k(lane), arow = Tr::a_row(lane);
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < KT) load_tiles(kt + 1);
+  for (int kt = kt_beg; kt < kt_end; ++kt) {
+    const int buf = (kt - kt_beg) & 1;
+    if (kt + 1 < kt_end) load_tiles(kt + 1);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += Tr::KB) {
       R fa_r[CF::FM], fa_i[CF::FM], fb_r[CF::FN], fb_i[CF::FN], fb_n[CF::FN];
@@ -253,12 +292,12 @@ __global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs
           acci[i][j] = Tr::mfma(fa_i[i], fb_r[j], acci[i][j]);
         }
     }
-    if (kt + 1 < KT) store_tiles(buf ^ 1);
+    if (kt + 1 < kt_end) store_tiles(buf ^ 1, kt + 1);
     __syncthreads();
   }
 
-  // epilogue: Y = alpha (H X) + beta P + gamma Q
   const int ccol = Tr::acc_col(lane);
+  C* wsp = ws + (int64_t)sp * m * N2;
 #pragma unroll
   for (int i = 0; i < CF::FM; ++i)
 #pragma unroll
@@ -268,51 +307,121 @@ __global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs
         const int gr = m0 + wm0 + i * Tr::MB + Tr::acc_row(r, lane);
         const int gc = n0 + wn0 + j * Tr::NB + ccol;
         if (gr < m && gc < N2) {
-          R hr = accr[i][j][r], hi = acci[i][j][r];
-          int64_t orow = gr;
-          int ocol = gc;
-          if (gc >= kc) {  // bottom half: -conj(R)
-            hr = -hr;
-            orow += m;
-            ocol -= kc;
+          if (splits > 1) {
+            C z;
+            z.re = accr[i][j][r];
+            z.im = acci[i][j][r];
+            wsp[(int64_t)gc * m + gr] = z;
+          } else {
+            epilogue_store<R, C>(a, gr, gc, accr[i][j][r], acci[i][j][r]);
           }
-          R yr = a.alpha * hr, yi = a.alpha * hi;
-          if (a.P) {
-            C p = a.P[(int64_t)ocol * a.ldp + orow];
-            yr += a.beta * p.re;
-            yi += a.beta * p.im;
-          }
-          if (a.Q) {
-            C q = a.Q[(int64_t)ocol * a.ldq + orow];
-            yr += a.gamma * q.re;
-            yi += a.gamma * q.im;
-          }
-          C out;
-          out.re = yr;
-          out.im = yi;
-          a.Y[(int64_t)ocol * a.ldy + orow] = out;
         }
       }
 }
 
-}  // namespace
+// Sum the split-K partials in a fixed order and apply the epilogue.
+template <typename R, typename C>
+__global__ void apply_h_reduce(const ApplyHArgs<R> a, int splits, const C* ws) {
+  const int m = (int)a.m;
+  const int64_t total = (int64_t)m * 2 * a.k;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int gc = (int)(t / m), gr = (int)(t % m);
+    R sr = 0, si = 0;
+    for (int s = 0; s < splits; ++s) {
+      const C z = ws[(int64_t)s * total + t];
+      sr += z.re;
+      si += z.im;
+    }
+    epilogue_store<R, C>(a, gr, gc, sr, si);
+  }
+}
 
-Err launch_apply_h_f32(const ApplyHArgs<float>& a, hipStream_t s) {
-  if (a.k <= 0 || a.m <= 0) return ok();
-  constexpr int BM = 128, BN = 128, BK = 16;
-  const int64_t tiles = ceil_div(a.m, BM) * ceil_div(2 * (int64_t)a.k, BN);
-  hipLaunchKernelGGL((apply_h_kernel<TF32, BM, BN, BK, 2, 2>), dim3((unsigned)tiles), dim3(256), 0, s, a);
+struct Plan {
+  int cfg, splits, kps;
+  int64_t tiles;
+};
+
+// Pick the tile shape and K split that minimise (rounds of 256 workgroups)
+// x (K slabs per workgroup) x (outputs per tile), with a mild preference for
+// fewer splits (each split costs a partial-sum write and read).
+template <int NCFG>
+Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG], const int (&bk)[NCFG],
+               size_t elem, size_t ws_bytes) {
+  const int64_t slots = 256;
+  Plan best{0, 1, 1, 0};
+  double best_cost = 1e300;
+  for (int c = 0; c < NCFG; ++c) {
+    const int64_t kt = 2 * ceil_div(m, bk[c]);
+    const int64_t tiles = ceil_div(m, bm[c]) * ceil_div(n2, bn[c]);
+    for (int s = 1; s <= 16; ++s) {
+      if (s > 1 && (size_t)s * m * n2 * elem > ws_bytes) break;
+      const int64_t kps = ceil_div(kt, s);
+      const int64_t real_s = ceil_div(kt, kps);
+      const int64_t rounds = ceil_div(tiles * real_s, slots);
+      const double cost = (double)rounds * kps * bk[c] * bm[c] * bn[c] * (1.0 + 0.02 * (real_s - 1));
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        best = Plan{c, (int)real_s, (int)kps, tiles};
+      }
+    }
+  }
+  return best;
+}
+
+template <typename Tr, int BM, int BN, int BK, int WGM, int WGN, int VB>
+Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hipStream_t s) {
+  using C = typename Tr::C;
+  const int64_t grid = p.tiles * p.splits;
+  hipLaunchKernelGGL((apply_h_kernel<Tr, BM, BN, BK, WGM, WGN, VB>), dim3((unsigned)grid), dim3(64 * WGM * WGN), 0, s,
+                     a, p.splits, p.kps, (C*)ws);
   CHASE_LAUNCH_CHECK();
+  if (p.splits > 1) {
+    const int64_t total = a.m * 2 * (int64_t)a.k;
+    const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 8192);
+    hipLaunchKernelGGL((apply_h_reduce<typename Tr::R, C>), dim3(blocks), dim3(256), 0, s, a, p.splits, (const C*)ws);
+    CHASE_LAUNCH_CHECK();
+  }
   return ok();
 }
 
-Err launch_apply_h_f64(const ApplyHArgs<double>& a, hipStream_t s) {
+// CHASE_PH_APPLY_PLAN="cfg,splits" forces a tile shape and K split (tuning aid).
+template <int NCFG>
+void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG],
+                   const int (&bk)[NCFG], size_t elem, size_t ws_bytes) {
+  const char* e = std::getenv("CHASE_PH_APPLY_PLAN");
+  if (!e) return;
+  int c = 0, s = 1;
+  if (std::sscanf(e, "%d,%d", &c, &s) != 2 || c < 0 || c >= NCFG || s < 1) return;
+  const int64_t kt = 2 * ceil_div(m, bk[c]);
+  if (s > 1 && (size_t)s * m * n2 * elem > ws_bytes) return;
+  p.cfg = c;
+  p.kps = (int)ceil_div(kt, s);
+  p.splits = (int)ceil_div(kt, p.kps);
+  p.tiles = ceil_div(m, bm[c]) * ceil_div(n2, bn[c]);
+}
+
+}  // namespace
+
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
-  constexpr int BM = 128, BN = 64, BK = 16;
-  const int64_t tiles = ceil_div(a.m, BM) * ceil_div(2 * (int64_t)a.k, BN);
-  hipLaunchKernelGGL((apply_h_kernel<TF64, BM, BN, BK, 2, 2>), dim3((unsigned)tiles), dim3(256), 0, s, a);
-  CHASE_LAUNCH_CHECK();
-  return ok();
+  static const int bm[2] = {128, 256}, bn[2] = {128, 64}, bk[2] = {32, 16};
+  const size_t wsb = ws ? ws_bytes : 0;
+  Plan p = make_plan<2>(a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  plan_override<2>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  const bool vb2 = (a.m % 2 == 0) && (a.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0);
+  if (p.cfg == 0)
+    return vb2 ? launch_cfg<TF32, 128, 128, 32, 2, 2, 2>(a, p, ws, s) : launch_cfg<TF32, 128, 128, 32, 2, 2, 1>(a, p, ws, s);
+  return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s) : launch_cfg<TF32, 256, 64, 16, 4, 1, 1>(a, p, ws, s);
+}
+
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (a.k <= 0 || a.m <= 0) return ok();
+  static const int bm[2] = {128, 256}, bn[2] = {64, 32}, bk[2] = {16, 16};
+  const size_t wsb = ws ? ws_bytes : 0;
+  Plan p = make_plan<2>(a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
+  plan_override<2>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
+  if (p.cfg == 0) return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
+  return launch_cfg<TF64, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
 }
 
 }  // namespace chase

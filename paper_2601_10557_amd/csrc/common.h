@@ -96,8 +96,10 @@ struct ApplyHArgs {
   R alpha, beta, gamma;
 };
 
-Err launch_apply_h_f32(const ApplyHArgs<float>& a, hipStream_t s);
-Err launch_apply_h_f64(const ApplyHArgs<double>& a, hipStream_t s);
+// ws: device workspace for split-K partial products (ws_bytes may be 0:
+// then the K range is never split).
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s);
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Generic complex FP64 GEMM (zgemm.hip):
