@@ -500,18 +500,29 @@ Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, doubl
   return ok();
 }
 
+// Phase timer on its own event pair (the stage calls it brackets record
+// the handle's e0/e1 for chase_ph_last_timing).
 struct Timer {
   chase_ph_t h;
+  hipEvent_t a = nullptr, b = nullptr;
   explicit Timer(chase_ph_t hh) : h(hh) {}
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
   Err start() {
-    CHASE_HIP(hipEventRecord(h->e0, h->st));
+    if (!a) {
+      CHASE_HIP(hipEventCreate(&a));
+      CHASE_HIP(hipEventCreate(&b));
+    }
+    CHASE_HIP(hipEventRecord(a, h->st));
     return ok();
   }
   Err stop(double* acc) {
-    CHASE_HIP(hipEventRecord(h->e1, h->st));
-    CHASE_HIP(hipEventSynchronize(h->e1));
+    CHASE_HIP(hipEventRecord(b, h->st));
+    CHASE_HIP(hipEventSynchronize(b));
     float ms = 0;
-    CHASE_HIP(hipEventElapsedTime(&ms, h->e0, h->e1));
+    CHASE_HIP(hipEventElapsedTime(&ms, a, b));
     *acc += ms * 1e-3;
     return ok();
   }
@@ -548,30 +559,42 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       !(mu_n > mu_nevex))
     return fail(CHASE_PH_ERR_NOT_DEFINITE, "Lanczos spectral estimates invalid (SH not positive definite?)");
   const double switch_tol = p.switch_tol > 0 ? p.switch_tol : 1e-5 * mu_n;
-  bool fp64_filter = p.precision != CHASE_PH_MIXED;
-  if (p.precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
+  const bool mixed = p.precision == CHASE_PH_MIXED;
+  if (mixed) CHASE_TRY(ensure_shadow(h));
 
   int locked = 0;
   std::vector<double> lam_locked, res_locked;
   std::vector<int> degs(nevex, p.deg);
   std::vector<double> ritz(nevex), res(nevex);
+  // per Ritz index (ascending order of the current search block): filter
+  // precision and the residual of the previous iteration
+  std::vector<char> st64(nevex, mixed ? 0 : 1);
+  std::vector<double> prev_res(nevex, 1e300);
+  int n64 = mixed ? 0 : nevex;  // the first n64 columns of W are filtered in FP64
   int hist_pos = 0;
   *converged = false;
   for (int it = 0; it < p.max_iter; ++it) {
     const int kw = nevex - locked;
-    // filter the positive half (Alg. 3; Thm 4.2)
+    // filter the positive half (Alg. 3; Thm 4.2): columns [0, n64) in c128,
+    // columns [n64, kw) in c64
     double fl = 0;
     CHASE_TRY(tm.start());
-    if (fp64_filter) {
-      CHASE_TRY(filter_any(h, kw, h->Wk, n, degs, mu1, mu_nevex, mu_n, CHASE_PH_FP64, &fl));
-    } else {
-      CHASE_TRY(convert_to_c64(h->Wk, n, h->W32, n, n, kw, h->st));
-      CHASE_TRY(filter_any(h, kw, h->W32, n, degs, mu1, mu_nevex, mu_n, CHASE_PH_FP32, &fl));
-      CHASE_TRY(convert_to_c128(h->W32, n, h->Wk, n, n, kw, h->st));
+    if (n64 > 0) {
+      std::vector<int> d64(degs.begin(), degs.begin() + n64);
+      CHASE_TRY(filter_any(h, n64, h->Wk, n, d64, mu1, mu_nevex, mu_n, CHASE_PH_FP64, &fl));
+      inf.filter_flops += fl;
+      if (inf.switch_iter < 0) inf.switch_iter = it;
+    }
+    if (n64 < kw) {
+      const int k32 = kw - n64;
+      std::vector<int> d32(degs.begin() + n64, degs.begin() + kw);
+      CHASE_TRY(convert_to_c64(h->Wk + (int64_t)n64 * n, n, h->W32, n, n, k32, h->st));
+      CHASE_TRY(filter_any(h, k32, h->W32, n, d32, mu1, mu_nevex, mu_n, CHASE_PH_FP32, &fl));
+      CHASE_TRY(convert_to_c128(h->W32, n, h->Wk + (int64_t)n64 * n, n, n, k32, h->st));
       inf.filter_flops_fp32 += fl;
+      inf.filter_flops += fl;
     }
     CHASE_TRY(tm.stop(&inf.t_filter));
-    inf.filter_flops += fl;
     // assemble [S Y+, S K conj(Y+), W+, K conj(W+)] and orthonormalise (eq. 4.5)
     const int kx = 2 * nevex;
     CHASE_TRY(tm.start());
@@ -606,10 +629,10 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       res_locked.push_back(res[i]);
     }
     if (verbose) {
-      std::fprintf(stderr, "[chase_ph] it=%d locked=%d kw=%d prec=%s nlock=%d ritz[0]=%.12g res[0]=%.3e res[kw-1]=%.3e mu_nevex=%.6g shifted=%d\n",
-                   it, locked, kw, fp64_filter ? "fp64" : "fp32", nlock, ritz[0], res[0], res[kw - 1], ritz[kw - 1], used);
+      std::fprintf(stderr, "[chase_ph] it=%d locked=%d kw=%d prec=%s n64=%d nlock=%d ritz[0]=%.12g res[0]=%.3e res[kw-1]=%.3e mu_nevex=%.6g shifted=%d\n",
+                   it, locked, kw, n64 == kw ? "fp64" : (n64 ? "mixed" : "fp32"), n64, nlock, ritz[0], res[0], res[kw - 1],
+                   ritz[kw - 1], used);
     }
-    const int wanted_left = nev - locked;
     locked += nlock;
     // largest non-converged positive Ritz value; the interval only narrows (Section 4.1)
     mu_nevex = std::min(mu_nevex, ritz[kw - 1]);
@@ -619,7 +642,21 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       break;
     }
     const int kn = kw - nlock;
-    // next search block W+ <- unconverged Ritz vectors, ordered by degree
+    // Precision of the next filter, per Ritz pair (mixed path): a pair moves
+    // to FP64 once its residual is at or below switch_tol, or once it stops
+    // improving near the c64 rounding floor; it then stays in FP64.
+    std::vector<char> nst(kn);
+    std::vector<double> npr(kn);
+    for (int j = 0; j < kn; ++j) {
+      const int i = nlock + j;
+      const double r = res[i];
+      bool to64 = st64[i] != 0;
+      if (!to64 && (r <= switch_tol || (r < 30.0 * switch_tol && r > 0.7 * prev_res[i]))) to64 = true;
+      nst[j] = to64;
+      npr[j] = r;
+    }
+    // next search block W+ <- unconverged Ritz vectors, FP64 group first,
+    // each group ordered by degree
     std::vector<int> nd(kn, p.deg);
     std::vector<int> perm(kn);
     std::iota(perm.begin(), perm.end(), 0);
@@ -639,27 +676,26 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
         }
         nd[j] = d;
       }
-      std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return nd[a] < nd[b]; });
     }
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      if (nst[a] != nst[b]) return nst[a] > nst[b];
+      return nd[a] < nd[b];
+    });
     std::vector<int> src(kn);
     degs.assign(kn, p.deg);
+    n64 = 0;
     for (int j = 0; j < kn; ++j) {
       src[j] = nlock + perm[j];
       degs[j] = nd[perm[j]];
+      n64 += nst[j] ? 1 : 0;
+    }
+    // state stays indexed by Ritz order (pairs keep their order across iterations)
+    for (int j = 0; j < kn; ++j) {
+      st64[j] = nst[j];
+      prev_res[j] = npr[j];
     }
     CHASE_HIP(hipMemcpyAsync(h->dperm, src.data(), sizeof(int) * kn, hipMemcpyHostToDevice, h->st));
     CHASE_TRY(gather_columns(h->Vt, n, h->Wk, n, n, kn, h->dperm, h->st));
-    // mixed precision: move the filter to FP64 once the wanted residuals
-    // are within reach of the c64 rounding floor
-    if (!fp64_filter) {
-      const int nw = std::max(1, wanted_left - nlock);
-      std::vector<double> wr(res.begin() + nlock, res.begin() + nlock + std::min(nw, kn));
-      std::nth_element(wr.begin(), wr.begin() + wr.size() / 2, wr.end());
-      if (wr[wr.size() / 2] <= switch_tol) {
-        fp64_filter = true;
-        inf.switch_iter = it + 1;
-      }
-    }
   }
   CHASE_HIP(hipEventRecord(t1, h->st));
   CHASE_HIP(hipEventSynchronize(t1));
@@ -761,6 +797,7 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, &h->dws.tmp, (size_t)h->kp * 64));
   CHASE_TRY(dalloc(h, &h->dws.U, (size_t)h->kp * 64));
   CHASE_TRY(dalloc(h, &h->dws.flag, 4));
+  CHASE_TRY(dalloc(h, &h->dws.pflag, (size_t)h->kp / 64 + 1));
   CHASE_TRY(dalloc(h, &h->dws.dscalar, 4));
   // zgemm split-K partials (up to 8 k x k blocks) and apply_h split-K
   // partials (up to 8 x m x 2 nevex complex), within [16 MiB, 1 GiB]

@@ -53,10 +53,60 @@ __global__ void zero_upper_kernel(c128* M, int64_t ld, int kp) {
 }
 
 // ------------------------------------------------------- Cholesky block
-// Factor the 64 x 64 diagonal block at (p, p) in LDS; on a non-positive or
-// non-finite pivot set *fail and continue with a unit pivot (the result is
-// then discarded by the host).  Writes L_pp (lower, upper zeroed) and
-// its inverse into inv (64 x 64, ld 64).
+// 64 x 64 blocks held in LDS, 256 threads.  Dot products of length up to 63
+// are split over 4 consecutive lanes and combined with lane shuffles.
+__device__ __forceinline__ c128 quad_sum(c128 v) {
+  v.re += __shfl_xor(v.re, 1);
+  v.im += __shfl_xor(v.im, 1);
+  v.re += __shfl_xor(v.re, 2);
+  v.im += __shfl_xor(v.im, 2);
+  return v;
+}
+
+// In place lower Cholesky S = L L^H (left-looking by columns).  A
+// non-positive or non-finite pivot sets *fail and is replaced by 1 so that
+// the block stays finite (the host then discards the result).
+__device__ void chol64(c128 (*S)[NB + 1], int* fail) {
+  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  for (int j = 0; j < NB; ++j) {
+    c128 sum{0.0, 0.0};
+    if (row >= j)
+      for (int l = part; l < j; l += 4) sum = cadd(sum, cmul(S[row][l], cconj(S[j][l])));
+    sum = quad_sum(sum);
+    if (row == j && part == 0) {
+      double d = S[j][j].re - sum.re;
+      if (!(d > 0.0) || !isfinite(d)) {
+        atomicOr(fail, 1);
+        d = 1.0;
+      }
+      S[j][j] = c128{sqrt(d), 0.0};
+    }
+    __syncthreads();
+    if (row > j && part == 0) S[row][j] = cscale(1.0 / S[j][j].re, csub(S[row][j], sum));
+    __syncthreads();
+  }
+}
+
+// I = L^{-1} for the lower-triangular L in S (forward substitution per
+// column; the four lanes of a column all keep the solved entries, so no
+// block barrier is needed inside the loop).
+__device__ void trinv64(c128 (*S)[NB + 1], c128 (*I)[NB + 1]) {
+  const int tid = threadIdx.x, c = tid >> 2, part = tid & 3;
+  for (int i = 0; i < NB; ++i) {
+    if (i < c) {
+      if (part == 0) I[i][c] = c128{0.0, 0.0};
+      continue;
+    }
+    c128 sum{0.0, 0.0};
+    for (int l = c + part; l < i; l += 4) sum = cadd(sum, cmul(S[i][l], I[l][c]));
+    sum = quad_sum(sum);
+    const c128 rhs = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+    I[i][c] = cscale(1.0 / S[i][i].re, csub(rhs, sum));
+  }
+}
+
+// Factor the 64 x 64 diagonal block at (p, p): writes L_pp (lower, upper
+// zeroed) in place and L_pp^{-1} into inv (64 x 64, ld 64).
 __global__ __launch_bounds__(256) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
   __shared__ c128 S[NB][NB + 1];
   __shared__ c128 I[NB][NB + 1];
@@ -66,38 +116,8 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(c128* M, int64_t ld, in
     S[i][j] = M[(int64_t)(p + j) * ld + p + i];
   }
   __syncthreads();
-  __shared__ double piv;
-  for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = S[j][j].re;
-      if (!(d > 0.0) || !isfinite(d)) {
-        atomicOr(fail, 1);
-        d = 1.0;
-      }
-      piv = sqrt(d);
-      S[j][j] = c128{piv, 0.0};
-    }
-    __syncthreads();
-    const double rp = 1.0 / piv;
-    for (int i = j + 1 + tid; i < NB; i += 256) S[i][j] = cscale(rp, S[i][j]);
-    __syncthreads();
-    // trailing update of the lower part: S[i][l] -= L[i][j] conj(L[l][j]), i >= l > j
-    const int w = NB - j - 1;
-    for (int t = tid; t < w * w; t += 256) {
-      const int l = j + 1 + t / w, i = j + 1 + t % w;
-      if (i >= l) S[i][l] = csub(S[i][l], cmul(S[i][j], cconj(S[l][j])));
-    }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular block: column c solves L x = e_c
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      c128 s = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
-      for (int l = c; l < i; ++l) s = csub(s, cmul(S[i][l], I[l][c]));
-      I[i][c] = (i < c) ? c128{0.0, 0.0} : cscale(1.0 / S[i][i].re, s);
-    }
-  }
+  chol64(S, fail);
+  trinv64(S, I);
   __syncthreads();
   for (int t = tid; t < NB * NB; t += 256) {
     const int j = t / NB, i = t % NB;
@@ -115,7 +135,7 @@ __global__ void copy_block_kernel(const c128* src, int64_t lds, c128* dst, int64
 }
 
 // Invert each 64 x 64 diagonal block of a lower-triangular L (padded) and
-// write it into the diagonal of Linv; zero the strict upper part of Linv.
+// write it into the diagonal of Linv.
 __global__ __launch_bounds__(256) void trinv_diag_kernel(const c128* L, c128* X, int64_t ld) {
   __shared__ c128 S[NB][NB + 1];
   __shared__ c128 I[NB][NB + 1];
@@ -126,18 +146,11 @@ __global__ __launch_bounds__(256) void trinv_diag_kernel(const c128* L, c128* X,
     S[i][j] = L[(int64_t)(p + j) * ld + p + i];
   }
   __syncthreads();
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      c128 s = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
-      for (int l = c; l < i; ++l) s = csub(s, cmul(S[i][l], I[l][c]));
-      I[i][c] = (i < c) ? c128{0.0, 0.0} : cscale(1.0 / S[i][i].re, s);
-    }
-  }
+  trinv64(S, I);
   __syncthreads();
   for (int t = tid; t < NB * NB; t += 256) {
     const int j = t / NB, i = t % NB;
-    X[(int64_t)(p + j) * ld + p + i] = I[i][j];
+    X[(int64_t)(p + j) * ld + p + i] = (i >= j) ? I[i][j] : c128{0.0, 0.0};
   }
 }
 
@@ -173,7 +186,8 @@ __device__ __forceinline__ int rr_player(int pos, int r, int n) {
 // by cyclic Jacobi in LDS; write the accumulated unitary U (64 x 64) to
 // Uw[pair] and count significant rotations in *count.
 __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t ld, int nbj, int round,
-                                                         c128* Uw, double thr, int max_sweeps, int* count) {
+                                                         c128* Uw, double thr, int max_sweeps, int* count,
+                                                         int* pflag) {
   __shared__ c128 S[SP][SP + 1];
   __shared__ c128 U[SP][SP + 1];
   __shared__ double rc[SP / 2];
@@ -191,8 +205,18 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
     S[i][j] = G[(int64_t)gj * ld + gi];
     U[i][j] = (i == j) ? c128{1.0, 0.0} : c128{0.0, 0.0};
   }
+  if (tid == 0) any = 0;
+  __syncthreads();
+  // nothing to rotate: leave U = I and let the apply kernel skip this pair
+  for (int t = tid; t < SP * SP; t += 256) {
+    const int j = t / SP, i = t % SP;
+    if (i != j && hypot(S[i][j].re, S[i][j].im) > thr) any = 1;
+  }
+  __syncthreads();
+  const int needed = any;
   __syncthreads();
   int total = 0;
+  if (!needed) max_sweeps = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) any = 0;
     __syncthreads();
@@ -260,7 +284,11 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
     if (!any_now) break;
     ++total;
   }
-  if (tid == 0 && total > 0) atomicAdd(count, 1);
+  if (tid == 0) {
+    if (total > 0) atomicAdd(count, 1);
+    pflag[pair] = total > 0;
+  }
+  if (total == 0) return;
   c128* Uo = Uw + (int64_t)pair * SP * SP;
   for (int t = tid; t < SP * SP; t += 256) {
     const int j = t / SP, i = t % SP;
@@ -279,7 +307,7 @@ __device__ __forceinline__ int sub_index(int pair, int round, int nbj, int i) {
 // index set); block (a, b) of pairs is U_a^H G_ab U_b.  Also V <- V J on
 // row chunks of 64.  blockIdx.x < npair^2: G blocks; the rest: V blocks.
 __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int64_t ld, int kp, int nbj, int round,
-                                                           const c128* Uw) {
+                                                           const c128* Uw, const int* pflag) {
   __shared__ c128 X[SP][SP + 1];
   __shared__ c128 Y[SP][SP + 1];
   const int npair = nbj / 2;
@@ -288,6 +316,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
   int blk = blockIdx.x;
   if (blk < npair * npair) {
     const int a = blk / npair, b = blk % npair;
+    if (!pflag[a] && !pflag[b]) return;  // both rotations are the identity
     const c128* Ua = Uw + (int64_t)a * SP * SP;
     const c128* Ub = Uw + (int64_t)b * SP * SP;
     for (int t = tid; t < SP * SP; t += 256) {
@@ -295,27 +324,34 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
       X[i][j] = G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)];
     }
     __syncthreads();
+    const bool ua = pflag[a], ub = pflag[b];
     // Y = X Ub
     c128 acc[4][4];
     for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
-    for (int l = 0; l < SP; ++l) {
-      c128 u[4];
-      for (int c = 0; c < 4; ++c) u[c] = Ub[(int64_t)(tj * 4 + c) * SP + l];
-      for (int r = 0; r < 4; ++r) {
-        const c128 x = X[ti * 4 + r][l];
-        for (int c = 0; c < 4; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
+    if (ub) {
+      for (int l = 0; l < SP; ++l) {
+        c128 u[4];
+        for (int c = 0; c < 4; ++c) u[c] = Ub[(int64_t)(tj * 4 + c) * SP + l];
+        for (int r = 0; r < 4; ++r) {
+          const c128 x = X[ti * 4 + r][l];
+          for (int c = 0; c < 4; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
+        }
       }
+    } else {
+      for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = X[ti * 4 + r][tj * 4 + c];
     }
     for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) Y[ti * 4 + r][tj * 4 + c] = acc[r][c];
     __syncthreads();
     // out = Ua^H Y
-    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
-    for (int l = 0; l < SP; ++l) {
-      c128 u[4];
-      for (int r = 0; r < 4; ++r) u[r] = cconj(Ua[(int64_t)(ti * 4 + r) * SP + l]);
-      for (int c = 0; c < 4; ++c) {
-        const c128 y = Y[l][tj * 4 + c];
-        for (int r = 0; r < 4; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
+    if (ua) {
+      for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+      for (int l = 0; l < SP; ++l) {
+        c128 u[4];
+        for (int r = 0; r < 4; ++r) u[r] = cconj(Ua[(int64_t)(ti * 4 + r) * SP + l]);
+        for (int c = 0; c < 4; ++c) {
+          const c128 y = Y[l][tj * 4 + c];
+          for (int r = 0; r < 4; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
+        }
       }
     }
     for (int r = 0; r < 4; ++r)
@@ -328,6 +364,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
   } else {
     blk -= npair * npair;
     const int a = blk % npair, rb = blk / npair;  // pair, row chunk
+    if (!pflag[a]) return;
     const c128* Ua = Uw + (int64_t)a * SP * SP;
     const int r0 = rb * SP;
     for (int t = tid; t < SP * SP; t += 256) {
@@ -493,16 +530,20 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
   CHASE_HIP(hipMemcpyAsync(&fro, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
   CHASE_HIP(hipStreamSynchronize(s));
   const double thr = 1e-16 * std::max(fro, 1e-300);
+  // One cyclic sweep per subproblem: block Jacobi with approximate
+  // subproblem solutions needs about as many outer sweeps as with exact ones
+  // and a fraction of the inner work.
+  const int inner_sweeps = 1;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     CHASE_HIP(hipMemsetAsync(ws.flag, 0, sizeof(int), s));
     for (int r = 0; r < nbj - 1; ++r) {
       hipLaunchKernelGGL(jacobi_sub_kernel, dim3(npair), dim3(256), 0, s, (const c128*)G, (int64_t)kp, nbj, r,
-                         ws.U, thr, 30, ws.flag);
+                         ws.U, thr, inner_sweeps, ws.flag, ws.pflag);
       CHASE_LAUNCH_CHECK();
       const int blocks = npair * npair + npair * (kp / SP);
       hipLaunchKernelGGL(jacobi_apply_kernel, dim3(blocks), dim3(256), 0, s, G, V, (int64_t)kp, kp, nbj, r,
-                         (const c128*)ws.U);
+                         (const c128*)ws.U, (const int*)ws.pflag);
       CHASE_LAUNCH_CHECK();
     }
     int cnt = 0;
