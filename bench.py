@@ -40,6 +40,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def apply_h_source_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2601_10557_amd", "csrc", "apply_h.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the c64 H X kernel from the committed
+    rocprofv3 --pmc summary (FETCH_SIZE and WRITE_SIZE runs of this bench
+    command, scaled by the same counters on a copy of known size); None if
+    absent or if the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "apply_h_c64_traffic_mixed_vs_fp64_m4000.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha256") != apply_h_source_sha256():
+        return None
+    return d
+
+
 def cpu_baseline(p, seconds_target=10.0):
     """The oracle's Chebyshev filter on a bounded sample of the workload:
     degree-d filter on k sample columns of the same H, on the host cores."""
@@ -74,6 +94,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a device copy of this many MiB before the timed region (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -91,6 +113,13 @@ def main():
     t0 = time.perf_counter()
     p = config_problem(args.config, seed=0)
     log(f"generated {p.name} in {time.perf_counter() - t0:.1f}s")
+    if args.calib_copy_mib > 0:
+        src = torch.empty((args.calib_copy_mib << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     A = torch.from_numpy(p.A).cuda()
     B = torch.from_numpy(p.B).cuda()
     W0 = colmajor(torch.from_numpy(p.w0_raw)).cuda()
@@ -142,10 +171,18 @@ def main():
                         "fp64": float(np.max(np.abs(ev_d - ref) / ref))}
 
     achieved = fl32 / (ms32 * 1e-3) / 1e12 if ms32 > 0 else 0.0
+    tr = measured_traffic()
+    traffic, traffic_detail = None, None
+    if tr is not None:
+        traffic = tr["hbm_bytes_per_launch"]
+        traffic_detail = {"algorithmic_bytes_per_launch": by32 / max(n32, 1),
+                          "fetch_bytes_per_launch": tr["fetch_bytes_per_launch"],
+                          "write_bytes_per_launch": tr["write_bytes_per_launch"],
+                          "source": "profiles/apply_h_c64_traffic_mixed_vs_fp64_m4000.json"}
     roofline = {
-        "kernel": "apply_h_kernel<TF32,128,128,16,2,2> (c64 H X, fused Chebyshev epilogue)",
+        "kernel": "apply_h_kernel<TF32,...> (c64 H X with fused Chebyshev epilogue; tile plan per launch)",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_detail": traffic_detail,
         "launches": n32, "avg_launch_us": round(ms32 * 1e3 / max(n32, 1), 2),
         "avg_flops_per_launch": fl32 / max(n32, 1),
         "algorithmic_gbs": round(by32 / (ms32 * 1e-3) / 1e9, 1) if ms32 > 0 else 0.0,

@@ -51,8 +51,10 @@ typedef enum {
 
 typedef enum {
   CHASE_PH_FP64 = 0,  /* filter in complex FP64 (c128)                                       */
-  CHASE_PH_MIXED = 1, /* filter in complex FP32 (c64) until the switch residual, then FP64;  */
-                      /* QR, Rayleigh-Ritz, residuals and locking always in FP64            */
+  CHASE_PH_MIXED = 1, /* filter products in complex FP32 (c64): the first filter plainly,     */
+                      /* later ones in the residual-correction form of chase_ph_filter_refined*/
+                      /* (FP64 residuals and recombination); QR, Rayleigh-Ritz, residuals   */
+                      /* and locking always in FP64                                          */
   CHASE_PH_FP32 = 2   /* stage calls only: run one apply_h / filter in c64                   */
 } chase_ph_precision;
 
@@ -69,8 +71,8 @@ typedef struct {
   int32_t max_iter;     /* outer iterations (Section 6.1: 25)                               */
   double tol;           /* absolute residual ||H v - lambda v||_2 on unit v                 */
   int32_t precision;    /* chase_ph_precision: FP64 or MIXED                                */
-  double switch_tol;    /* MIXED: residual below which columns are filtered in FP64;        */
-                        /* <= 0 selects 1e-5 * mu_n                                          */
+  double switch_tol;    /* MIXED: > 0 keeps pairs with residual above it on the plain c64    */
+                        /* filter; <= 0 (default): residual-correction form for every pair  */
   double gamma;         /* lower-half scaling of the initial block (Section 4.6: 1e-3)      */
   int32_t lanczos_steps;/* per run, even (Section 4.1; 26)                                  */
   int32_t lanczos_vecs; /* independent Lanczos runs (4)                                     */
@@ -125,6 +127,20 @@ chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_
 chase_ph_status chase_ph_filter(chase_ph_t h, int32_t k, void* dW, int64_t ldw,
                                 const int32_t* degs, double mu1, double mu_nevex,
                                 double mu_n, int32_t prec);
+
+/* In place W <- p(H^2) W for k unit Ritz vectors (c128, dW) with Ritz
+ * values hLam (host, k) and residual vectors dR = H W - W diag(hLam)
+ * (c128, n x k), evaluated with c64 matrix products and FP64 refinement:
+ *   p(H^2) w = p(lambda^2) w + q(H^2) (H + lambda) r,
+ * q the divided difference of the scaled Chebyshev polynomial p of eq. 4.1
+ * (Section 4.2), built by the same three-term recurrence with a source
+ * term.  The result equals the filter of chase_ph_filter in exact
+ * arithmetic; the c64 rounding error is relative to the correction term,
+ * which shrinks with the residual.  degs, mu1, mu_nevex, mu_n as in
+ * chase_ph_filter; dR is not modified. */
+chase_ph_status chase_ph_filter_refined(chase_ph_t h, int32_t k, void* dW, int64_t ldw, const void* dR,
+                                        int64_t ldr, const double* hLam, const int32_t* degs, double mu1,
+                                        double mu_nevex, double mu_n);
 
 /* In place CholeskyQR2 of an n x k c128 block dX (Section 2: Cholesky QR
  * orthonormalisation; shifted CholeskyQR3 fallback when the first

@@ -47,7 +47,7 @@ EXPORTS = [
     "chase_ph_default_params", "chase_ph_create", "chase_ph_destroy", "chase_ph_last_error",
     "chase_ph_apply_h", "chase_ph_filter", "chase_ph_qr", "chase_ph_oblique_rr",
     "chase_ph_residuals", "chase_ph_solve", "chase_ph_eigval_backward", "chase_ph_last_timing",
-    "chase_ph_profile", "chase_ph_profile_read",
+    "chase_ph_profile", "chase_ph_profile_read", "chase_ph_filter_refined",
 ]
 
 
@@ -68,6 +68,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.chase_ph_last_error.restype = C.c_char_p
     lib.chase_ph_apply_h.argtypes = [vp, i32, vp, i64, vp, i64, i32]
     lib.chase_ph_filter.argtypes = [vp, i32, vp, i64, pi, dbl, dbl, dbl, i32]
+    lib.chase_ph_filter_refined.argtypes = [vp, i32, vp, i64, vp, i64, pd, pi, dbl, dbl, dbl]
     lib.chase_ph_qr.argtypes = [vp, i32, vp, i64, vp, i64, pi]
     lib.chase_ph_oblique_rr.argtypes = [vp, i32, vp, i64, pd, vp, i64, vp, i64]
     lib.chase_ph_residuals.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp, i64, pd, vp, i64, pd]

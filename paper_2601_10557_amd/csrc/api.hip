@@ -36,6 +36,14 @@ struct chase_ph_s {
   c64* W32 = nullptr;
   c64* F1_32 = nullptr;
   c64* FT_32 = nullptr;
+  // residual-correction filter (mixed path)
+  c128* Rv = nullptr;     // n x nevex unit-Ritz-vector residuals from the last RR
+  c128* Rk = nullptr;     // same, in the column order of Wk
+  c64* S32 = nullptr;     // n x nevex source (H + lambda) r
+  c64* R32 = nullptr;     // n x nevex residuals in c64
+  float* dcoef = nullptr; // per-step per-column source coefficients
+  double* dpw = nullptr;  // per-column p_d(lambda^2)
+  int coef_cap = 0;
   // QR / RR (n x kmax)
   c128* Xs = nullptr;
   c128* Xt = nullptr;
@@ -107,6 +115,14 @@ Err dalloc(chase_ph_t h, T** p, size_t count) {
   return ok();
 }
 
+// Small host-to-device copy from pageable host memory; waits for it so the
+// host buffer may be released right after.
+Err h2d(chase_ph_t h, void* dst, const void* src, size_t bytes) {
+  CHASE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  return ok();
+}
+
 Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alpha, const c128* A, int64_t lda,
          const c128* B, int64_t ldb, c128 beta, c128* C, int64_t ldc, int64_t kneg = -1, bool split = true) {
   ZgemmArgs g{};
@@ -127,6 +143,11 @@ Err ensure_shadow(chase_ph_t h) {
   CHASE_TRY(dalloc(h, &h->W32, (size_t)h->n * h->nevex));
   CHASE_TRY(dalloc(h, &h->F1_32, (size_t)h->n * h->nevex));
   CHASE_TRY(dalloc(h, &h->FT_32, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->Rv, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->Rk, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->S32, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->R32, (size_t)h->n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->dpw, (size_t)h->nevex));
   return make_shadow(h->A, h->B, h->ld, h->p.a_conj, h->A32, h->B32, h->ld32, h->m, h->st);
 }
 
@@ -170,11 +191,12 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
 
 Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy, float alpha = 1,
             const c64* P = nullptr, int64_t ldp = 0, float beta = 0, const c64* Q = nullptr, int64_t ldq = 0,
-            float gamma = 0) {
+            float gamma = 0, const c64* S = nullptr, int64_t lds = 0, const float* dcol = nullptr) {
   ApplyHArgs<float> a{};
   a.A = h->A32; a.B = h->B32; a.lda = h->ld32; a.a_conj = 0; a.m = h->m; a.k = k;
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
+  a.S = S; a.lds = lds; a.dcol = dcol;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
   CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st));
@@ -233,6 +255,89 @@ Err filter_impl(chase_ph_t h, int k, C* W, int64_t ldw, const std::vector<int>& 
     j = j2;
   }
   return ok();
+}
+
+// p_d(H^2) v evaluated as p_d(lambda^2) v + D_d / e with the correction
+// D_d = e [p_d(H^2) - p_d(lambda^2)] v built in c64 from the FP64 residual
+// r = H v - lambda v of each unit Ritz vector (lambda its Ritz value):
+//   s = (H + lambda) r = (H^2 - lambda^2) v,   D_1 = sigma_1 s,
+//   D_{j+1} = (2 sigma_{j+1} / e)(H^2 - c) D_j - sigma_j sigma_{j+1} D_{j-1}
+//             + 2 sigma_{j+1} p_j(lambda^2) s,
+// with p_j(lambda^2) = T_j(tau)/T_j(t_0) from the same scaled recurrence
+// (tau = (lambda^2 - c)/e).  This is the scaled Chebyshev filter of eq. 4.1
+// rearranged exactly (divided differences of T_d); the c64 rounding error is
+// relative to the correction, which shrinks with the residual, so the c64
+// products carry the filter to FP64 accuracy.  Columns sorted by degree;
+// W (c128, in place) holds the unit Ritz vectors, R (c128) their residuals.
+Err filter_correction(chase_ph_t h, int k, c128* W, int64_t ldw, const c128* R, int64_t ldr,
+                      const std::vector<double>& lam, const std::vector<int>& d, double mu1, double mu_nevex,
+                      double mu_n, double* flops) {
+  if (k == 0) return ok();
+  const int64_t n = h->n;
+  const double c = 0.5 * (mu_n * mu_n + mu_nevex * mu_nevex);
+  const double e = 0.5 * (mu_n * mu_n - mu_nevex * mu_nevex);
+  const double sigma1 = e / (mu1 * mu1 - c);
+  const int maxd = d[k - 1];
+  // host scalars: sigma_j, p_j(lambda_col^2), source coefficients
+  std::vector<double> sig(maxd + 1, 0.0);
+  sig[1] = sigma1;
+  for (int j = 1; j < maxd; ++j) sig[j + 1] = 1.0 / (2.0 / sigma1 - sig[j]);
+  const int rows = std::max(1, maxd - 1);
+  std::vector<float> coef((size_t)(rows + 1) * k, 0.0f);
+  std::vector<double> pw(k);
+  for (int col = 0; col < k; ++col) {
+    const double tau = (lam[col] * lam[col] - c) / e;
+    double pprev = 1.0, pcur = sigma1 * tau;  // p_0, p_1
+    for (int j = 1; j < d[col]; ++j) {
+      coef[(size_t)(j - 1) * k + col] = (float)(2.0 * sig[j + 1] * pcur);
+      const double pn = 2.0 * sig[j + 1] * tau * pcur - sig[j] * sig[j + 1] * pprev;
+      pprev = pcur;
+      pcur = pn;
+    }
+    pw[col] = pcur;
+    coef[(size_t)rows * k + col] = (float)lam[col];  // row `rows`: lambda for s
+  }
+  if (h->coef_cap < (int)coef.size()) {
+    CHASE_TRY(dalloc(h, &h->dcoef, coef.size()));
+    h->coef_cap = (int)coef.size();
+  }
+  CHASE_TRY(h2d(h, h->dcoef, coef.data(), coef.size() * sizeof(float)));
+  CHASE_TRY(h2d(h, h->dpw, pw.data(), k * sizeof(double)));
+  CHASE_TRY(convert_to_c64(R, ldr, h->R32, n, n, k, h->st));
+  auto count = [&](int kc) { *flops += 8.0 * (double)n * (double)n * kc; };
+  // s = H r + lambda r
+  CHASE_TRY(apply32(h, k, h->R32, n, h->S32, n, 1.0f, nullptr, 0, 0.0f, nullptr, 0, 0.0f, h->R32, n,
+                    h->dcoef + (size_t)rows * k));
+  count(k);
+  c64* B0 = h->W32;   // D_j for even j
+  c64* B1 = h->F1_32; // D_j for odd j
+  c64* T = h->FT_32;
+  CHASE_TRY(scale_c64(h->S32, n, B1, n, n, k, (float)sigma1, h->st));  // D_1
+  int j0 = 0;
+  for (int j = 1; j < maxd; ++j) {
+    while (j0 < k && d[j0] < j + 1) ++j0;
+    const int kc = k - j0;
+    c64* cur = (j % 2 ? B1 : B0) + (int64_t)j0 * n;
+    c64* prev = (j % 2 ? B0 : B1) + (int64_t)j0 * n;
+    const double sn = sig[j + 1];
+    CHASE_TRY(apply32(h, kc, cur, n, T + (int64_t)j0 * n, n));
+    count(kc);
+    CHASE_TRY(apply32(h, kc, T + (int64_t)j0 * n, n, prev, n, (float)(2.0 * sn / e), cur, n, (float)(-2.0 * sn * c / e),
+                      j >= 2 ? prev : nullptr, n, (float)(-sig[j] * sn), h->S32 + (int64_t)j0 * n, n,
+                      h->dcoef + (size_t)(j - 1) * k + j0));
+    count(kc);
+  }
+  // odd final degrees ended in B1
+  int j = 0;
+  while (j < k) {
+    int j2 = j;
+    while (j2 < k && d[j2] == d[j]) ++j2;
+    if (d[j] % 2 == 1)
+      CHASE_HIP(hipMemcpy2DAsync(B0 + (int64_t)j * n, n * sizeof(c64), B1 + (int64_t)j * n, n * sizeof(c64),
+                                 n * sizeof(c64), j2 - j, hipMemcpyDeviceToDevice, h->st));
+    j = j2;
+  }
+  return combine_correction(W, ldw, B0, n, h->dpw, 1.0 / e, n, k, h->st);
 }
 
 Err check_filter_args(chase_ph_t h, int k, int64_t ldw, const int32_t* degs, double mu1, double mu_nevex, double mu_n,
@@ -361,14 +466,13 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
 }
 
 Err resid_impl(chase_ph_t h, int k, int kk, const c128* Q, int64_t ldq, const c128* T, int64_t ldt, const c128* Zpos,
-               int64_t ldz, const double* ritz_host, c128* V, int64_t ldv, double* resid) {
+               int64_t ldz, const double* ritz_host, c128* V, int64_t ldv, double* resid, c128* Rout = nullptr) {
   if (kk == 0) return ok();
   const int64_t n = h->n;
   CHASE_TRY(gemm(h, 0, 0, n, kk, k, {1, 0}, Q, ldq, Zpos, ldz, {0, 0}, V, ldv, -1, false));
   CHASE_TRY(gemm(h, 0, 0, n, kk, k, {1, 0}, T, ldt, Zpos, ldz, {0, 0}, h->TZ, n, -1, false));
-  if (ritz_host)
-    CHASE_HIP(hipMemcpyAsync(h->dlam, ritz_host, sizeof(double) * kk, hipMemcpyHostToDevice, h->st));
-  CHASE_TRY(residual_norms(V, ldv, h->TZ, n, h->dlam, n, kk, h->dres, h->st));
+  if (ritz_host) CHASE_TRY(h2d(h, h->dlam, ritz_host, sizeof(double) * kk));
+  CHASE_TRY(residual_norms(V, ldv, h->TZ, n, h->dlam, n, kk, h->dres, Rout, n, h->st));
   CHASE_HIP(hipMemcpyAsync(resid, h->dres, sizeof(double) * kk, hipMemcpyDeviceToHost, h->st));
   CHASE_HIP(hipStreamSynchronize(h->st));
   return ok();
@@ -558,7 +662,6 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   if (!std::isfinite(mu1) || !std::isfinite(mu_n) || !std::isfinite(mu_nevex) || !(mu1 > 0) || !(mu_nevex > mu1) ||
       !(mu_n > mu_nevex))
     return fail(CHASE_PH_ERR_NOT_DEFINITE, "Lanczos spectral estimates invalid (SH not positive definite?)");
-  const double switch_tol = p.switch_tol > 0 ? p.switch_tol : 1e-5 * mu_n;
   const bool mixed = p.precision == CHASE_PH_MIXED;
   if (mixed) CHASE_TRY(ensure_shadow(h));
 
@@ -566,31 +669,43 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   std::vector<double> lam_locked, res_locked;
   std::vector<int> degs(nevex, p.deg);
   std::vector<double> ritz(nevex), res(nevex);
-  // per Ritz index (ascending order of the current search block): filter
-  // precision and the residual of the previous iteration
-  std::vector<char> st64(nevex, mixed ? 0 : 1);
-  std::vector<double> prev_res(nevex, 1e300);
-  int n64 = mixed ? 0 : nevex;  // the first n64 columns of W are filtered in FP64
+  // Filter mode per Ritz pair (ascending order of the current search
+  // block): 0 = c128, 1 = c64 residual correction, 2 = plain c64.  The FP64
+  // path uses mode 0 throughout.  The mixed path starts in mode 2 (no Ritz
+  // pairs yet), moves every pair to mode 1 once it has a Ritz value and an
+  // FP64 residual (above switch_tol > 0 a pair stays in mode 2), and moves a
+  // pair to mode 0 only if its residual stagnates close to tol.
+  std::vector<char> mode(nevex, mixed ? 2 : 0);
+  std::vector<double> prev_res(nevex, 1e300), lamcol(nevex, 0.0);
+  int g0 = mixed ? 0 : nevex, g1 = 0;  // W columns: [mode 0 | mode 1 | mode 2]
   int hist_pos = 0;
   *converged = false;
   for (int it = 0; it < p.max_iter; ++it) {
     const int kw = nevex - locked;
-    // filter the positive half (Alg. 3; Thm 4.2): columns [0, n64) in c128,
-    // columns [n64, kw) in c64
     double fl = 0;
     CHASE_TRY(tm.start());
-    if (n64 > 0) {
-      std::vector<int> d64(degs.begin(), degs.begin() + n64);
-      CHASE_TRY(filter_any(h, n64, h->Wk, n, d64, mu1, mu_nevex, mu_n, CHASE_PH_FP64, &fl));
+    if (g0 > 0) {
+      std::vector<int> d0(degs.begin(), degs.begin() + g0);
+      CHASE_TRY(filter_any(h, g0, h->Wk, n, d0, mu1, mu_nevex, mu_n, CHASE_PH_FP64, &fl));
       inf.filter_flops += fl;
-      if (inf.switch_iter < 0) inf.switch_iter = it;
+      if (inf.switch_iter < 0 && mixed) inf.switch_iter = it;
     }
-    if (n64 < kw) {
-      const int k32 = kw - n64;
-      std::vector<int> d32(degs.begin() + n64, degs.begin() + kw);
-      CHASE_TRY(convert_to_c64(h->Wk + (int64_t)n64 * n, n, h->W32, n, n, k32, h->st));
-      CHASE_TRY(filter_any(h, k32, h->W32, n, d32, mu1, mu_nevex, mu_n, CHASE_PH_FP32, &fl));
-      CHASE_TRY(convert_to_c128(h->W32, n, h->Wk + (int64_t)n64 * n, n, n, k32, h->st));
+    if (g1 > 0) {
+      fl = 0;
+      std::vector<int> d1(degs.begin() + g0, degs.begin() + g0 + g1);
+      std::vector<double> l1(lamcol.begin() + g0, lamcol.begin() + g0 + g1);
+      CHASE_TRY(filter_correction(h, g1, h->Wk + (int64_t)g0 * n, n, h->Rk + (int64_t)g0 * n, n, l1, d1, mu1,
+                                  mu_nevex, mu_n, &fl));
+      inf.filter_flops_fp32 += fl;
+      inf.filter_flops += fl;
+    }
+    if (g0 + g1 < kw) {
+      const int c0 = g0 + g1, k32 = kw - c0;
+      fl = 0;
+      std::vector<int> d2(degs.begin() + c0, degs.begin() + kw);
+      CHASE_TRY(convert_to_c64(h->Wk + (int64_t)c0 * n, n, h->W32, n, n, k32, h->st));
+      CHASE_TRY(filter_any(h, k32, h->W32, n, d2, mu1, mu_nevex, mu_n, CHASE_PH_FP32, &fl));
+      CHASE_TRY(convert_to_c128(h->W32, n, h->Wk + (int64_t)c0 * n, n, n, k32, h->st));
       inf.filter_flops_fp32 += fl;
       inf.filter_flops += fl;
     }
@@ -611,7 +726,8 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     CHASE_TRY(tm.stop(&inf.t_rr));
     // half back-transform and residuals (Section 4.5)
     CHASE_TRY(tm.start());
-    CHASE_TRY(resid_impl(h, kq, kw, Q, n, h->Tq, n, h->Zp, h->kmax, nullptr, h->Vt, n, res.data()));
+    CHASE_TRY(resid_impl(h, kq, kw, Q, n, h->Tq, n, h->Zp, h->kmax, nullptr, h->Vt, n, res.data(),
+                         mixed ? h->Rv : nullptr));
     CHASE_TRY(tm.stop(&inf.t_resid));
     inf.rr_flops += 8.0 * n * n * kq + 12.0 * n * (double)kq * kq + 16.0 * n * (double)kx * kx;
     if (inf.resid_history && hist_pos + kw <= inf.resid_history_len) {
@@ -629,8 +745,8 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       res_locked.push_back(res[i]);
     }
     if (verbose) {
-      std::fprintf(stderr, "[chase_ph] it=%d locked=%d kw=%d prec=%s n64=%d nlock=%d ritz[0]=%.12g res[0]=%.3e res[kw-1]=%.3e mu_nevex=%.6g shifted=%d\n",
-                   it, locked, kw, n64 == kw ? "fp64" : (n64 ? "mixed" : "fp32"), n64, nlock, ritz[0], res[0], res[kw - 1],
+      std::fprintf(stderr, "[chase_ph] it=%d locked=%d kw=%d prec=%s n_fp64=%d nlock=%d ritz[0]=%.12g res[0]=%.3e res[kw-1]=%.3e mu_nevex=%.6g shifted=%d\n",
+                   it, locked, kw, g0 == kw ? "fp64" : (g1 ? "corr" : "fp32"), g0, nlock, ritz[0], res[0], res[kw - 1],
                    ritz[kw - 1], used);
     }
     locked += nlock;
@@ -642,21 +758,20 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       break;
     }
     const int kn = kw - nlock;
-    // Precision of the next filter, per Ritz pair (mixed path): a pair moves
-    // to FP64 once its residual is at or below switch_tol, or once it stops
-    // improving near the c64 rounding floor; it then stays in FP64.
-    std::vector<char> nst(kn);
+    // filter mode of each remaining pair for the next iteration
+    std::vector<char> nmode(kn);
     std::vector<double> npr(kn);
     for (int j = 0; j < kn; ++j) {
       const int i = nlock + j;
       const double r = res[i];
-      bool to64 = st64[i] != 0;
-      if (!to64 && (r <= switch_tol || (r < 30.0 * switch_tol && r > 0.7 * prev_res[i]))) to64 = true;
-      nst[j] = to64;
+      char md = mode[i];
+      if (mixed && md == 2 && !(p.switch_tol > 0 && r > p.switch_tol)) md = 1;
+      if (mixed && md == 1 && r < 1e3 * p.tol && r > 0.7 * prev_res[i]) md = 0;
+      nmode[j] = md;
       npr[j] = r;
     }
-    // next search block W+ <- unconverged Ritz vectors, FP64 group first,
-    // each group ordered by degree
+    // next search block W+ <- unconverged Ritz vectors, grouped by filter
+    // mode, each group ordered by degree
     std::vector<int> nd(kn, p.deg);
     std::vector<int> perm(kn);
     std::iota(perm.begin(), perm.end(), 0);
@@ -678,24 +793,28 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       }
     }
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-      if (nst[a] != nst[b]) return nst[a] > nst[b];
+      if (nmode[a] != nmode[b]) return nmode[a] < nmode[b];
       return nd[a] < nd[b];
     });
     std::vector<int> src(kn);
     degs.assign(kn, p.deg);
-    n64 = 0;
+    g0 = 0;
+    g1 = 0;
     for (int j = 0; j < kn; ++j) {
       src[j] = nlock + perm[j];
       degs[j] = nd[perm[j]];
-      n64 += nst[j] ? 1 : 0;
+      lamcol[j] = ritz[nlock + perm[j]];
+      g0 += nmode[j] == 0;
+      g1 += nmode[j] == 1;
     }
     // state stays indexed by Ritz order (pairs keep their order across iterations)
     for (int j = 0; j < kn; ++j) {
-      st64[j] = nst[j];
+      mode[j] = nmode[j];
       prev_res[j] = npr[j];
     }
-    CHASE_HIP(hipMemcpyAsync(h->dperm, src.data(), sizeof(int) * kn, hipMemcpyHostToDevice, h->st));
+    CHASE_TRY(h2d(h, h->dperm, src.data(), sizeof(int) * kn));
     CHASE_TRY(gather_columns(h->Vt, n, h->Wk, n, n, kn, h->dperm, h->st));
+    if (mixed) CHASE_TRY(gather_columns(h->Rv, n, h->Rk, n, n, kn, h->dperm, h->st));
   }
   CHASE_HIP(hipEventRecord(t1, h->st));
   CHASE_HIP(hipEventSynchronize(t1));
@@ -797,7 +916,7 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, &h->dws.tmp, (size_t)h->kp * 64));
   CHASE_TRY(dalloc(h, &h->dws.U, (size_t)h->kp * 64));
   CHASE_TRY(dalloc(h, &h->dws.flag, 4));
-  CHASE_TRY(dalloc(h, &h->dws.pflag, (size_t)h->kp / 64 + 1));
+  CHASE_TRY(dalloc(h, &h->dws.pflag, (size_t)h->kp / 8 + 1));
   CHASE_TRY(dalloc(h, &h->dws.dscalar, 4));
   // zgemm split-K partials (up to 8 k x k blocks) and apply_h split-K
   // partials (up to 8 x m x 2 nevex complex), within [16 MiB, 1 GiB]
@@ -906,6 +1025,23 @@ chase_ph_status chase_ph_filter(chase_ph_t h, int32_t k, void* dW, int64_t ldw, 
   if (!e && k > 0 && !dW) e = fail(CHASE_PH_ERR_ARG, "filter: null W");
   if (e) return finish(h, e);
   return finish(h, filter_any(h, k, dW, ldw, d, mu1, mu_nevex, mu_n, prec, nullptr));
+}
+
+chase_ph_status chase_ph_filter_refined(chase_ph_t h, int32_t k, void* dW, int64_t ldw, const void* dR, int64_t ldr,
+                                        const double* hLam, const int32_t* degs, double mu1, double mu_nevex,
+                                        double mu_n) {
+  CHECK_HANDLE(h);
+  std::vector<int> d;
+  Err e = check_filter_args(h, k, ldw, degs, mu1, mu_nevex, mu_n, d);
+  if (!e && k > 0 && (!dW || !dR || !hLam || ldr < h->n)) e = fail(CHASE_PH_ERR_ARG, "filter_refined: bad arguments");
+  if (e) return finish(h, e);
+  if (k == 0) return CHASE_PH_OK;
+  e = ensure_shadow(h);
+  std::vector<double> lam(hLam, hLam + k);
+  double fl = 0;
+  if (!e) e = filter_correction(h, k, (c128*)dW, ldw, (const c128*)dR, ldr, lam, d, mu1, mu_nevex, mu_n, &fl);
+  if (!e && hipStreamSynchronize(h->st) != hipSuccess) e = fail(CHASE_PH_ERR_HIP, "filter_refined: sync");
+  return finish(h, e);
 }
 
 chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void* dR, int64_t ldr, int32_t* used_shift) {

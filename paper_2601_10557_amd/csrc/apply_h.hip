@@ -9,7 +9,7 @@
 // buffer holds conj(A)); the conjugation and half swap K conj(X) are folded
 // into the loads of the small operand, and the sign/conj of the bottom half
 // into the epilogue, which also fuses the Chebyshev three-term update
-//   Y = alpha (H X) + beta P + gamma Q.
+//   Y = alpha (H X) + beta P + gamma Q + diag(dcol) S.
 //
 // Complex products run on real MFMA tiles: Re += Ar Br - Ai Bi,
 // Im += Ar Bi + Ai Br (four MFMAs per complex k-slice, two accumulators).
@@ -125,6 +125,12 @@ __device__ __forceinline__ void epilogue_store(const ApplyHArgs<R>& a, int gr, i
     const C q = a.Q[(int64_t)ocol * a.ldq + orow];
     yr += a.gamma * q.re;
     yi += a.gamma * q.im;
+  }
+  if (a.S) {
+    const C z = a.S[(int64_t)ocol * a.lds + orow];
+    const R d = a.dcol[ocol];
+    yr += d * z.re;
+    yi += d * z.im;
   }
   C out;
   out.re = yr;

@@ -73,8 +73,10 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Computes, for the active columns of an n x k block X,
 //   R = [A B] * [X, K conj(X)]          (m x 2k GEMM, K-dim 2m)
 //   (H X)_top = R[:, :k],  (H X)_bot = -conj(R[:, k:])
-// and writes  Y = alpha (H X) + beta P + gamma Q  (P, Q optional, real scalars).
-// Y may alias Q (element-wise read-before-write in the same thread).
+// and writes  Y = alpha (H X) + beta P + gamma Q + diag(dcol) S
+// (P, Q, S optional; alpha, beta, gamma real scalars, dcol a device array of
+// per-column real scalars).  Y may alias Q (element-wise read-before-write
+// in the same thread).
 // ----------------------------------------------------------------------------
 template <typename R>
 struct ApplyHArgs {
@@ -94,6 +96,9 @@ struct ApplyHArgs {
   const C* Q;       // may be null
   int64_t ldq;
   R alpha, beta, gamma;
+  const C* S;       // may be null
+  int64_t lds;
+  const R* dcol;    // k per-column scalars for S (device)
 };
 
 // ws: device workspace for split-K partial products (ws_bytes may be 0:

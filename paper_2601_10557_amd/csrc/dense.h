@@ -8,9 +8,9 @@ struct DenseWs {
   c128* small = nullptr;   // 64 x 64
   c128* panel = nullptr;   // kp_max x 64
   c128* tmp = nullptr;     // kp_max x 64 (batched 64 x 64 blocks)
-  c128* U = nullptr;       // kp_max x 64 (one 64 x 64 rotation per Jacobi pair)
+  c128* U = nullptr;       // kp_max x 64 (one rotation block per Jacobi pair)
   int* flag = nullptr;     // 4 ints
-  int* pflag = nullptr;    // kp_max / 64 ints (Jacobi pair rotated?)
+  int* pflag = nullptr;    // kp_max / 8 ints (Jacobi pair rotated?)
   double* dscalar = nullptr;  // 4 doubles
 };
 

@@ -4,10 +4,10 @@
 // 64, leading dimension kp) so that every blocked step has uniform sizes:
 //  * Cholesky  M = L L^H, right-looking, 64-column panels;
 //  * triangular inverse L^{-1}, by block diagonals of batched GEMMs;
-//  * Hermitian eigensolver: block Jacobi with 32-column blocks; each pair of
-//    blocks (a 64 x 64 subproblem) is diagonalised by cyclic Jacobi in LDS
-//    and the block rotations are applied to the matrix and the eigenvectors
-//    with 64 x 64 complex products.
+//  * Hermitian eigensolver: block Jacobi with 16-column blocks; each pair of
+//    blocks (a 32 x 32 subproblem) gets one cyclic Jacobi sweep in LDS and
+//    the block rotations are applied to the matrix and the eigenvectors with
+//    32 x 32 complex products.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -19,7 +19,8 @@ namespace chase {
 namespace {
 
 constexpr int NB = 64;   // panel / padding granularity
-constexpr int JB = 32;   // Jacobi block (subproblem is 2*JB)
+constexpr int JB = 16;   // Jacobi block (subproblem is 2*JB)
+constexpr int TR = 2 * JB / 16;  // rows/cols per thread in the 16x16-thread block products
 constexpr int SP = 2 * JB;
 
 __device__ __forceinline__ c128 cmul(c128 a, c128 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
   __shared__ c128 Y[SP][SP + 1];
   const int npair = nbj / 2;
   const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;  // 4x4 outputs per thread: rows ti*4.., cols tj*4..
+  const int ti = tid / 16, tj = tid % 16;  // TR x TR outputs per thread
   int blk = blockIdx.x;
   if (blk < npair * npair) {
     const int a = blk / npair, b = blk % npair;
@@ -326,37 +327,37 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
     __syncthreads();
     const bool ua = pflag[a], ub = pflag[b];
     // Y = X Ub
-    c128 acc[4][4];
-    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+    c128 acc[TR][TR];
+    for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
     if (ub) {
       for (int l = 0; l < SP; ++l) {
-        c128 u[4];
-        for (int c = 0; c < 4; ++c) u[c] = Ub[(int64_t)(tj * 4 + c) * SP + l];
-        for (int r = 0; r < 4; ++r) {
-          const c128 x = X[ti * 4 + r][l];
-          for (int c = 0; c < 4; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
+        c128 u[TR];
+        for (int c = 0; c < TR; ++c) u[c] = Ub[(int64_t)(tj * TR + c) * SP + l];
+        for (int r = 0; r < TR; ++r) {
+          const c128 x = X[ti * TR + r][l];
+          for (int c = 0; c < TR; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
         }
       }
     } else {
-      for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = X[ti * 4 + r][tj * 4 + c];
+      for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = X[ti * TR + r][tj * TR + c];
     }
-    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) Y[ti * 4 + r][tj * 4 + c] = acc[r][c];
+    for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) Y[ti * TR + r][tj * TR + c] = acc[r][c];
     __syncthreads();
     // out = Ua^H Y
     if (ua) {
-      for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+      for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
       for (int l = 0; l < SP; ++l) {
-        c128 u[4];
-        for (int r = 0; r < 4; ++r) u[r] = cconj(Ua[(int64_t)(ti * 4 + r) * SP + l]);
-        for (int c = 0; c < 4; ++c) {
-          const c128 y = Y[l][tj * 4 + c];
-          for (int r = 0; r < 4; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
+        c128 u[TR];
+        for (int r = 0; r < TR; ++r) u[r] = cconj(Ua[(int64_t)(ti * TR + r) * SP + l]);
+        for (int c = 0; c < TR; ++c) {
+          const c128 y = Y[l][tj * TR + c];
+          for (int r = 0; r < TR; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
         }
       }
     }
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 4; ++c) {
-        const int i = ti * 4 + r, j = tj * 4 + c;
+    for (int r = 0; r < TR; ++r)
+      for (int c = 0; c < TR; ++c) {
+        const int i = ti * TR + r, j = tj * TR + c;
         c128 v = acc[r][c];
         if (a == b && i == j) v.im = 0.0;
         G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)] = v;
@@ -372,30 +373,46 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
       X[i][j] = V[(int64_t)sub_index(a, round, nbj, j) * ld + r0 + i];
     }
     __syncthreads();
-    c128 acc[4][4];
-    for (int r = 0; r < 4; ++r) for (int c = 0; c < 4; ++c) acc[r][c] = c128{0, 0};
+    c128 acc[TR][TR];
+    for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
     for (int l = 0; l < SP; ++l) {
-      c128 u[4];
-      for (int c = 0; c < 4; ++c) u[c] = Ua[(int64_t)(tj * 4 + c) * SP + l];
-      for (int r = 0; r < 4; ++r) {
-        const c128 x = X[ti * 4 + r][l];
-        for (int c = 0; c < 4; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
+      c128 u[TR];
+      for (int c = 0; c < TR; ++c) u[c] = Ua[(int64_t)(tj * TR + c) * SP + l];
+      for (int r = 0; r < TR; ++r) {
+        const c128 x = X[ti * TR + r][l];
+        for (int c = 0; c < TR; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
       }
     }
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 4; ++c)
-        V[(int64_t)sub_index(a, round, nbj, tj * 4 + c) * ld + r0 + ti * 4 + r] = acc[r][c];
+    for (int r = 0; r < TR; ++r)
+      for (int c = 0; c < TR; ++c)
+        V[(int64_t)sub_index(a, round, nbj, tj * TR + c) * ld + r0 + ti * TR + r] = acc[r][c];
   }
 }
 
-__global__ void frob_kernel(const c128* G, int64_t ld, int kp, double* out) {
+// Frobenius norm in two deterministic stages: one block per column writes the
+// column's sum of squares, then one block adds the kp column sums in a fixed
+// order.
+__global__ __launch_bounds__(256) void frob_cols_kernel(const c128* G, int64_t ld, int kp, double* part) {
   __shared__ double red[256];
+  const int64_t col = blockIdx.x;
   double s = 0;
-  const int64_t total = (int64_t)kp * kp;
-  for (int64_t t = threadIdx.x; t < total; t += 256) {
-    const c128 z = G[(t / kp) * ld + t % kp];
+  for (int i = threadIdx.x; i < kp; i += 256) {
+    const c128 z = G[col * ld + i];
     s += z.re * z.re + z.im * z.im;
   }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[col] = red[0];
+}
+
+__global__ __launch_bounds__(256) void frob_sum_kernel(const double* part, int kp, double* out) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int i = threadIdx.x; i < kp; i += 256) s += part[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -439,6 +456,17 @@ __global__ void select_kernel(const c128* G, const c128* V, int64_t ld, int k, i
 
 // ---------------------------------------------------------------------------
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048)); }
+
+static Err frob_norm(const c128* G, int kp, DenseWs& ws, hipStream_t s, double* host_out) {
+  double* part = reinterpret_cast<double*>(ws.panel);  // kp doubles (panel holds kp x 64 c128)
+  hipLaunchKernelGGL(frob_cols_kernel, dim3(kp), dim3(256), 0, s, G, (int64_t)kp, kp, part);
+  CHASE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(frob_sum_kernel, dim3(1), dim3(256), 0, s, (const double*)part, kp, ws.dscalar);
+  CHASE_LAUNCH_CHECK();
+  CHASE_HIP(hipMemcpyAsync(host_out, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  return ok();
+}
 
 Err fill_padded(c128* M, int kp, int k, double inner, double pad, bool zero_all, hipStream_t s) {
   hipLaunchKernelGGL(fill_diag_kernel, dim3(grid_for((int64_t)kp * kp)), dim3(256), 0, s, M, (int64_t)kp, kp, k,
@@ -524,11 +552,8 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
   const int nbj = kp / JB;  // even since kp % 64 == 0
   const int npair = nbj / 2;
   CHASE_TRY(fill_padded(V, kp, kp, 1.0, 1.0, true, s));
-  hipLaunchKernelGGL(frob_kernel, dim3(1), dim3(256), 0, s, (const c128*)G, (int64_t)kp, kp, ws.dscalar);
-  CHASE_LAUNCH_CHECK();
   double fro = 0;
-  CHASE_HIP(hipMemcpyAsync(&fro, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
-  CHASE_HIP(hipStreamSynchronize(s));
+  CHASE_TRY(frob_norm(G, kp, ws, s, &fro));
   const double thr = 1e-16 * std::max(fro, 1e-300);
   // One cyclic sweep per subproblem: block Jacobi with approximate
   // subproblem solutions needs about as many outer sweeps as with exact ones
@@ -558,11 +583,8 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
 Err select_positive(const c128* G, const c128* V, int k, int kp, c128* Ysel, double* dlam, DenseWs& ws,
                     hipStream_t s, int* npos, int* nneg) {
   // tiny: 1e3 * u * max|theta| bounded by the Frobenius norm
-  hipLaunchKernelGGL(frob_kernel, dim3(1), dim3(256), 0, s, G, (int64_t)kp, kp, ws.dscalar);
-  CHASE_LAUNCH_CHECK();
   double fro = 0;
-  CHASE_HIP(hipMemcpyAsync(&fro, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
-  CHASE_HIP(hipStreamSynchronize(s));
+  CHASE_TRY(frob_norm(G, kp, ws, s, &fro));
   const double tiny = 1e3 * 1.1102230246251565e-16 * fro;
   CHASE_HIP(hipMemsetAsync(ws.flag, 0, 2 * sizeof(int), s));
   CHASE_HIP(hipMemsetAsync(Ysel, 0, (size_t)kp * (k / 2) * sizeof(c128), s));

@@ -13,7 +13,11 @@ Err make_shadow(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, 
 Err scale_lower_half(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g,
                      hipStream_t s);
 Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* dlam, int64_t n, int kk,
-                   double* dres, hipStream_t s);
+                   double* dres, c128* R, int64_t ldr, hipStream_t s);
+Err scale_c64(const c64* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, float a, hipStream_t s);
+// W[:, j] = pw[j] W[:, j] + ce D[:, j]  (pw device, k values)
+Err combine_correction(c128* W, int64_t ldw, const c64* D, int64_t ldd, const double* dpw, double ce, int64_t n, int k,
+                       hipStream_t s);
 Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s);
 Err lanczos_residual(const c128* w, const c128* v, const c128* vp, c128* r, int64_t ld, int64_t n, int nv,
                      const double* alpha, const double* beta_prev, hipStream_t s);

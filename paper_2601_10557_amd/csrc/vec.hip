@@ -97,9 +97,10 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-// Per column j: nu = ||V_j||, r_j = ||TZ_j - lam_j V_j|| / nu, V_j /= nu.
+// Per column j: nu = ||V_j||, r_j = ||TZ_j - lam_j V_j|| / nu, V_j /= nu;
+// optionally the residual vector of the unit Ritz vector, (TZ_j - lam_j V_j) / nu.
 __global__ __launch_bounds__(256) void resid_kernel(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* lam,
-                                                    int64_t n, double* resid) {
+                                                    int64_t n, double* resid, c128* R, int64_t ldr) {
   __shared__ double red[256];
   const int j = blockIdx.x;
   c128* v = V + (int64_t)j * ldv;
@@ -116,8 +117,13 @@ __global__ __launch_bounds__(256) void resid_kernel(c128* V, int64_t ldv, const 
   const double rr2 = block_sum(s2, red);
   const double nu = sqrt(nu2);
   const double inv = nu > 0 ? 1.0 / nu : 0.0;
+  c128* rv = R ? R + (int64_t)j * ldr : nullptr;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     c128 a = v[i];
+    if (rv) {
+      const c128 b = tz[i];
+      rv[i] = c128{(b.re - l * a.re) * inv, (b.im - l * a.im) * inv};
+    }
     v[i] = c128{a.re * inv, a.im * inv};
   }
   if (threadIdx.x == 0) resid[j] = sqrt(rr2) * inv;
@@ -216,7 +222,45 @@ __global__ void gather_cols_kernel(const c128* src, int64_t lds, c128* dst, int6
   }
 }
 
+// W[:, j] = pw[j] W[:, j] + ce D[:, j]   (W c128 in place, D c64)
+__global__ void combine_kernel(c128* W, int64_t ldw, const c64* D, int64_t ldd, const double* pw, double ce, int64_t n,
+                               int k) {
+  const int64_t total = n * k;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / n);
+    const int64_t i = t % n;
+    const double p = pw[j];
+    c128 w = W[(int64_t)j * ldw + i];
+    const c64 d = D[(int64_t)j * ldd + i];
+    W[(int64_t)j * ldw + i] = c128{p * w.re + ce * (double)d.re, p * w.im + ce * (double)d.im};
+  }
+}
+
+__global__ void scale_c64_kernel(const c64* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, float a) {
+  const int64_t total = rows * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / rows, i = t % rows;
+    const c64 z = src[j * lds + i];
+    dst[j * ldd + i] = c64{a * z.re, a * z.im};
+  }
+}
+
 }  // namespace
+
+Err scale_c64(const c64* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, float a, hipStream_t s) {
+  if (rows * cols == 0) return ok();
+  hipLaunchKernelGGL(scale_c64_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, a);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err combine_correction(c128* W, int64_t ldw, const c64* D, int64_t ldd, const double* dpw, double ce, int64_t n, int k,
+                       hipStream_t s) {
+  if (k == 0) return ok();
+  hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n * k)), dim3(256), 0, s, W, ldw, D, ldd, dpw, ce, n, k);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
 
 Err build_search_block(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx,
                        int64_t m, hipStream_t s) {
@@ -257,9 +301,9 @@ Err scale_lower_half(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64
 }
 
 Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* dlam, int64_t n, int kk,
-                   double* dres, hipStream_t s) {
+                   double* dres, c128* R, int64_t ldr, hipStream_t s) {
   if (kk == 0) return ok();
-  hipLaunchKernelGGL(resid_kernel, dim3(kk), dim3(256), 0, s, V, ldv, TZ, ldt, dlam, n, dres);
+  hipLaunchKernelGGL(resid_kernel, dim3(kk), dim3(256), 0, s, V, ldv, TZ, ldt, dlam, n, dres, R, ldr);
   CHASE_LAUNCH_CHECK();
   return ok();
 }

@@ -14,6 +14,8 @@ namespace {
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 constexpr int LDS_A = BM + 2, LDS_B = BN + 2;
 
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -50,22 +52,24 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
   const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
 
   constexpr int PER = BM * BK / NT;  // 4 elements of each operand per thread
-  double ar[PER], ai[PER], br[PER], bi[PER];
+  // raw loads (clamped addresses) plus validity bits; conj / sign are applied
+  // when the tile is written to LDS, after the MFMAs of the previous slab
+  doublex2 ra[PER], rb[PER];
+  unsigned okA = 0, okB = 0, negB = 0;
 
   auto load = [&](int kt) {
     const int64_t k0 = kbeg + (int64_t)kt * BK;
+    okA = okB = negB = 0;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int el = tid + e * NT;
       int i, kk;
       if (g.transA == 0) { kk = el / BM; i = el % BM; } else { i = el / BK; kk = el % BK; }
       const int64_t gi = m0 + i, gk = k0 + kk;
-      double vr = 0, vi = 0;
-      if (gi < g.M && gk < kend) {
-        if (g.transA == 0) { c128 z = A[gk * g.lda + gi]; vr = z.re; vi = z.im; }
-        else { c128 z = A[gi * g.lda + gk]; vr = z.re; vi = -z.im; }
-      }
-      ar[e] = vr; ai[e] = vi;
+      const bool ok = gi < g.M && gk < kend;
+      const int64_t idx = ok ? (g.transA == 0 ? gk * g.lda + gi : gi * g.lda + gk) : 0;
+      ra[e] = *reinterpret_cast<const doublex2*>(A + idx);
+      if (ok) okA |= 1u << e;
     }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -73,31 +77,33 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
       int j, kk;
       if (g.transB == 0) { j = el / BK; kk = el % BK; } else { kk = el / BN; j = el % BN; }
       const int64_t gj = n0 + j, gk = k0 + kk;
-      double vr = 0, vi = 0;
-      if (gj < g.N && gk < kend) {
-        if (g.transB == 0) { c128 z = B[gj * g.ldb + gk]; vr = z.re; vi = z.im; }
-        else { c128 z = B[gk * g.ldb + gj]; vr = z.re; vi = -z.im; }
-        if (gk >= g.kneg) { vr = -vr; vi = -vi; }
-      }
-      br[e] = vr; bi[e] = vi;
+      const bool ok = gj < g.N && gk < kend;
+      const int64_t idx = ok ? (g.transB == 0 ? gj * g.ldb + gk : gk * g.ldb + gj) : 0;
+      rb[e] = *reinterpret_cast<const doublex2*>(B + idx);
+      if (ok) okB |= 1u << e;
+      if (gk >= g.kneg) negB |= 1u << e;
     }
   };
   auto store = [&](int buf) {
+    const double ca = g.transA ? -1.0 : 1.0, cb = g.transB ? -1.0 : 1.0;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int el = tid + e * NT;
       int i, kk;
       if (g.transA == 0) { kk = el / BM; i = el % BM; } else { i = el / BK; kk = el % BK; }
-      As[buf][0][kk][i] = ar[e];
-      As[buf][1][kk][i] = ai[e];
+      const bool ok = (okA >> e) & 1u;
+      As[buf][0][kk][i] = ok ? ra[e][0] : 0.0;
+      As[buf][1][kk][i] = ok ? ra[e][1] * ca : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int el = tid + e * NT;
       int j, kk;
       if (g.transB == 0) { j = el / BK; kk = el % BK; } else { kk = el / BN; j = el % BN; }
-      Bs[buf][0][kk][j] = br[e];
-      Bs[buf][1][kk][j] = bi[e];
+      const bool ok = (okB >> e) & 1u;
+      const double sg = ((negB >> e) & 1u) ? -1.0 : 1.0;
+      Bs[buf][0][kk][j] = ok ? rb[e][0] * sg : 0.0;
+      Bs[buf][1][kk][j] = ok ? rb[e][1] * cb * sg : 0.0;
     }
   };
 

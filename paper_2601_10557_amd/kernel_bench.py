@@ -1,0 +1,71 @@
+"""Microbenchmark of the block-structured H X kernel through the C ABI.
+
+    python -m paper_2601_10557_amd.kernel_bench --m 4000 --k 260 [--prec c64|c128|both]
+        [--reps 5] [--calib-copy-mib 1024]
+
+Prints one line per (precision, k) with the best per-launch time (HIP events
+on the library's stream), TFLOP/s at 8 n^2 k flops per launch and the
+algorithmic GB/s.  ``--calib-copy-mib`` first runs a plain device-to-device
+copy of that many MiB, a reference dispatch of known traffic for hardware
+counter calibration.  Random Hermitian A and symmetric B are drawn on the
+device; no parity is checked here (see tests/).
+"""
+from __future__ import annotations
+
+import argparse
+
+import torch
+
+from . import FP32, FP64, PHSolver, colmajor, empty_cm
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--m", type=int, default=4000)
+    ap.add_argument("--k", type=str, default="260")
+    ap.add_argument("--prec", choices=["c64", "c128", "both"], default="both")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--calib-copy-mib", type=int, default=0)
+    args = ap.parse_args(argv)
+    ks = [int(x) for x in args.k.split(",")]
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written", flush=True)
+        del src, dst
+    m, n = args.m, 2 * args.m
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    A = torch.randn(m, m, dtype=torch.complex128, device="cuda", generator=g)
+    A = 0.5 * (A + A.conj().T.contiguous())
+    B = torch.randn(m, m, dtype=torch.complex128, device="cuda", generator=g)
+    B = 0.5 * (B + B.T.contiguous())
+    kmax = max(ks)
+    s = PHSolver(A, B, min(kmax // 2 + 8, m // 2), kmax // 2 + 8)
+    precs = {"c64": [(FP32, torch.complex64)], "c128": [(FP64, torch.complex128)],
+             "both": [(FP32, torch.complex64), (FP64, torch.complex128)]}[args.prec]
+    for prec, dt in precs:
+        name = "c64" if prec == FP32 else "c128"
+        peak = 157.3 if prec == FP32 else 78.6
+        elem = 8 if prec == FP32 else 16
+        for k in ks:
+            X = colmajor(torch.randn(n, k, dtype=dt, device="cuda", generator=g))
+            Y = empty_cm(n, k, dt)
+            best = 1e30
+            for _ in range(args.reps + 1):
+                s.apply_h(X, Y, prec=prec)
+                best = min(best, s.last_timing()[0])
+            fl = 8.0 * n * n * k
+            by = (2.0 * m * m + 2.0 * n * k) * elem
+            print(f"{name} m={m} k={k}: {best * 1e3:.1f} us  {fl / best / 1e9:.2f} TFLOP/s "
+                  f"({fl / best / 1e9 / peak * 100:.1f}% of {peak})  {by / best / 1e6:.1f} GB/s algorithmic",
+                  flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

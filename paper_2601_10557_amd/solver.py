@@ -178,6 +178,23 @@ class PHSolver:
         self._check(lib().chase_ph_filter(self._h, k, _ptr(W), _ld(W), dp, mu1, mu_nevex, mu_n, prec))
         return W
 
+    def filter_refined(self, W: torch.Tensor, R: torch.Tensor, lam, mu1: float, mu_nevex: float,
+                       mu_n: float, degs: Optional[Sequence[int]] = None):
+        """In place W <- p(H^2) W for unit Ritz vectors W with Ritz values lam and
+        residuals R = H W - W diag(lam): c64 products, FP64 refinement."""
+        assert W.stride(0) == 1
+        R = colmajor(R)
+        k = W.shape[1]
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+        dp = None
+        if degs is not None:
+            arr = (C.c_int32 * k)(*[int(x) for x in degs])
+            dp = C.cast(arr, C.POINTER(C.c_int32))
+        self._check(lib().chase_ph_filter_refined(
+            self._h, k, _ptr(W), _ld(W), _ptr(R), _ld(R), lam.ctypes.data_as(C.POINTER(C.c_double)), dp,
+            mu1, mu_nevex, mu_n))
+        return W
+
     def qr(self, X: torch.Tensor, want_r: bool = True):
         """In place CholeskyQR2 of X (n x k c128, column-major); returns (R, shifted)."""
         assert X.stride(0) == 1

@@ -95,6 +95,30 @@ def test_filter_fp32(prob, solver):
     assert np.max(err) < 1e-4, err
 
 
+@pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-8])
+def test_filter_refined_accuracy_tracks_the_residual(prob, solver, eps):
+    # c64 products + FP64 refinement: the error is relative to the
+    # correction term, so near-eigenvectors are filtered to FP64 accuracy
+    # while the plain c64 filter stays at ~1e-6 relative.
+    print_case("filter_refined", m=prob.m, eps=eps)
+    lam, Vp = dense.dense_ph_eig(prob.A, prob.B)
+    mu1, mu_nevex, mu_n = _mus(prob)
+    rng = np.random.default_rng(11)
+    k = 6
+    V = Vp[:, :k] + eps * complex_normal(rng, (prob.n, k))
+    V = V / np.linalg.norm(V, axis=0)[None, :]
+    HV = ham.apply_h(prob.A, prob.B, V)
+    lr = np.real(np.einsum("ij,ij->j", V.conj(), HV))
+    R = HV - V * lr[None, :]
+    degs = [2, 5, 5, 8, 12, 12]
+    ref = chebyshev.chebyshev_filter(prob.A, prob.B, V, np.array(degs), mu1, mu_nevex, mu_n)
+    Wd = to_dev(V)
+    solver.filter_refined(Wd, to_dev(R), lr, mu1, mu_nevex, mu_n, degs=degs)
+    got = to_host(Wd)
+    err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.max(err) < 1e-3 * eps + 1e-12, err
+
+
 def test_filter_kconj_equivariance(prob, solver):
     # Thm 4.2 on the device path
     mu1, mu_nevex, mu_n = _mus(prob)
