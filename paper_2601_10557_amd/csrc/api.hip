@@ -923,6 +923,8 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   h->ws_bytes = std::max(kp2 * sizeof(c128) * 8, (size_t)8 * h->m * h->kmax * sizeof(c128));
   h->ws_bytes = std::min<size_t>((size_t)1 << 30, std::max<size_t>((size_t)16 << 20, h->ws_bytes));
   CHASE_TRY(dalloc(h, (char**)&h->ws, h->ws_bytes));
+  h->dws.gemm_ws = h->ws;
+  h->dws.gemm_ws_bytes = h->ws_bytes;
   if (p->precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
   return ok();
 }

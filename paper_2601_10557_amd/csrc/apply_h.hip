@@ -48,6 +48,22 @@ struct TF32 {
   }
 };
 
+// Same FP32 rate on 16 x 16 output blocks (k = 4 per MFMA): lets the N tile
+// follow 2k in steps of 16 columns instead of 32 or 64.
+struct TF32S {
+  using R = float;
+  using C = c64;
+  using Acc = floatx4;
+  static constexpr int MB = 16, NB = 16, KB = 4, NACC = 4;
+  __device__ static int a_row(int l) { return l & 15; }
+  __device__ static int a_k(int l) { return l >> 4; }
+  __device__ static int acc_row(int r, int l) { return 4 * (l >> 4) + r; }
+  __device__ static int acc_col(int l) { return l & 15; }
+  __device__ static Acc mfma(R a, R b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
 struct TF64 {
   using R = double;
   using C = c128;
@@ -91,7 +107,12 @@ struct Cfg {
   static constexpr int VEC = sizeof(R) == 4 ? 2 : 1;   // complex per A load
   static constexpr int ACHUNK = BM * BK / VEC / NT;     // A loads per thread
   static constexpr int BCHUNK = BK * BN / VB / NT;      // B loads per thread
-  static constexpr int LDA_S = BM + 4, LDB_S = BN + 4;
+  // LDS row pitch: fragment reads of the FP32 16-row MFMA take four k rows
+  // of 16 words, conflict-free when the pitch is 16 mod 32 words; the other
+  // shapes keep a pad of 4 elements (measured best for them).
+  static constexpr bool kF32x16 = sizeof(R) == 4 && Tr::MB == 16;
+  static constexpr int pitch(int x) { return kF32x16 ? x + ((16 - x % 32) + 32) % 32 : x + 4; }
+  static constexpr int LDA_S = pitch(BM), LDB_S = pitch(BN);
   static_assert(BM * BK % (VEC * NT) == 0, "A tile split");
   static_assert(BK * BN % (VB * NT) == 0, "B tile split");
   static_assert(BK % Tr::KB == 0, "BK");
@@ -348,11 +369,14 @@ struct Plan {
 };
 
 // Pick the tile shape and K split that minimise (rounds of 256 workgroups)
-// x (K slabs per workgroup) x (outputs per tile), with a mild preference for
-// fewer splits (each split costs a partial-sum write and read).
+// x (K slabs per workgroup) x (outputs per tile) / (relative MFMA efficiency
+// of the shape) x (1 + split_penalty per extra split: each split costs a
+// partial-sum write and read).  The efficiencies of the c64 shapes were
+// fitted to a sweep of every shape and split over 2k = 32 ... 520 on the
+// m = 4000 workload (the fitted plans came within 2% of the fastest ones).
 template <int NCFG>
 Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG], const int (&bk)[NCFG],
-               size_t elem, size_t ws_bytes) {
+               const double (&eff)[NCFG], double split_penalty, size_t elem, size_t ws_bytes) {
   const int64_t slots = 256;
   Plan best{0, 1, 1, 0};
   double best_cost = 1e300;
@@ -364,7 +388,7 @@ Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCF
       const int64_t kps = ceil_div(kt, s);
       const int64_t real_s = ceil_div(kt, kps);
       const int64_t rounds = ceil_div(tiles * real_s, slots);
-      const double cost = (double)rounds * kps * bk[c] * bm[c] * bn[c] * (1.0 + 0.02 * (real_s - 1));
+      const double cost = (double)rounds * kps * bk[c] * bm[c] * bn[c] * (1.0 + split_penalty * (real_s - 1)) / eff[c];
       if (cost < best_cost * 0.999) {
         best_cost = cost;
         best = Plan{c, (int)real_s, (int)kps, tiles};
@@ -378,8 +402,8 @@ template <typename Tr, int BM, int BN, int BK, int WGM, int WGN, int VB>
 Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hipStream_t s) {
   using C = typename Tr::C;
   const int64_t grid = p.tiles * p.splits;
-  hipLaunchKernelGGL((apply_h_kernel<Tr, BM, BN, BK, WGM, WGN, VB>), dim3((unsigned)grid), dim3(64 * WGM * WGN), 0, s,
-                     a, p.splits, p.kps, (C*)ws);
+  hipLaunchKernelGGL((apply_h_kernel<Tr, BM, BN, BK, WGM, WGN, VB>), dim3((unsigned)grid), dim3(64 * WGM * WGN), 0,
+                     s, a, p.splits, p.kps, (C*)ws);
   CHASE_LAUNCH_CHECK();
   if (p.splits > 1) {
     const int64_t total = a.m * 2 * (int64_t)a.k;
@@ -410,21 +434,36 @@ void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const 
 
 Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
-  static const int bm[2] = {128, 256}, bn[2] = {128, 64}, bk[2] = {32, 16};
+  // 0, 1: 32 x 32 MFMA tiles; 2, 3: 16 x 16 MFMA tiles whose widths let the
+  // plan cover N = 2k with less padding (N is rounded up to the tile width).
+  // Wider 16 x 16 tiles need more accumulators than one wave can hold
+  // without spilling into extra register moves and were slower.
+  static const int bm[4] = {128, 256, 256, 256};
+  static const int bn[4] = {128, 64, 32, 48};
+  static const int bk[4] = {32, 16, 16, 16};
+  static const double eff[4] = {0.9, 1.0, 0.9, 0.97};
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<2>(a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
-  plan_override<2>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  Plan p = make_plan<4>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, 0.0, sizeof(c64), wsb);
+  plan_override<4>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
   const bool vb2 = (a.m % 2 == 0) && (a.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0);
-  if (p.cfg == 0)
-    return vb2 ? launch_cfg<TF32, 128, 128, 32, 2, 2, 2>(a, p, ws, s) : launch_cfg<TF32, 128, 128, 32, 2, 2, 1>(a, p, ws, s);
-  return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s) : launch_cfg<TF32, 256, 64, 16, 4, 1, 1>(a, p, ws, s);
+  switch (p.cfg) {
+    case 0:
+      return vb2 ? launch_cfg<TF32, 128, 128, 32, 2, 2, 2>(a, p, ws, s)
+                 : launch_cfg<TF32, 128, 128, 32, 2, 2, 1>(a, p, ws, s);
+    case 1:
+      return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s)
+                 : launch_cfg<TF32, 256, 64, 16, 4, 1, 1>(a, p, ws, s);
+    case 2: return launch_cfg<TF32S, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
+    default: return launch_cfg<TF32S, 256, 48, 16, 4, 1, 1>(a, p, ws, s);
+  }
 }
 
 Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
   static const int bm[2] = {128, 256}, bn[2] = {64, 32}, bk[2] = {16, 16};
+  static const double eff[2] = {1.0, 1.0};
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<2>(a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
+  Plan p = make_plan<2>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, 0.02, sizeof(c128), wsb);
   plan_override<2>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
   if (p.cfg == 0) return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
   return launch_cfg<TF64, 256, 32, 16, 4, 1, 1>(a, p, ws, s);

@@ -12,6 +12,8 @@ struct DenseWs {
   int* flag = nullptr;     // 4 ints
   int* pflag = nullptr;    // kp_max / 8 ints (Jacobi pair rotated?)
   double* dscalar = nullptr;  // 4 doubles
+  void* gemm_ws = nullptr;     // split-K partials of the batched GEMMs (may be null)
+  size_t gemm_ws_bytes = 0;
 };
 
 int pad64(int k);

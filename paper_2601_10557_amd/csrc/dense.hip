@@ -64,6 +64,28 @@ __device__ __forceinline__ c128 quad_sum(c128 v) {
   return v;
 }
 
+// Sum over l = part, part + 4, ... < lim of x(l) * y(l), the terms read in
+// chunks of four so that their LDS loads are in flight together (all l < 64
+// are valid addresses; terms with l >= lim are masked out).
+template <typename FX, typename FY>
+__device__ __forceinline__ c128 strided_dot(int part, int lo, int lim, FX x, FY y) {
+  c128 sum{0.0, 0.0};
+  for (int t0 = 0; t0 < NB / 4; t0 += 4) {
+    if (lo + part + 4 * t0 >= lim) break;
+    c128 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int l = min(lo + part + 4 * (t0 + u), NB - 1);
+      a[u] = x(l);
+      b[u] = y(l);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lo + part + 4 * (t0 + u) < lim) sum = cadd(sum, cmul(a[u], b[u]));
+  }
+  return sum;
+}
+
 // In place lower Cholesky S = L L^H (left-looking by columns).  A
 // non-positive or non-finite pivot sets *fail and is replaced by 1 so that
 // the block stays finite (the host then discards the result).
@@ -72,7 +94,7 @@ __device__ void chol64(c128 (*S)[NB + 1], int* fail) {
   for (int j = 0; j < NB; ++j) {
     c128 sum{0.0, 0.0};
     if (row >= j)
-      for (int l = part; l < j; l += 4) sum = cadd(sum, cmul(S[row][l], cconj(S[j][l])));
+      sum = strided_dot(part, 0, j, [&](int l) { return S[row][l]; }, [&](int l) { return cconj(S[j][l]); });
     sum = quad_sum(sum);
     if (row == j && part == 0) {
       double d = S[j][j].re - sum.re;
@@ -98,8 +120,7 @@ __device__ void trinv64(c128 (*S)[NB + 1], c128 (*I)[NB + 1]) {
       if (part == 0) I[i][c] = c128{0.0, 0.0};
       continue;
     }
-    c128 sum{0.0, 0.0};
-    for (int l = c + part; l < i; l += 4) sum = cadd(sum, cmul(S[i][l], I[l][c]));
+    c128 sum = strided_dot(part, c, i, [&](int l) { return S[i][l]; }, [&](int l) { return I[l][c]; });
     sum = quad_sum(sum);
     const c128 rhs = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
     I[i][c] = cscale(1.0 / S[i][i].re, csub(rhs, sum));
@@ -533,7 +554,7 @@ Err tri_inverse_lower(const c128* L, c128* X, int kp, DenseWs& ws, hipStream_t s
     g.B = X; g.ldb = kp; g.strideB = stride;
     g.C = ws.tmp; g.ldc = NB; g.strideC = (int64_t)NB * NB;
     g.kneg = g.K; g.batch = batch;
-    CHASE_TRY(zgemm(g, nullptr, 0, s));
+    CHASE_TRY(zgemm(g, ws.gemm_ws, ws.gemm_ws_bytes, s));  // K = d * 64: split along K
     // X[j+d, j] = -X[j+d, j+d] * T_j
     ZgemmArgs h{};
     h.transA = 0; h.transB = 0;

@@ -224,7 +224,7 @@ Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   int splits = 1;
   if (a.K > 0 && ws && tiles * a.batch < 512) {
     const int64_t want = ceil_div(1024, tiles * a.batch);
-    const int64_t maxk = std::max<int64_t>(1, a.K / (8 * BK));
+    const int64_t maxk = std::max<int64_t>(1, a.K / (4 * BK));  // at least 4 K slabs per split
     int64_t sp = std::min(want, maxk);
     const int64_t per = a.M * a.N * a.batch * (int64_t)sizeof(c128);
     sp = std::min<int64_t>(sp, (int64_t)(ws_bytes / per));

@@ -1,11 +1,13 @@
 """Microbenchmark of the block-structured H X kernel through the C ABI.
 
     python -m paper_2601_10557_amd.kernel_bench --m 4000 --k 260 [--prec c64|c128|both]
-        [--reps 5] [--calib-copy-mib 1024]
+        [--reps 5] [--calib-copy-mib 1024] [--plans "cfg,splits;cfg,splits;..."]
 
 Prints one line per (precision, k) with the best per-launch time (HIP events
 on the library's stream), TFLOP/s at 8 n^2 k flops per launch and the
-algorithmic GB/s.  ``--calib-copy-mib`` first runs a plain device-to-device
+algorithmic GB/s.  ``--plans`` repeats each measurement with the tile plan
+forced through ``CHASE_PH_APPLY_PLAN`` (a tuning aid; "auto" is the
+library's own choice).  ``--calib-copy-mib`` first runs a plain device-to-device
 copy of that many MiB, a reference dispatch of known traffic for hardware
 counter calibration.  Random Hermitian A and symmetric B are drawn on the
 device; no parity is checked here (see tests/).
@@ -13,6 +15,7 @@ device; no parity is checked here (see tests/).
 from __future__ import annotations
 
 import argparse
+import os
 
 import torch
 
@@ -26,6 +29,7 @@ def main(argv=None):
     ap.add_argument("--prec", choices=["c64", "c128", "both"], default="both")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--calib-copy-mib", type=int, default=0)
+    ap.add_argument("--plans", type=str, default="auto")
     args = ap.parse_args(argv)
     ks = [int(x) for x in args.k.split(",")]
     if args.calib_copy_mib > 0:
@@ -55,15 +59,21 @@ def main(argv=None):
         for k in ks:
             X = colmajor(torch.randn(n, k, dtype=dt, device="cuda", generator=g))
             Y = empty_cm(n, k, dt)
-            best = 1e30
-            for _ in range(args.reps + 1):
-                s.apply_h(X, Y, prec=prec)
-                best = min(best, s.last_timing()[0])
-            fl = 8.0 * n * n * k
-            by = (2.0 * m * m + 2.0 * n * k) * elem
-            print(f"{name} m={m} k={k}: {best * 1e3:.1f} us  {fl / best / 1e9:.2f} TFLOP/s "
-                  f"({fl / best / 1e9 / peak * 100:.1f}% of {peak})  {by / best / 1e6:.1f} GB/s algorithmic",
-                  flush=True)
+            for plan in args.plans.split(";"):
+                if plan == "auto":
+                    os.environ.pop("CHASE_PH_APPLY_PLAN", None)
+                else:
+                    os.environ["CHASE_PH_APPLY_PLAN"] = plan
+                best = 1e30
+                for _ in range(args.reps + 1):
+                    s.apply_h(X, Y, prec=prec)
+                    best = min(best, s.last_timing()[0])
+                fl = 8.0 * n * n * k
+                by = (2.0 * m * m + 2.0 * n * k) * elem
+                print(f"{name} m={m} k={k} plan={plan}: {best * 1e3:.1f} us  {fl / best / 1e9:.2f} TFLOP/s "
+                      f"({fl / best / 1e9 / peak * 100:.1f}% of {peak})  {by / best / 1e6:.1f} GB/s algorithmic",
+                      flush=True)
+            os.environ.pop("CHASE_PH_APPLY_PLAN", None)
     s.close()
 
 
