@@ -56,11 +56,21 @@ __global__ void zero_upper_kernel(c128* M, int64_t ld, int kp) {
 // ------------------------------------------------------- Cholesky block
 // 64 x 64 blocks held in LDS, 256 threads.  Dot products of length up to 63
 // are split over 4 consecutive lanes and combined with lane shuffles.
+// Lane exchange inside a quad of lanes by DPP quad_perm (no LDS round
+// trip): 0xB1 swaps lanes 0<->1 and 2<->3, 0x4E swaps 0<->2 and 1<->3.
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ c128 quad_sum(c128 v) {
-  v.re += __shfl_xor(v.re, 1);
-  v.im += __shfl_xor(v.im, 1);
-  v.re += __shfl_xor(v.re, 2);
-  v.im += __shfl_xor(v.im, 2);
+  v.re += quad_swap<0xB1>(v.re);
+  v.im += quad_swap<0xB1>(v.im);
+  v.re += quad_swap<0x4E>(v.re);
+  v.im += quad_swap<0x4E>(v.im);
   return v;
 }
 
@@ -178,22 +188,24 @@ __global__ __launch_bounds__(256) void trinv_diag_kernel(const c128* L, c128* X,
 
 // ------------------------------------------------------------- Jacobi
 // Complex Jacobi rotation J = [[c, s], [-conj(s), c]] that diagonalises
-// [[a, b], [conj(b), d]] (a, d real):  with b = |b| e^{i phi},
-// tau = (d - a) / (2 |b|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
-// c = 1 / sqrt(1 + t^2), s = t c e^{i phi}  (Golub & Van Loan, symmetric
-// Schur 2x2, conjugated by diag(1, e^{-i phi})).
+// Rotation annihilating b in [[a, b], [conj(b), d]] (a, d real).  With
+// x = d - a and the classical t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// tau = x / (2|b|) (Golub & Van Loan, symmetric Schur 2x2, conjugated by
+// diag(1, e^{-i arg b})), write t = tp |b| with
+//   tp = 2 sign(x) / (|x| + sqrt(x^2 + 4|b|^2)),
+// so that c = 1 / sqrt(1 + tp^2 |b|^2), s = tp c b and the diagonal shift
+// t |b| = tp |b|^2 need no |b| itself (two square roots and two divisions).
 __device__ __forceinline__ void jacobi_rot(double a, double d, c128 b, double thr, double& c, c128& s, double& t_out, int& did) {
-  const double ab = hypot(b.re, b.im);
-  if (!(ab > thr)) {
+  const double nb2 = b.re * b.re + b.im * b.im;
+  if (!(nb2 > thr * thr)) {
     c = 1.0; s = c128{0.0, 0.0}; t_out = 0.0; did = 0;
     return;
   }
-  const double tau = (d - a) / (2.0 * ab);
-  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
-  const double sr = t * c;
-  s = c128{sr * b.re / ab, sr * b.im / ab};
-  t_out = t * ab;
+  const double x = d - a;
+  const double tp = (x >= 0.0 ? 2.0 : -2.0) / (fabs(x) + sqrt(x * x + 4.0 * nb2));
+  c = 1.0 / sqrt(1.0 + tp * tp * nb2);
+  s = c128{tp * c * b.re, tp * c * b.im};
+  t_out = tp * nb2;
   did = 1;
 }
 
@@ -204,106 +216,91 @@ __device__ __forceinline__ int rr_player(int pos, int r, int n) {
   return ((pos - 1 + r) % (n - 1)) + 1;
 }
 
-// Solve one 64 x 64 subproblem [[G_pp, G_pq], [G_qp, G_qq]] to convergence
-// by cyclic Jacobi in LDS; write the accumulated unitary U (64 x 64) to
-// Uw[pair] and count significant rotations in *count.
-__global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t ld, int nbj, int round,
-                                                         c128* Uw, double thr, int max_sweeps, int* count,
-                                                         int* pflag) {
-  __shared__ c128 S[SP][SP + 1];
+// One cyclic Jacobi sweep on the 32 x 32 subproblem [[G_pp, G_pq],
+// [G_qp, G_qq]] of pair `pair` in round `round`: 31 steps of 16 disjoint
+// rotations (round-robin pairing).  Thread (a, b) = (tid % 16, tid / 16)
+// owns the 2 x 2 block of rotation a's rows and rotation b's columns and
+// rows b, b + 16 of rotation a's two columns of the accumulated unitary.
+// Every lane computes rotation a = lane % 16 from the step's input matrix
+// and takes rotation b from lane b of its own wave by a lane shuffle; the
+// matrix is double-buffered in LDS, so a step needs one barrier.  Writes U (32 x 32, column-major) to
+// Uw[pair] and flags the pair in pflag when it rotated; *count counts the
+// pairs that rotated.  A subproblem whose off-diagonal entries are all at or
+// below thr is left alone (U = I is implied by pflag = 0).
+__global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t ld, int nbj, int round, c128* Uw,
+                                                         double thr, int max_sweeps, int* count, int* pflag) {
+  __shared__ c128 S[2][SP][SP + 1];
   __shared__ c128 U[SP][SP + 1];
-  __shared__ double rc[SP / 2];
-  __shared__ c128 rs[SP / 2];
-  __shared__ double rt[SP / 2];
-  __shared__ int any;
   const int pair = blockIdx.x;
   const int tid = threadIdx.x;
   const int bp = rr_player(pair, round, nbj), bq = rr_player(nbj - 1 - pair, round, nbj);
   const int P = min(bp, bq) * JB, Q = max(bp, bq) * JB;
+  int big = 0;
   for (int t = tid; t < SP * SP; t += 256) {
     const int j = t / SP, i = t % SP;
     const int gi = i < JB ? P + i : Q + i - JB;
     const int gj = j < JB ? P + j : Q + j - JB;
-    S[i][j] = G[(int64_t)gj * ld + gi];
+    const c128 g = G[(int64_t)gj * ld + gi];
+    S[0][i][j] = g;
     U[i][j] = (i == j) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+    if (i != j && g.re * g.re + g.im * g.im > thr * thr) big = 1;
   }
-  if (tid == 0) any = 0;
-  __syncthreads();
-  // nothing to rotate: leave U = I and let the apply kernel skip this pair
-  for (int t = tid; t < SP * SP; t += 256) {
-    const int j = t / SP, i = t % SP;
-    if (i != j && hypot(S[i][j].re, S[i][j].im) > thr) any = 1;
-  }
-  __syncthreads();
-  const int needed = any;
-  __syncthreads();
+  const bool needed = __syncthreads_or(big);
+  const int a = tid % (SP / 2), b = tid / (SP / 2);
   int total = 0;
-  if (!needed) max_sweeps = 0;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) any = 0;
-    __syncthreads();
+  for (int sweep = 0; needed && sweep < max_sweeps; ++sweep) {
+    int did_any = 0;
     for (int r = 0; r < SP - 1; ++r) {
-      if (tid < SP / 2) {
-        const int p = rr_player(tid, r, SP), q = rr_player(SP - 1 - tid, r, SP);
-        const int lo = min(p, q), hi = max(p, q);
-        double c, t;
-        c128 s;
-        int did;
-        jacobi_rot(S[lo][lo].re, S[hi][hi].re, S[lo][hi], thr, c, s, t, did);
-        rc[tid] = c;
-        rs[tid] = s;
-        rt[tid] = t;
-        if (did) any = 1;
-      }
-      __syncthreads();
-      // S <- J^H S J on 2x2 blocks (pair a rows, pair b cols)
-      for (int t = tid; t < (SP / 2) * (SP / 2); t += 256) {
-        const int a = t / (SP / 2), b = t % (SP / 2);
-        const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
-        const int pb0 = rr_player(b, r, SP), qb0 = rr_player(SP - 1 - b, r, SP);
-        const int pa = min(pa0, qa0), qa = max(pa0, qa0), pb = min(pb0, qb0), qb = max(pb0, qb0);
-        const double ca = rc[a], cb = rc[b];
-        const c128 sa = rs[a], sb = rs[b];
-        c128 x00 = S[pa][pb], x01 = S[pa][qb], x10 = S[qa][pb], x11 = S[qa][qb];
-        // rows: row_p' = c row_p - s row_q ; row_q' = conj(s) row_p + c row_q
-        c128 y00 = csub(cscale(ca, x00), cmul(sa, x10));
-        c128 y01 = csub(cscale(ca, x01), cmul(sa, x11));
-        c128 y10 = cadd(cmul(cconj(sa), x00), cscale(ca, x10));
-        c128 y11 = cadd(cmul(cconj(sa), x01), cscale(ca, x11));
-        // cols: col_p' = c col_p - conj(s) col_q ; col_q' = s col_p + c col_q
-        c128 z00 = csub(cscale(cb, y00), cmul(cconj(sb), y01));
-        c128 z01 = cadd(cmul(sb, y00), cscale(cb, y01));
-        c128 z10 = csub(cscale(cb, y10), cmul(cconj(sb), y11));
-        c128 z11 = cadd(cmul(sb, y10), cscale(cb, y11));
-        if (a == b) {
-          if (rt[a] != 0.0) {
-            z00 = c128{S[pa][pa].re - rt[a], 0.0};
-            z11 = c128{S[qa][qa].re + rt[a], 0.0};
-            z01 = c128{0.0, 0.0};
-            z10 = c128{0.0, 0.0};
-          } else {
-            z00.im = 0.0;
-            z11.im = 0.0;
-          }
+      const c128 (*cur)[SP + 1] = S[r & 1];
+      c128 (*nxt)[SP + 1] = S[(r + 1) & 1];
+      const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
+      const int pb0 = rr_player(b, r, SP), qb0 = rr_player(SP - 1 - b, r, SP);
+      const int pa = min(pa0, qa0), qa = max(pa0, qa0), pb = min(pb0, qb0), qb = max(pb0, qb0);
+      double ca, ta;
+      c128 sa;
+      int da;
+      jacobi_rot(cur[pa][pa].re, cur[qa][qa].re, cur[pa][qa], thr, ca, sa, ta, da);
+      did_any |= da;
+      // rotation b was computed by lane b of this wave (lane % 16 == b)
+      const double cb = __shfl(ca, b);
+      const c128 sb{__shfl(sa.re, b), __shfl(sa.im, b)};
+      const c128 x00 = cur[pa][pb], x01 = cur[pa][qb], x10 = cur[qa][pb], x11 = cur[qa][qb];
+      // rows: row_p' = c row_p - s row_q ; row_q' = conj(s) row_p + c row_q
+      const c128 y00 = csub(cscale(ca, x00), cmul(sa, x10));
+      const c128 y01 = csub(cscale(ca, x01), cmul(sa, x11));
+      const c128 y10 = cadd(cmul(cconj(sa), x00), cscale(ca, x10));
+      const c128 y11 = cadd(cmul(cconj(sa), x01), cscale(ca, x11));
+      // cols: col_p' = c col_p - conj(s) col_q ; col_q' = s col_p + c col_q
+      c128 z00 = csub(cscale(cb, y00), cmul(cconj(sb), y01));
+      c128 z01 = cadd(cmul(sb, y00), cscale(cb, y01));
+      c128 z10 = csub(cscale(cb, y10), cmul(cconj(sb), y11));
+      c128 z11 = cadd(cmul(sb, y10), cscale(cb, y11));
+      if (a == b) {
+        if (ta != 0.0) {
+          z00 = c128{x00.re - ta, 0.0};
+          z11 = c128{x11.re + ta, 0.0};
+          z01 = c128{0.0, 0.0};
+          z10 = c128{0.0, 0.0};
+        } else {
+          z00.im = 0.0;
+          z11.im = 0.0;
         }
-        S[pa][pb] = z00; S[pa][qb] = z01; S[qa][pb] = z10; S[qa][qb] = z11;
       }
-      // U <- U J
-      for (int t = tid; t < SP * (SP / 2); t += 256) {
-        const int a = t / SP, i = t % SP;
-        const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
-        const int pa = min(pa0, qa0), qa = max(pa0, qa0);
-        const double ca = rc[a];
-        const c128 sa = rs[a];
+      nxt[pa][pb] = z00;
+      nxt[pa][qb] = z01;
+      nxt[qa][pb] = z10;
+      nxt[qa][qb] = z11;
+      // U <- U J on the columns of rotation a
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = b + (SP / 2) * v;
         const c128 up = U[i][pa], uq = U[i][qa];
         U[i][pa] = csub(cscale(ca, up), cmul(cconj(sa), uq));
         U[i][qa] = cadd(cmul(sa, up), cscale(ca, uq));
       }
       __syncthreads();
     }
-    const int any_now = any;
-    __syncthreads();
-    if (!any_now) break;
+    if (!__syncthreads_or(did_any)) break;
     ++total;
   }
   if (tid == 0) {
@@ -318,42 +315,48 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
   }
 }
 
-// Index of row/col i (0..63) of the subproblem of pair `pair` in round `round`.
+// Index of row/col i (0..2*JB-1) of the subproblem of pair `pair` in round `round`.
 __device__ __forceinline__ int sub_index(int pair, int round, int nbj, int i) {
   const int bp = rr_player(pair, round, nbj), bq = rr_player(nbj - 1 - pair, round, nbj);
   const int P = min(bp, bq) * JB, Q = max(bp, bq) * JB;
   return i < JB ? P + i : Q + i - JB;
 }
 
-// G <- J^H G J with J block-diagonal (one 64 x 64 U per pair, in the pair's
+// G <- J^H G J with J block-diagonal (one 32 x 32 U per pair, in the pair's
 // index set); block (a, b) of pairs is U_a^H G_ab U_b.  Also V <- V J on
-// row chunks of 64.  blockIdx.x < npair^2: G blocks; the rest: V blocks.
+// row chunks of 32.  blockIdx.x < npair^2: G blocks; the rest: V blocks.
+// The rotation blocks are staged in LDS next to the data block.
 __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int64_t ld, int kp, int nbj, int round,
                                                            const c128* Uw, const int* pflag) {
   __shared__ c128 X[SP][SP + 1];
   __shared__ c128 Y[SP][SP + 1];
+  __shared__ c128 UA[SP][SP + 1];
+  __shared__ c128 UB[SP][SP + 1];
   const int npair = nbj / 2;
   const int tid = threadIdx.x;
   const int ti = tid / 16, tj = tid % 16;  // TR x TR outputs per thread
   int blk = blockIdx.x;
   if (blk < npair * npair) {
     const int a = blk / npair, b = blk % npair;
-    if (!pflag[a] && !pflag[b]) return;  // both rotations are the identity
+    const bool ua = pflag[a], ub = pflag[b];
+    if (!ua && !ub) return;  // both rotations are the identity
     const c128* Ua = Uw + (int64_t)a * SP * SP;
     const c128* Ub = Uw + (int64_t)b * SP * SP;
     for (int t = tid; t < SP * SP; t += 256) {
       const int j = t / SP, i = t % SP;
       X[i][j] = G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)];
+      if (ua) UA[i][j] = Ua[t];
+      if (ub) UB[i][j] = Ub[t];
     }
     __syncthreads();
-    const bool ua = pflag[a], ub = pflag[b];
     // Y = X Ub
     c128 acc[TR][TR];
     for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
     if (ub) {
+#pragma unroll 4
       for (int l = 0; l < SP; ++l) {
         c128 u[TR];
-        for (int c = 0; c < TR; ++c) u[c] = Ub[(int64_t)(tj * TR + c) * SP + l];
+        for (int c = 0; c < TR; ++c) u[c] = UB[l][tj * TR + c];
         for (int r = 0; r < TR; ++r) {
           const c128 x = X[ti * TR + r][l];
           for (int c = 0; c < TR; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
@@ -367,9 +370,10 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
     // out = Ua^H Y
     if (ua) {
       for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
+#pragma unroll 4
       for (int l = 0; l < SP; ++l) {
         c128 u[TR];
-        for (int r = 0; r < TR; ++r) u[r] = cconj(Ua[(int64_t)(ti * TR + r) * SP + l]);
+        for (int r = 0; r < TR; ++r) u[r] = cconj(UA[l][ti * TR + r]);
         for (int c = 0; c < TR; ++c) {
           const c128 y = Y[l][tj * TR + c];
           for (int r = 0; r < TR; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
@@ -392,13 +396,15 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
     for (int t = tid; t < SP * SP; t += 256) {
       const int j = t / SP, i = t % SP;
       X[i][j] = V[(int64_t)sub_index(a, round, nbj, j) * ld + r0 + i];
+      UA[i][j] = Ua[t];
     }
     __syncthreads();
     c128 acc[TR][TR];
     for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
+#pragma unroll 4
     for (int l = 0; l < SP; ++l) {
       c128 u[TR];
-      for (int c = 0; c < TR; ++c) u[c] = Ua[(int64_t)(tj * TR + c) * SP + l];
+      for (int c = 0; c < TR; ++c) u[c] = UA[l][tj * TR + c];
       for (int r = 0; r < TR; ++r) {
         const c128 x = X[ti * TR + r][l];
         for (int c = 0; c < TR; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
