@@ -123,9 +123,16 @@ Err h2d(chase_ph_t h, void* dst, const void* src, size_t bytes) {
   return ok();
 }
 
+// Structure flags of gemm(): see ZgemmArgs.
+constexpr int GEMM_LOWER_ONLY = 1, GEMM_A_LOWER = 2, GEMM_B_UPPER = 4;
+
 Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alpha, const c128* A, int64_t lda,
-         const c128* B, int64_t ldb, c128 beta, c128* C, int64_t ldc, int64_t kneg = -1, bool split = true) {
+         const c128* B, int64_t ldb, c128 beta, c128* C, int64_t ldc, int64_t kneg = -1, bool split = true,
+         int flags = 0) {
   ZgemmArgs g{};
+  g.lower_only = (flags & GEMM_LOWER_ONLY) != 0;
+  g.a_lower = (flags & GEMM_A_LOWER) != 0;
+  g.b_upper = (flags & GEMM_B_UPPER) != 0;
   g.transA = ta; g.transB = tb;
   g.M = M; g.N = N; g.K = K;
   g.alpha = alpha; g.beta = beta;
@@ -382,12 +389,13 @@ Err filter_any(chase_ph_t h, int k, void* dW, int64_t ldw, const std::vector<int
 Err cholqr_pass(chase_ph_t h, int k, int kp, const c128* Xin, int64_t ldin, c128* Xout, int64_t ldout, c128* Lbuf,
                 double shift, bool* failed) {
   CHASE_TRY(fill_padded(Lbuf, kp, k, 0.0, 1.0, true, h->st));
-  CHASE_TRY(gemm(h, 1, 0, k, k, h->n, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp));
+  // Gram matrix: the Cholesky reads its lower triangle only
+  CHASE_TRY(gemm(h, 1, 0, k, k, h->n, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp, -1, true, GEMM_LOWER_ONLY));
   if (shift != 0.0) CHASE_TRY(add_diag(Lbuf, kp, k, shift, h->st));
   CHASE_TRY(cholesky_lower(Lbuf, kp, h->dws, h->st, failed));
   if (*failed) return ok();
   CHASE_TRY(tri_inverse_lower(Lbuf, h->Li, kp, h->dws, h->st));
-  return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout);
+  return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout, -1, true, GEMM_B_UPPER);
 }
 
 Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift) {
@@ -404,7 +412,7 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
   } else {
     // shifted CholeskyQR3: s = 11 (n k + k (k + 1)) u ||X||_F^2
     CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
-    CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, X, ldx, X, ldx, {0, 0}, h->G, kp));
+    CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, X, ldx, X, ldx, {0, 0}, h->G, kp, -1, true, GEMM_LOWER_ONLY));
     CHASE_TRY(trace(h->G, kp, k, h->dws.dscalar, h->st));
     double fro2 = 0;
     CHASE_HIP(hipMemcpyAsync(&fro2, h->dws.dscalar, sizeof(double), hipMemcpyDeviceToHost, h->st));
@@ -440,15 +448,18 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
   const int64_t m = h->m, n = h->n;
   CHASE_TRY(apply64(h, k, Q, ldq, T, ldt));                                   // T = H Q
   CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
-  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m));  // M = Q^H S T
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m, true,
+                 GEMM_LOWER_ONLY));  // M = Q^H S T (Hermitian; the Cholesky reads the lower triangle)
   bool failed = false;
   CHASE_TRY(cholesky_lower(h->G, kp, h->dws, h->st, &failed));                // L L^H = M
   if (failed) return fail(CHASE_PH_ERR_NOT_DEFINITE, "Cholesky of Q^H S H Q failed (SH not positive definite on range(Q))");
   CHASE_TRY(tri_inverse_lower(h->G, h->Li, kp, h->dws, h->st));
   CHASE_TRY(fill_padded(h->Nb, kp, k, 1.0, 0.0, true, h->st));              // N = I - 2 Q2^H Q2
   CHASE_TRY(gemm(h, 1, 0, k, k, m, {-2, 0}, Q + m, ldq, Q + m, ldq, {1, 0}, h->Nb, kp));
-  CHASE_TRY(gemm(h, 0, 1, kp, kp, kp, {1, 0}, h->Nb, kp, h->Li, kp, {0, 0}, h->Tk, kp, -1, false));  // N L^{-H}
-  CHASE_TRY(gemm(h, 0, 0, kp, kp, kp, {1, 0}, h->Li, kp, h->Tk, kp, {0, 0}, h->G, kp, -1, false));   // L^{-1} N L^{-H}
+  CHASE_TRY(gemm(h, 0, 1, kp, kp, kp, {1, 0}, h->Nb, kp, h->Li, kp, {0, 0}, h->Tk, kp, -1, false,
+                 GEMM_B_UPPER));  // N L^{-H}
+  CHASE_TRY(gemm(h, 0, 0, kp, kp, kp, {1, 0}, h->Li, kp, h->Tk, kp, {0, 0}, h->G, kp, -1, false,
+                 GEMM_A_LOWER));  // L^{-1} N L^{-H}
   int sweeps = 0;
   CHASE_TRY(jacobi_eigh(h->G, h->Ev, kp, h->dws, h->st, 40, &sweeps));
   int npos = 0, nneg = 0;

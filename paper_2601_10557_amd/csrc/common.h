@@ -124,6 +124,14 @@ struct ZgemmArgs {
   int64_t ldc, strideC;
   int64_t kneg;  // K index from which the sign flips (K for none)
   int batch;
+  // Exact structure that lets tiles skip work (all default off):
+  //  lower_only: only C's tiles on or below the diagonal are needed (a
+  //              Hermitian product whose consumer reads its lower triangle;
+  //              M == N); tiles strictly above are neither computed nor
+  //              written;
+  //  a_lower:    op(A) is lower triangular (op(A)[i][k] = 0 for k > i);
+  //  b_upper:    op(B) is upper triangular (op(B)[k][j] = 0 for k > j).
+  int lower_only = 0, a_lower = 0, b_upper = 0;
 };
 // workspace: device buffer of ws_bytes (may be 0 => no split-K)
 Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s);

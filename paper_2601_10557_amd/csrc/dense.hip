@@ -10,6 +10,7 @@
 //    32 x 32 complex products.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -54,104 +55,148 @@ __global__ void zero_upper_kernel(c128* M, int64_t ld, int kp) {
 }
 
 // ------------------------------------------------------- Cholesky block
-// 64 x 64 blocks held in LDS, 256 threads.  Dot products of length up to 63
-// are split over 4 consecutive lanes and combined with lane shuffles.
-// Lane exchange inside a quad of lanes by DPP quad_perm (no LDS round
-// trip): 0xB1 swaps lanes 0<->1 and 2<->3, 0x4E swaps 0<->2 and 1<->3.
+// 64 x 64 blocks held in LDS, 1024 threads: each row (Cholesky) or column
+// (inverse) has a row of 16 lanes, which split its dot products and combine
+// them with DPP lane swaps.
+constexpr int PT = 16;          // lanes per row / column
+constexpr int PTHREADS = NB * PT;
+
+// Lane exchange inside a row of 16 lanes by DPP (no LDS round trip):
+// quad_perm 0xB1 swaps lanes 0<->1 and 2<->3 of each quad, 0x4E swaps
+// 0<->2 and 1<->3, 0x141 mirrors each half row of 8, 0x140 mirrors the row.
 template <int CTRL>
-__device__ __forceinline__ double quad_swap(double x) {
+__device__ __forceinline__ double dpp_swap(double x) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ c128 quad_sum(c128 v) {
-  v.re += quad_swap<0xB1>(v.re);
-  v.im += quad_swap<0xB1>(v.im);
-  v.re += quad_swap<0x4E>(v.re);
-  v.im += quad_swap<0x4E>(v.im);
+// Sum over the 16 lanes of a row.  Each stage adds a value and its exact
+// partner (x + y and y + x round alike), so all 16 lanes end with the same
+// bits.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_swap<0xB1>(v);
+  v += dpp_swap<0x4E>(v);
+  v += dpp_swap<0x141>(v);
+  v += dpp_swap<0x140>(v);
   return v;
 }
 
-// Sum over l = part, part + 4, ... < lim of x(l) * y(l), the terms read in
-// chunks of four so that their LDS loads are in flight together (all l < 64
-// are valid addresses; terms with l >= lim are masked out).
-template <typename FX, typename FY>
-__device__ __forceinline__ c128 strided_dot(int part, int lo, int lim, FX x, FY y) {
-  c128 sum{0.0, 0.0};
-  for (int t0 = 0; t0 < NB / 4; t0 += 4) {
-    if (lo + part + 4 * t0 >= lim) break;
-    c128 a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int l = min(lo + part + 4 * (t0 + u), NB - 1);
-      a[u] = x(l);
-      b[u] = y(l);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (lo + part + 4 * (t0 + u) < lim) sum = cadd(sum, cmul(a[u], b[u]));
-  }
-  return sum;
-}
+__device__ __forceinline__ c128 row16_sum(c128 v) { return c128{row16_sum(v.re), row16_sum(v.im)}; }
 
-// In place lower Cholesky S = L L^H (left-looking by columns).  A
-// non-positive or non-finite pivot sets *fail and is replaced by 1 so that
-// the block stays finite (the host then discards the result).
-__device__ void chol64(c128 (*S)[NB + 1], int* fail) {
-  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+// In place lower Cholesky S = L L^H, right-looking in LDL^H form: step j
+// takes the pivot d_j = S[j][j] and applies the rank-1 update
+// S[i][l] -= S[i][j] conj(S[l][j]) / d_j to the lower trailing block, so a
+// step needs one barrier and no cross-lane reduction; the columns are scaled
+// by 1 / sqrt(d_j) at the end.  Row i is updated by the 16 lanes of row
+// group i, four columns each.  A non-positive or non-finite pivot sets
+// *fail and is replaced by 1 so that the block stays finite (the host then
+// discards the result).
+__device__ __forceinline__ void chol64(c128 (*S)[NB + 1], double* piv, int* fail) {
+  const int tid = threadIdx.x, i = tid / PT, part = tid % PT;
   for (int j = 0; j < NB; ++j) {
-    c128 sum{0.0, 0.0};
-    if (row >= j)
-      sum = strided_dot(part, 0, j, [&](int l) { return S[row][l]; }, [&](int l) { return cconj(S[j][l]); });
-    sum = quad_sum(sum);
-    if (row == j && part == 0) {
-      double d = S[j][j].re - sum.re;
-      if (!(d > 0.0) || !isfinite(d)) {
-        atomicOr(fail, 1);
-        d = 1.0;
+    double d = S[j][j].re;
+    if (!(d > 0.0) || !isfinite(d)) d = 1.0;
+    const double inv = 1.0 / d;
+    if (i > j) {
+      const c128 sij = cscale(inv, S[i][j]);
+      c128 lj[NB / PT], sil[NB / PT];
+#pragma unroll
+      for (int t = 0; t < NB / PT; ++t) {
+        const int l = min(j + 1 + part + PT * t, NB - 1);
+        lj[t] = S[l][j];
+        sil[t] = S[i][l];
       }
-      S[j][j] = c128{sqrt(d), 0.0};
+#pragma unroll
+      for (int t = 0; t < NB / PT; ++t) {
+        const int l = j + 1 + part + PT * t;
+        if (l <= i) S[i][l] = csub(sil[t], cmul(sij, cconj(lj[t])));
+      }
     }
     __syncthreads();
-    if (row > j && part == 0) S[row][j] = cscale(1.0 / S[j][j].re, csub(S[row][j], sum));
-    __syncthreads();
+  }
+  if (tid < NB) {
+    const double d = S[tid][tid].re;
+    if (!(d > 0.0) || !isfinite(d)) atomicOr(fail, 1);
+    piv[tid] = (d > 0.0 && isfinite(d)) ? sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += PTHREADS) {
+    const int jj = t / NB, ii = t % NB;
+    if (ii > jj) S[ii][jj] = cscale(1.0 / piv[jj], S[ii][jj]);
+    else if (ii == jj) S[ii][jj] = c128{piv[jj], 0.0};
+  }
+  __syncthreads();
+}
+
+// Broadcast lane L of each row of 16 lanes to the whole row (DPP row_share).
+template <int L>
+__device__ __forceinline__ double row_share(double x) { return dpp_swap<0x150 + L>(x); }
+
+// f(std::integral_constant<int, B>), ..., f(std::integral_constant<int, E - 1>)
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
   }
 }
 
-// I = L^{-1} for the lower-triangular L in S (forward substitution per
-// column; the four lanes of a column all keep the solved entries, so no
-// block barrier is needed inside the loop).
-__device__ void trinv64(c128 (*S)[NB + 1], c128 (*I)[NB + 1]) {
-  const int tid = threadIdx.x, c = tid >> 2, part = tid & 3;
-  for (int i = 0; i < NB; ++i) {
-    if (i < c) {
-      if (part == 0) I[i][c] = c128{0.0, 0.0};
-      continue;
-    }
-    c128 sum = strided_dot(part, c, i, [&](int l) { return S[i][l]; }, [&](int l) { return I[l][c]; });
-    sum = quad_sum(sum);
-    const c128 rhs = (i == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
-    I[i][c] = cscale(1.0 / S[i][i].re, csub(rhs, sum));
+// I = L^{-1} for the lower-triangular L in S, by column sweeps: the 16 lanes
+// of column c hold its right-hand side (rows part + 16 t); at step i the
+// lane holding row i forms x_i = b_i / L[i][i], shares it across the row of
+// lanes by DPP, and every lane updates b_r -= L[r][i] x_i for its rows
+// r > i.  No barrier and no LDS round trip inside the sweep.  The rows are
+// swept in blocks of 16; after each block the registers shift down one block
+// so that the current block is always b[0] (no dynamic register index).
+// Needs the reciprocal pivots in rpiv (1 / L[i][i]).
+__device__ __forceinline__ void trinv64(const c128 (*S)[NB + 1], const double* rpiv, c128 (*I)[NB + 1]) {
+  constexpr int NT = NB / PT;
+  const int tid = threadIdx.x, c = tid / PT, part = tid % PT;
+  c128 b[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) b[t] = (part + PT * t == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+#pragma unroll 1
+  for (int t0 = 0; t0 < NT; ++t0) {
+    static_for<0, PT>([&](auto U) {
+      constexpr int u = decltype(U)::value;
+      const int i = PT * t0 + u;
+      // x_i on the lane that holds row i (lane u of the row); shared to all
+      const c128 xl = cscale(rpiv[i], b[0]);
+      const c128 x{row_share<u>(xl.re), row_share<u>(xl.im)};
+      if (part == 0) I[i][c] = x;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int r = part + PT * (t0 + t);
+        const c128 l = S[min(r, NB - 1)][i];
+        if (r > i && r < NB) b[t] = csub(b[t], cmul(l, x));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    });
+#pragma unroll
+    for (int t = 0; t + 1 < NT; ++t) b[t] = b[t + 1];
   }
 }
 
 // Factor the 64 x 64 diagonal block at (p, p): writes L_pp (lower, upper
 // zeroed) in place and L_pp^{-1} into inv (64 x 64, ld 64).
-__global__ __launch_bounds__(256) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
+__global__ __launch_bounds__(PTHREADS) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
   __shared__ c128 S[NB][NB + 1];
   __shared__ c128 I[NB][NB + 1];
+  __shared__ double piv[NB];
   const int tid = threadIdx.x;
-  for (int t = tid; t < NB * NB; t += 256) {
+  for (int t = tid; t < NB * NB; t += PTHREADS) {
     const int j = t / NB, i = t % NB;
     S[i][j] = M[(int64_t)(p + j) * ld + p + i];
   }
   __syncthreads();
-  chol64(S, fail);
-  trinv64(S, I);
+  chol64(S, piv, fail);
+  if (tid < NB) piv[tid] = 1.0 / piv[tid];
   __syncthreads();
-  for (int t = tid; t < NB * NB; t += 256) {
+  trinv64(S, piv, I);
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += PTHREADS) {
     const int j = t / NB, i = t % NB;
     M[(int64_t)(p + j) * ld + p + i] = (i >= j) ? S[i][j] : c128{0.0, 0.0};
     inv[(int64_t)j * NB + i] = (i >= j) ? I[i][j] : c128{0.0, 0.0};
@@ -168,26 +213,28 @@ __global__ void copy_block_kernel(const c128* src, int64_t lds, c128* dst, int64
 
 // Invert each 64 x 64 diagonal block of a lower-triangular L (padded) and
 // write it into the diagonal of Linv.
-__global__ __launch_bounds__(256) void trinv_diag_kernel(const c128* L, c128* X, int64_t ld) {
+__global__ __launch_bounds__(PTHREADS) void trinv_diag_kernel(const c128* L, c128* X, int64_t ld) {
   __shared__ c128 S[NB][NB + 1];
   __shared__ c128 I[NB][NB + 1];
+  __shared__ double rpiv[NB];
   const int p = blockIdx.x * NB;
   const int tid = threadIdx.x;
-  for (int t = tid; t < NB * NB; t += 256) {
+  for (int t = tid; t < NB * NB; t += PTHREADS) {
     const int j = t / NB, i = t % NB;
     S[i][j] = L[(int64_t)(p + j) * ld + p + i];
   }
   __syncthreads();
-  trinv64(S, I);
+  if (tid < NB) rpiv[tid] = 1.0 / S[tid][tid].re;
   __syncthreads();
-  for (int t = tid; t < NB * NB; t += 256) {
+  trinv64(S, rpiv, I);
+  __syncthreads();
+  for (int t = tid; t < NB * NB; t += PTHREADS) {
     const int j = t / NB, i = t % NB;
     X[(int64_t)(p + j) * ld + p + i] = (i >= j) ? I[i][j] : c128{0.0, 0.0};
   }
 }
 
 // ------------------------------------------------------------- Jacobi
-// Complex Jacobi rotation J = [[c, s], [-conj(s), c]] that diagonalises
 // Rotation annihilating b in [[a, b], [conj(b), d]] (a, d real).  With
 // x = d - a and the classical t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 // tau = x / (2|b|) (Golub & Van Loan, symmetric Schur 2x2, conjugated by
@@ -507,7 +554,7 @@ Err cholesky_lower(c128* M, int kp, DenseWs& ws, hipStream_t s, bool* failed) {
   const int nblk = kp / NB;
   for (int b = 0; b < nblk; ++b) {
     const int p = b * NB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, M, (int64_t)kp, p, ws.small, ws.flag);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(PTHREADS), 0, s, M, (int64_t)kp, p, ws.small, ws.flag);
     CHASE_LAUNCH_CHECK();
     const int rest = kp - p - NB;
     if (rest <= 0) break;
@@ -546,7 +593,7 @@ Err cholesky_lower(c128* M, int kp, DenseWs& ws, hipStream_t s, bool* failed) {
 Err tri_inverse_lower(const c128* L, c128* X, int kp, DenseWs& ws, hipStream_t s) {
   const int nblk = kp / NB;
   CHASE_TRY(fill_padded(X, kp, kp, 0.0, 0.0, true, s));
-  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(256), 0, s, L, X, (int64_t)kp);
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(PTHREADS), 0, s, L, X, (int64_t)kp);
   CHASE_LAUNCH_CHECK();
   const int64_t stride = (int64_t)NB * (kp + 1);
   for (int d = 1; d < nblk; ++d) {

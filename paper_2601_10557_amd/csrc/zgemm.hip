@@ -31,6 +31,7 @@ struct ZgemmDev {
   c128* C;
   int64_t ldc, strideC;
   int64_t kneg;
+  int lower_only, a_lower, b_upper;
   int splits;
   int64_t kchunk;  // K range per split (multiple of BK)
   c128* ws;        // splits * batch * M * N partials (split-K only)
@@ -44,10 +45,16 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
   const int64_t m0 = (int64_t)(blockIdx.x / TN) * BM;
   const int64_t n0 = (int64_t)(blockIdx.x % TN) * BN;
   const int bt = blockIdx.y, sp = blockIdx.z;
+  if (g.lower_only && m0 + BM <= n0) return;  // strictly above the diagonal
   const c128* A = g.A + (int64_t)bt * g.strideA;
   const c128* B = g.B + (int64_t)bt * g.strideB;
+  // triangular operands: products with k beyond the last row of this tile
+  // (lower op(A)) or the last column (upper op(B)) vanish
+  int64_t klim = g.K;
+  if (g.a_lower) klim = min(klim, m0 + BM);
+  if (g.b_upper) klim = min(klim, n0 + BN);
   const int64_t kbeg = (int64_t)sp * g.kchunk;
-  const int64_t kend = min(g.K, kbeg + g.kchunk);
+  const int64_t kend = min(klim, kbeg + g.kchunk);
   const int KT = (int)((kend - kbeg + BK - 1) / BK);
   const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
 
@@ -192,6 +199,7 @@ __global__ void zgemm_reduce(const ZgemmDev g, int batch) {
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t bt = t / (g.M * g.N), rem = t % (g.M * g.N);
     const int64_t gj = rem / g.M, gi = rem % g.M;
+    if (g.lower_only && gi / BM < gj / BN) continue;  // tile not computed
     double sr = 0, si = 0;
     for (int s = 0; s < g.splits; ++s) {
       c128 w = g.ws[((int64_t)s * batch + bt) * g.M * g.N + rem];
@@ -220,10 +228,13 @@ Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   g.B = a.B; g.ldb = a.ldb; g.strideB = a.strideB;
   g.C = a.C; g.ldc = a.ldc; g.strideC = a.strideC;
   g.kneg = a.kneg;
+  g.lower_only = a.lower_only; g.a_lower = a.a_lower; g.b_upper = a.b_upper;
   const int64_t tiles = ceil_div(a.M, BM) * ceil_div(a.N, BN);
+  const int64_t tm = ceil_div(a.M, BM);
+  const int64_t work_tiles = a.lower_only ? tm * (tm + 1) / 2 : tiles;  // tiles that compute
   int splits = 1;
-  if (a.K > 0 && ws && tiles * a.batch < 512) {
-    const int64_t want = ceil_div(1024, tiles * a.batch);
+  if (a.K > 0 && ws && work_tiles * a.batch < 512) {
+    const int64_t want = ceil_div(1024, work_tiles * a.batch);
     const int64_t maxk = std::max<int64_t>(1, a.K / (4 * BK));  // at least 4 K slabs per split
     int64_t sp = std::min(want, maxk);
     const int64_t per = a.M * a.N * a.batch * (int64_t)sizeof(c128);
