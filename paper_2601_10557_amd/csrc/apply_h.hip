@@ -108,10 +108,14 @@ struct Cfg {
   static constexpr int ACHUNK = BM * BK / VEC / NT;     // A loads per thread
   static constexpr int BCHUNK = BK * BN / VB / NT;      // B loads per thread
   // LDS row pitch: fragment reads of the FP32 16-row MFMA take four k rows
-  // of 16 words, conflict-free when the pitch is 16 mod 32 words; the other
-  // shapes keep a pad of 4 elements (measured best for them).
+  // of 16 words, conflict-free when the pitch is 16 mod 32 words; those of
+  // the FP32 32-row MFMA take two half-waves of 32 consecutive words, so no
+  // pad is needed (which keeps the 256 x 64 tile at 80 KB, two workgroups
+  // per CU); the FP64 shapes keep a pad of 4 elements.
   static constexpr bool kF32x16 = sizeof(R) == 4 && Tr::MB == 16;
-  static constexpr int pitch(int x) { return kF32x16 ? x + ((16 - x % 32) + 32) % 32 : x + 4; }
+  static constexpr int pitch(int x) {
+    return kF32x16 ? x + ((16 - x % 32) + 32) % 32 : (sizeof(R) == 4 ? x : x + 4);
+  }
   static constexpr int LDA_S = pitch(BM), LDB_S = pitch(BN);
   static_assert(BM * BK % (VEC * NT) == 0, "A tile split");
   static_assert(BK * BN % (VB * NT) == 0, "B tile split");
@@ -159,8 +163,11 @@ __device__ __forceinline__ void epilogue_store(const ApplyHArgs<R>& a, int gr, i
   a.Y[(int64_t)ocol * a.ldy + orow] = out;
 }
 
+// Two waves per SIMD where registers and LDS allow (the 256-row FP32 tiles
+// use at most 80 KB of LDS): while one workgroup waits at a tile boundary
+// the other keeps the matrix cores busy.
 template <typename Tr, int BM, int BN, int BK, int WGM, int WGN, int VB>
-__global__ __launch_bounds__(64 * WGM* WGN) void apply_h_kernel(const ApplyHArgs<typename Tr::R> a, int splits,
+__global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2, 2))) void apply_h_kernel(const ApplyHArgs<typename Tr::R> a, int splits,
                                                                  int kps, typename Tr::C* ws) {
   using CF = Cfg<Tr, BM, BN, BK, WGM, WGN, VB>;
   using R = typename Tr::R;
@@ -368,16 +375,17 @@ struct Plan {
   int64_t tiles;
 };
 
-// Pick the tile shape and K split that minimise (rounds of 256 workgroups)
-// x (K slabs per workgroup) x (outputs per tile) / (relative MFMA efficiency
-// of the shape) x (1 + split_penalty per extra split: each split costs a
-// partial-sum write and read).  The efficiencies of the c64 shapes were
-// fitted to a sweep of every shape and split over 2k = 32 ... 520 on the
-// m = 4000 workload (the fitted plans came within 2% of the fastest ones).
+// Pick the tile shape and K split that minimise (rounds of 256 x occ
+// workgroups, occ sharing a CU) x occ x (K slabs per workgroup) x (outputs
+// per tile) / (relative MFMA efficiency of the shape) x (1 + split_penalty
+// per extra split: each split costs a partial-sum write and read).  The
+// efficiencies of the c64 shapes were fitted to a sweep of every shape and
+// split over 2k = 32 ... 520 on the m = 4000 workload (the fitted plans came
+// within 1% of the fastest ones in total time).
 template <int NCFG>
 Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG], const int (&bk)[NCFG],
-               const double (&eff)[NCFG], double split_penalty, size_t elem, size_t ws_bytes) {
-  const int64_t slots = 256;
+               const double (&eff)[NCFG], const int (&occ)[NCFG], double split_penalty, size_t elem,
+               size_t ws_bytes) {
   Plan best{0, 1, 1, 0};
   double best_cost = 1e300;
   for (int c = 0; c < NCFG; ++c) {
@@ -387,7 +395,8 @@ Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCF
       if (s > 1 && (size_t)s * m * n2 * elem > ws_bytes) break;
       const int64_t kps = ceil_div(kt, s);
       const int64_t real_s = ceil_div(kt, kps);
-      const int64_t rounds = ceil_div(tiles * real_s, slots);
+      // occ[c] workgroups share a CU, each at 1 / occ[c] of its speed
+      const int64_t rounds = ceil_div(tiles * real_s, (int64_t)256 * occ[c]) * occ[c];
       const double cost = (double)rounds * kps * bk[c] * bm[c] * bn[c] * (1.0 + split_penalty * (real_s - 1)) / eff[c];
       if (cost < best_cost * 0.999) {
         best_cost = cost;
@@ -434,17 +443,20 @@ void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const 
 
 Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
-  // 0, 1: 32 x 32 MFMA tiles; 2, 3: 16 x 16 MFMA tiles whose widths let the
-  // plan cover N = 2k with less padding (N is rounded up to the tile width).
-  // Wider 16 x 16 tiles need more accumulators than one wave can hold
-  // without spilling into extra register moves and were slower.
-  static const int bm[4] = {128, 256, 256, 256};
-  static const int bn[4] = {128, 64, 32, 48};
-  static const int bk[4] = {32, 16, 16, 16};
-  static const double eff[4] = {0.9, 1.0, 0.9, 0.97};
+  // 32 x 32 MFMA tiles: 0 (128 x 128, BK 32), 1 (256 x 64), 4 (128 x 64),
+  // 5 (128 x 128, BK 16); 16 x 16 MFMA tiles, whose widths cover N = 2k with
+  // less padding: 2 (256 x 32), 3 (256 x 48), 6 (128 x 32), 7 (128 x 48).
+  // All but 0 fit two workgroups per CU, 6 and 7 three (LDS bound).  Wider
+  // 16 x 16 tiles need more accumulators than one wave holds without extra
+  // register moves.  eff / occ fitted as described at make_plan.
+  static const int bm[8] = {128, 256, 256, 256, 128, 128, 128, 128};
+  static const int bn[8] = {128, 64, 32, 48, 64, 128, 32, 48};
+  static const int bk[8] = {32, 16, 16, 16, 16, 16, 16, 16};
+  static const double eff[8] = {0.7, 1.0, 0.8, 0.9, 0.9, 0.7, 0.8, 0.8};
+  static const int occ[8] = {1, 2, 2, 2, 2, 2, 3, 3};
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<4>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, 0.0, sizeof(c64), wsb);
-  plan_override<4>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  Plan p = make_plan<8>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb);
+  plan_override<8>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
   const bool vb2 = (a.m % 2 == 0) && (a.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0);
   switch (p.cfg) {
     case 0:
@@ -454,19 +466,35 @@ Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hi
       return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s)
                  : launch_cfg<TF32, 256, 64, 16, 4, 1, 1>(a, p, ws, s);
     case 2: return launch_cfg<TF32S, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
-    default: return launch_cfg<TF32S, 256, 48, 16, 4, 1, 1>(a, p, ws, s);
+    case 3: return launch_cfg<TF32S, 256, 48, 16, 4, 1, 1>(a, p, ws, s);
+    case 4:
+      return vb2 ? launch_cfg<TF32, 128, 64, 16, 2, 2, 2>(a, p, ws, s)
+                 : launch_cfg<TF32, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
+    case 5:
+      return vb2 ? launch_cfg<TF32, 128, 128, 16, 2, 2, 2>(a, p, ws, s)
+                 : launch_cfg<TF32, 128, 128, 16, 2, 2, 1>(a, p, ws, s);
+    case 6: return launch_cfg<TF32S, 128, 32, 16, 2, 2, 1>(a, p, ws, s);
+    default: return launch_cfg<TF32S, 128, 48, 16, 4, 1, 1>(a, p, ws, s);
   }
 }
 
 Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
-  static const int bm[2] = {128, 256}, bn[2] = {64, 32}, bk[2] = {16, 16};
-  static const double eff[2] = {1.0, 1.0};
+  // 0, 1: one workgroup per CU; 2, 3: smaller K slab or tile, two per CU
+  // (2 reaches 70-77% of the FP64 peak on the m = 4000 shapes); eff fitted to
+  // a sweep of every shape and split over 2k = 32 ... 1040
+  static const int bm[4] = {128, 256, 128, 64}, bn[4] = {64, 32, 64, 64}, bk[4] = {16, 16, 8, 16};
+  static const double eff[4] = {1.0, 0.8, 1.2, 0.8};
+  static const int occ[4] = {1, 1, 2, 2};
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<2>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, 0.02, sizeof(c128), wsb);
-  plan_override<2>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
-  if (p.cfg == 0) return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
-  return launch_cfg<TF64, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
+  Plan p = make_plan<4>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.02, sizeof(c128), wsb);
+  plan_override<4>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
+  switch (p.cfg) {
+    case 0: return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
+    case 1: return launch_cfg<TF64, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
+    case 2: return launch_cfg<TF64, 128, 64, 8, 2, 2, 1>(a, p, ws, s);
+    default: return launch_cfg<TF64, 64, 64, 16, 2, 2, 1>(a, p, ws, s);
+  }
 }
 
 }  // namespace chase

@@ -64,7 +64,7 @@ def test_apply_h_fp32(prob, solver, k):
 
 # every c64 tile shape of H X (32x32 and 16x16 MFMA tiles), with and without
 # the split-K reduction; "cfg,splits" forces the plan of each launch
-@pytest.mark.parametrize("plan", ["0,1", "0,3", "1,1", "1,4", "2,1", "2,5", "3,1", "3,2", "3,7"])
+@pytest.mark.parametrize("plan", ["0,1", "0,3", "1,1", "1,4", "2,1", "2,5", "3,1", "3,2", "3,7", "4,1", "4,3", "5,2", "6,4", "7,1", "7,5"])
 @pytest.mark.parametrize("k", [37, 61])
 def test_apply_h_fp32_every_tile_plan(prob, solver, plan, k, monkeypatch):
     print_case("apply_h_fp32_plan", m=prob.m, k=k, plan=plan)
@@ -74,6 +74,18 @@ def test_apply_h_fp32_every_tile_plan(prob, solver, plan, k, monkeypatch):
     Y = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
     ref = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
     assert np.max(np.abs(Y - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("plan", ["0,1", "0,3", "1,2", "2,1", "2,4", "3,1", "3,5"])
+@pytest.mark.parametrize("k", [37, 61])
+def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
+    print_case("apply_h_fp64_plan", m=prob.m, k=k, plan=plan)
+    monkeypatch.setenv("CHASE_PH_APPLY_PLAN", plan)
+    rng = np.random.default_rng(300 + k)
+    X = complex_normal(rng, (prob.n, k))
+    Y = to_host(solver.apply_h(to_dev(X)))
+    ref = ham.apply_h(prob.A, prob.B, X)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 def _mus(prob):
