@@ -677,6 +677,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   if (mixed) CHASE_TRY(ensure_shadow(h));
 
   int locked = 0;
+  int lq = 0;  // locked pairs whose basis columns are in Xs[:, 0 : 2 lq]
   std::vector<double> lam_locked, res_locked;
   std::vector<int> degs(nevex, p.deg);
   std::vector<double> ritz(nevex), res(nevex);
@@ -721,12 +722,29 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       inf.filter_flops += fl;
     }
     CHASE_TRY(tm.stop(&inf.t_filter));
-    // assemble [S Y+, S K conj(Y+), W+, K conj(W+)] and orthonormalise (eq. 4.5)
-    const int kx = 2 * nevex;
+    // assemble [S Y+, S K conj(Y+), W+, K conj(W+)] and orthonormalise
+    // (eq. 4.5).  The columns of the locked pairs (Y+ locked) keep their
+    // orthonormal basis in the first 2 lq columns of Xs from the iteration
+    // they were locked in; only the pairs locked since then and the
+    // unlocked block are built, projected off that basis (block
+    // Gram-Schmidt, twice) and orthonormalised.  The basis of the unlocked
+    // part, which the Rayleigh-Ritz step uses, spans the same space as a QR
+    // of the whole block would give.
     CHASE_TRY(tm.start());
-    CHASE_TRY(build_search_block(h->Ylock, n, locked, h->Wk, n, kw, h->Xs, n, m, h->st));
+    const int ln = locked - lq;
+    c128* Xn = h->Xs + (int64_t)2 * lq * n;
+    const int kxn = 2 * ln + 2 * kw;
+    const double qr_flops = 16.0 * n * (double)kxn * kxn + 64.0 * n * (double)lq * kxn;
+    CHASE_TRY(build_search_block(h->Ylock + (int64_t)lq * n, n, ln, h->Wk, n, kw, Xn, n, m, h->st));
+    if (lq > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        CHASE_TRY(gemm(h, 1, 0, 2 * lq, kxn, n, {1, 0}, h->Xs, n, Xn, n, {0, 0}, h->G, h->kp));    // C = Qp^H X
+        CHASE_TRY(gemm(h, 0, 0, n, kxn, 2 * lq, {-1, 0}, h->Xs, n, h->G, h->kp, {1, 0}, Xn, n));  // X -= Qp C
+      }
+    }
     int used = 0;
-    CHASE_TRY(qr_impl(h, kx, h->Xs, n, nullptr, 0, &used));
+    CHASE_TRY(qr_impl(h, kxn, Xn, n, nullptr, 0, &used));
+    lq = locked;
     inf.shifted_qr_used += used;
     CHASE_TRY(tm.stop(&inf.t_qr));
     // oblique RR on the non-locked part (Alg. 2)
@@ -740,7 +758,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     CHASE_TRY(resid_impl(h, kq, kw, Q, n, h->Tq, n, h->Zp, h->kmax, nullptr, h->Vt, n, res.data(),
                          mixed ? h->Rv : nullptr));
     CHASE_TRY(tm.stop(&inf.t_resid));
-    inf.rr_flops += 8.0 * n * n * kq + 12.0 * n * (double)kq * kq + 16.0 * n * (double)kx * kx;
+    inf.rr_flops += 8.0 * n * n * kq + 12.0 * n * (double)kq * kq + qr_flops;
     if (inf.resid_history && hist_pos + kw <= inf.resid_history_len) {
       std::copy(res.begin(), res.begin() + kw, inf.resid_history + hist_pos);
       hist_pos += kw;

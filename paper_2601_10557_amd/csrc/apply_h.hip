@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.h"
 
@@ -122,6 +123,15 @@ struct Cfg {
   static_assert(BK % Tr::KB == 0, "BK");
   static_assert(WTM % Tr::MB == 0 && WTN % Tr::NB == 0, "wave tile");
 };
+
+// f(integral_constant<B>) ... f(integral_constant<E - 1>)
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for_n(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for_n<B + 1, E>(f);
+  }
+}
 
 __device__ __forceinline__ int xcd_remap(int w, int T) {
   // Workgroup w runs on XCD w % 8.  Give each XCD a contiguous range of
@@ -294,40 +304,59 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
   __syncthreads();
 
   const int ak = Tr::a_k(lane), arow = Tr::a_row(lane);
-  for (int kt = kt_beg; kt < kt_end; ++kt) {
-    const int buf = (kt - kt_beg) & 1;
-    if (kt + 1 < kt_end) load_tiles(kt + 1);
+  // The K loop, compiled for NL = 0 .. FN live column fragments of this
+  // wave: in the last tile column only the fragments that hold columns
+  // < 2k do MFMAs (the others stay zero and are never stored), so a ragged
+  // 2k (e.g. 520 = 8 x 64 + 8) wastes at most one fragment per wave.
+  auto kloop = [&](auto NLc) {
+    constexpr int NL = decltype(NLc)::value;
+    for (int kt = kt_beg; kt < kt_end; ++kt) {
+      const int buf = (kt - kt_beg) & 1;
+      if (kt + 1 < kt_end) load_tiles(kt + 1);
+      if constexpr (NL > 0) {
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += Tr::KB) {
-      R fa_r[CF::FM], fa_i[CF::FM], fb_r[CF::FN], fb_i[CF::FN], fb_n[CF::FN];
+        for (int ks = 0; ks < BK; ks += Tr::KB) {
+          R fa_r[CF::FM], fa_i[CF::FM], fb_r[NL], fb_i[NL], fb_n[NL];
 #pragma unroll
-      for (int i = 0; i < CF::FM; ++i) {
-        fa_r[i] = As[buf][0][ks + ak][wm0 + i * Tr::MB + arow];
-        fa_i[i] = As[buf][1][ks + ak][wm0 + i * Tr::MB + arow];
-      }
+          for (int i = 0; i < CF::FM; ++i) {
+            fa_r[i] = As[buf][0][ks + ak][wm0 + i * Tr::MB + arow];
+            fa_i[i] = As[buf][1][ks + ak][wm0 + i * Tr::MB + arow];
+          }
 #pragma unroll
-      for (int j = 0; j < CF::FN; ++j) {
-        fb_r[j] = Bs[buf][0][ks + ak][wn0 + j * Tr::NB + arow];
-        fb_i[j] = Bs[buf][1][ks + ak][wn0 + j * Tr::NB + arow];
-        fb_n[j] = -fb_i[j];
-      }
+          for (int j = 0; j < NL; ++j) {
+            fb_r[j] = Bs[buf][0][ks + ak][wn0 + j * Tr::NB + arow];
+            fb_i[j] = Bs[buf][1][ks + ak][wn0 + j * Tr::NB + arow];
+            fb_n[j] = -fb_i[j];
+          }
 #pragma unroll
-      for (int i = 0; i < CF::FM; ++i)
+          for (int i = 0; i < CF::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < CF::FN; ++j) {
-          accr[i][j] = Tr::mfma(fa_r[i], fb_r[j], accr[i][j]);
-          acci[i][j] = Tr::mfma(fa_r[i], fb_i[j], acci[i][j]);
+            for (int j = 0; j < NL; ++j) {
+              accr[i][j] = Tr::mfma(fa_r[i], fb_r[j], accr[i][j]);
+              acci[i][j] = Tr::mfma(fa_r[i], fb_i[j], acci[i][j]);
+            }
+#pragma unroll
+          for (int i = 0; i < CF::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < NL; ++j) {
+              accr[i][j] = Tr::mfma(fa_i[i], fb_n[j], accr[i][j]);
+              acci[i][j] = Tr::mfma(fa_i[i], fb_r[j], acci[i][j]);
+            }
         }
-#pragma unroll
-      for (int i = 0; i < CF::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < CF::FN; ++j) {
-          accr[i][j] = Tr::mfma(fa_i[i], fb_n[j], accr[i][j]);
-          acci[i][j] = Tr::mfma(fa_i[i], fb_r[j], acci[i][j]);
-        }
+      }
+      if (kt + 1 < kt_end) store_tiles(buf ^ 1, kt + 1);
+      __syncthreads();
     }
-    if (kt + 1 < kt_end) store_tiles(buf ^ 1, kt + 1);
-    __syncthreads();
+  };
+  const int live = (N2 - (n0 + wn0) + Tr::NB - 1) / Tr::NB;  // wave-uniform
+  if (live >= CF::FN) {
+    kloop(std::integral_constant<int, CF::FN>{});
+  } else if (live <= 0) {
+    kloop(std::integral_constant<int, 0>{});
+  } else {
+    static_for_n<1, CF::FN>([&](auto L) {
+      if (live == decltype(L)::value) kloop(L);
+    });
   }
 
   const int ccol = Tr::acc_col(lane);
@@ -423,6 +452,12 @@ Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hip
   return ok();
 }
 
+// CHASE_PH_PLAN_LOG=1 prints the plan of every launch to stderr (tuning aid).
+void plan_log(const char* prec, int64_t m, int k, const Plan& p) {
+  static const bool on = std::getenv("CHASE_PH_PLAN_LOG") != nullptr;
+  if (on) std::fprintf(stderr, "[chase_ph plan] %s m=%lld k=%d cfg=%d splits=%d\n", prec, (long long)m, k, p.cfg, p.splits);
+}
+
 // CHASE_PH_APPLY_PLAN="cfg,splits" forces a tile shape and K split (tuning aid).
 template <int NCFG>
 void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG],
@@ -443,37 +478,35 @@ void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const 
 
 Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
-  // 32 x 32 MFMA tiles: 0 (128 x 128, BK 32), 1 (256 x 64), 4 (128 x 64),
-  // 5 (128 x 128, BK 16); 16 x 16 MFMA tiles, whose widths cover N = 2k with
-  // less padding: 2 (256 x 32), 3 (256 x 48), 6 (128 x 32), 7 (128 x 48).
-  // All but 0 fit two workgroups per CU, 6 and 7 three (LDS bound).  Wider
-  // 16 x 16 tiles need more accumulators than one wave holds without extra
-  // register moves.  eff / occ fitted as described at make_plan.
-  static const int bm[8] = {128, 256, 256, 256, 128, 128, 128, 128};
-  static const int bn[8] = {128, 64, 32, 48, 64, 128, 32, 48};
-  static const int bk[8] = {32, 16, 16, 16, 16, 16, 16, 16};
-  static const double eff[8] = {0.7, 1.0, 0.8, 0.9, 0.9, 0.7, 0.8, 0.8};
-  static const int occ[8] = {1, 2, 2, 2, 2, 2, 3, 3};
+  // 32 x 32 MFMA tiles: 0 (256 x 64), 3 (128 x 64), 4 (128 x 128); 16 x 16
+  // MFMA tiles, whose widths cover N = 2k with less padding: 1 (256 x 32),
+  // 2 (256 x 48), 5 (128 x 32), 6 (128 x 48).  All fit two workgroups per
+  // CU, 5 and 6 three (LDS bound).  Wider 16 x 16 tiles need more
+  // accumulators than one wave holds without extra register moves.
+  // eff / occ fitted as described at make_plan.
+  static const int bm[7] = {256, 256, 256, 128, 128, 128, 128};
+  static const int bn[7] = {64, 32, 48, 64, 128, 32, 48};
+  static const int bk[7] = {16, 16, 16, 16, 16, 16, 16};
+  static const double eff[7] = {1.0, 0.8, 0.9, 0.9, 0.7, 0.8, 0.8};
+  static const int occ[7] = {2, 2, 2, 2, 2, 3, 3};
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<8>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb);
-  plan_override<8>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  Plan p = make_plan<7>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb);
+  plan_override<7>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  plan_log("c64", a.m, a.k, p);
   const bool vb2 = (a.m % 2 == 0) && (a.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0);
   switch (p.cfg) {
     case 0:
-      return vb2 ? launch_cfg<TF32, 128, 128, 32, 2, 2, 2>(a, p, ws, s)
-                 : launch_cfg<TF32, 128, 128, 32, 2, 2, 1>(a, p, ws, s);
-    case 1:
       return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s)
                  : launch_cfg<TF32, 256, 64, 16, 4, 1, 1>(a, p, ws, s);
-    case 2: return launch_cfg<TF32S, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
-    case 3: return launch_cfg<TF32S, 256, 48, 16, 4, 1, 1>(a, p, ws, s);
-    case 4:
+    case 1: return launch_cfg<TF32S, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
+    case 2: return launch_cfg<TF32S, 256, 48, 16, 4, 1, 1>(a, p, ws, s);
+    case 3:
       return vb2 ? launch_cfg<TF32, 128, 64, 16, 2, 2, 2>(a, p, ws, s)
                  : launch_cfg<TF32, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
-    case 5:
+    case 4:
       return vb2 ? launch_cfg<TF32, 128, 128, 16, 2, 2, 2>(a, p, ws, s)
                  : launch_cfg<TF32, 128, 128, 16, 2, 2, 1>(a, p, ws, s);
-    case 6: return launch_cfg<TF32S, 128, 32, 16, 2, 2, 1>(a, p, ws, s);
+    case 5: return launch_cfg<TF32S, 128, 32, 16, 2, 2, 1>(a, p, ws, s);
     default: return launch_cfg<TF32S, 128, 48, 16, 4, 1, 1>(a, p, ws, s);
   }
 }
@@ -489,6 +522,7 @@ Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, h
   const size_t wsb = ws ? ws_bytes : 0;
   Plan p = make_plan<4>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.02, sizeof(c128), wsb);
   plan_override<4>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
+  plan_log("c128", a.m, a.k, p);
   switch (p.cfg) {
     case 0: return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
     case 1: return launch_cfg<TF64, 256, 32, 16, 4, 1, 1>(a, p, ws, s);

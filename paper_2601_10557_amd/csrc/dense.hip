@@ -21,7 +21,6 @@ namespace {
 
 constexpr int NB = 64;   // panel / padding granularity
 constexpr int JB = 16;   // Jacobi block (subproblem is 2*JB)
-constexpr int TR = 2 * JB / 16;  // rows/cols per thread in the 16x16-thread block products
 constexpr int SP = 2 * JB;
 
 __device__ __forceinline__ c128 cmul(c128 a, c128 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
@@ -235,13 +234,31 @@ __global__ __launch_bounds__(PTHREADS) void trinv_diag_kernel(const c128* L, c12
 }
 
 // ------------------------------------------------------------- Jacobi
+// 1 / sqrt(y) and 1 / d for normal positive y and nonzero d: hardware
+// estimates refined by two Newton steps each (r <- r (3 - y r^2) / 2 and
+// q <- q (2 - d q)), which take the estimate to within about an ulp.
+__device__ __forceinline__ double rsqrt_nr(double y) {
+  double r = __builtin_amdgcn_rsq(y);
+  r = r * (1.5 - 0.5 * y * r * r);
+  r = r * (1.5 - 0.5 * y * r * r);
+  return r;
+}
+
+__device__ __forceinline__ double rcp_nr(double d) {
+  double q = __builtin_amdgcn_rcp(d);
+  q = q * (2.0 - d * q);
+  q = q * (2.0 - d * q);
+  return q;
+}
+
 // Rotation annihilating b in [[a, b], [conj(b), d]] (a, d real).  With
 // x = d - a and the classical t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 // tau = x / (2|b|) (Golub & Van Loan, symmetric Schur 2x2, conjugated by
 // diag(1, e^{-i arg b})), write t = tp |b| with
 //   tp = 2 sign(x) / (|x| + sqrt(x^2 + 4|b|^2)),
 // so that c = 1 / sqrt(1 + tp^2 |b|^2), s = tp c b and the diagonal shift
-// t |b| = tp |b|^2 need no |b| itself (two square roots and two divisions).
+// t |b| = tp |b|^2 need no |b| itself.  The square roots and the division
+// use refined hardware estimates; the rotation stays unitary to rounding.
 __device__ __forceinline__ void jacobi_rot(double a, double d, c128 b, double thr, double& c, c128& s, double& t_out, int& did) {
   const double nb2 = b.re * b.re + b.im * b.im;
   if (!(nb2 > thr * thr)) {
@@ -249,8 +266,9 @@ __device__ __forceinline__ void jacobi_rot(double a, double d, c128 b, double th
     return;
   }
   const double x = d - a;
-  const double tp = (x >= 0.0 ? 2.0 : -2.0) / (fabs(x) + sqrt(x * x + 4.0 * nb2));
-  c = 1.0 / sqrt(1.0 + tp * tp * nb2);
+  const double y = x * x + 4.0 * nb2;
+  const double tp = (x >= 0.0 ? 2.0 : -2.0) * rcp_nr(fabs(x) + y * rsqrt_nr(y));
+  c = rsqrt_nr(1.0 + tp * tp * nb2);
   s = c128{tp * c * b.re, tp * c * b.im};
   t_out = tp * nb2;
   did = 1;
@@ -369,10 +387,32 @@ __device__ __forceinline__ int sub_index(int pair, int round, int nbj, int i) {
   return i < JB ? P + i : Q + i - JB;
 }
 
+// 16 x 16 output tile of a 32 x 32 complex product on the FP64 MFMA
+// (v_mfma_f64_16x16x4f64; lane l holds A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16]; accumulator r of lane l is row l / 16 + 4 r,
+// column l % 16).  a(i, k) and b(k, j) fetch the complex operands; two
+// accumulators per tile take Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br.
+template <typename FA, typename FB>
+__device__ __forceinline__ void cgemm_tile32(int lane, FA a, FB b, doublex4& cr, doublex4& ci) {
+  cr = doublex4{0, 0, 0, 0};
+  ci = doublex4{0, 0, 0, 0};
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < SP; k0 += 4) {
+    const c128 x = a(li, k0 + lk);
+    const c128 y = b(k0 + lk, li);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, y.re, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x.re, y.im, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, -y.im, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x.im, y.re, ci, 0, 0, 0);
+  }
+}
+
 // G <- J^H G J with J block-diagonal (one 32 x 32 U per pair, in the pair's
 // index set); block (a, b) of pairs is U_a^H G_ab U_b.  Also V <- V J on
 // row chunks of 32.  blockIdx.x < npair^2: G blocks; the rest: V blocks.
-// The rotation blocks are staged in LDS next to the data block.
+// The data block and the rotation blocks are staged in LDS; each of the four
+// waves computes one 16 x 16 quarter of each 32 x 32 product on MFMA.
 __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int64_t ld, int kp, int nbj, int round,
                                                            const c128* Uw, const int* pflag) {
   __shared__ c128 X[SP][SP + 1];
@@ -380,9 +420,10 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
   __shared__ c128 UA[SP][SP + 1];
   __shared__ c128 UB[SP][SP + 1];
   const int npair = nbj / 2;
-  const int tid = threadIdx.x;
-  const int ti = tid / 16, tj = tid % 16;  // TR x TR outputs per thread
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = (wave >> 1) * 16, c0 = (wave & 1) * 16;  // this wave's quarter
   int blk = blockIdx.x;
+  doublex4 cr, ci;
   if (blk < npair * npair) {
     const int a = blk / npair, b = blk % npair;
     const bool ua = pflag[a], ub = pflag[b];
@@ -397,69 +438,56 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
     }
     __syncthreads();
     // Y = X Ub
-    c128 acc[TR][TR];
-    for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
     if (ub) {
-#pragma unroll 4
-      for (int l = 0; l < SP; ++l) {
-        c128 u[TR];
-        for (int c = 0; c < TR; ++c) u[c] = UB[l][tj * TR + c];
-        for (int r = 0; r < TR; ++r) {
-          const c128 x = X[ti * TR + r][l];
-          for (int c = 0; c < TR; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
-        }
-      }
+      cgemm_tile32(lane, [&](int i, int k) { return X[r0 + i][k]; }, [&](int k, int j) { return UB[k][c0 + j]; },
+                   cr, ci);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Y[r0 + (lane >> 4) + 4 * r][c0 + (lane & 15)] = c128{cr[r], ci[r]};
     } else {
-      for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = X[ti * TR + r][tj * TR + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + (lane >> 4) + 4 * r, j = c0 + (lane & 15);
+        Y[i][j] = X[i][j];
+      }
     }
-    for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) Y[ti * TR + r][tj * TR + c] = acc[r][c];
     __syncthreads();
     // out = Ua^H Y
     if (ua) {
-      for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
-#pragma unroll 4
-      for (int l = 0; l < SP; ++l) {
-        c128 u[TR];
-        for (int r = 0; r < TR; ++r) u[r] = cconj(UA[l][ti * TR + r]);
-        for (int c = 0; c < TR; ++c) {
-          const c128 y = Y[l][tj * TR + c];
-          for (int r = 0; r < TR; ++r) acc[r][c] = cadd(acc[r][c], cmul(u[r], y));
-        }
+      cgemm_tile32(lane, [&](int i, int k) { return cconj(UA[k][r0 + i]); },
+                   [&](int k, int j) { return Y[k][c0 + j]; }, cr, ci);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const c128 y = Y[r0 + (lane >> 4) + 4 * r][c0 + (lane & 15)];
+        cr[r] = y.re;
+        ci[r] = y.im;
       }
     }
-    for (int r = 0; r < TR; ++r)
-      for (int c = 0; c < TR; ++c) {
-        const int i = ti * TR + r, j = tj * TR + c;
-        c128 v = acc[r][c];
-        if (a == b && i == j) v.im = 0.0;
-        G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)] = v;
-      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = r0 + (lane >> 4) + 4 * r, j = c0 + (lane & 15);
+      const c128 v{cr[r], (a == b && i == j) ? 0.0 : ci[r]};
+      G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)] = v;
+    }
   } else {
     blk -= npair * npair;
     const int a = blk % npair, rb = blk / npair;  // pair, row chunk
     if (!pflag[a]) return;
     const c128* Ua = Uw + (int64_t)a * SP * SP;
-    const int r0 = rb * SP;
+    const int v0 = rb * SP;
     for (int t = tid; t < SP * SP; t += 256) {
       const int j = t / SP, i = t % SP;
-      X[i][j] = V[(int64_t)sub_index(a, round, nbj, j) * ld + r0 + i];
+      X[i][j] = V[(int64_t)sub_index(a, round, nbj, j) * ld + v0 + i];
       UA[i][j] = Ua[t];
     }
     __syncthreads();
-    c128 acc[TR][TR];
-    for (int r = 0; r < TR; ++r) for (int c = 0; c < TR; ++c) acc[r][c] = c128{0, 0};
-#pragma unroll 4
-    for (int l = 0; l < SP; ++l) {
-      c128 u[TR];
-      for (int c = 0; c < TR; ++c) u[c] = UA[l][tj * TR + c];
-      for (int r = 0; r < TR; ++r) {
-        const c128 x = X[ti * TR + r][l];
-        for (int c = 0; c < TR; ++c) acc[r][c] = cadd(acc[r][c], cmul(x, u[c]));
-      }
+    cgemm_tile32(lane, [&](int i, int k) { return X[r0 + i][k]; }, [&](int k, int j) { return UA[k][c0 + j]; }, cr,
+                 ci);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = r0 + (lane >> 4) + 4 * r, j = c0 + (lane & 15);
+      V[(int64_t)sub_index(a, round, nbj, j) * ld + v0 + i] = c128{cr[r], ci[r]};
     }
-    for (int r = 0; r < TR; ++r)
-      for (int c = 0; c < TR; ++c)
-        V[(int64_t)sub_index(a, round, nbj, tj * TR + c) * ld + r0 + ti * TR + r] = acc[r][c];
   }
 }
 
