@@ -24,6 +24,7 @@ struct chase_ph_s {
   const c128* B = nullptr;
   int64_t ld = 0;
   hipStream_t st = nullptr;
+  SideStream side;  // second stream for column-split H X launches
   int64_t m = 0, n = 0;
   int nevex = 0, kmax = 0, kp = 0;
   // c64 copies of A and B (mixed / FP32 filter)
@@ -192,7 +193,7 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
-  CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st));
+  CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st, &h->side));
   return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr);
 }
 
@@ -206,7 +207,7 @@ Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy,
   a.S = S; a.lds = lds; a.dcol = dcol;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
-  CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st));
+  CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st, &h->side));
   return prof_end(h, CHASE_PH_FP32, k, sizeof(c64), P != nullptr, Q != nullptr);
 }
 
@@ -909,6 +910,9 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   h->kp = pad64(h->kmax);
   const int64_t n = h->n;
   const size_t kp2 = (size_t)h->kp * h->kp;
+  CHASE_HIP(hipStreamCreateWithFlags(&h->side.st, hipStreamNonBlocking));
+  CHASE_HIP(hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming));
+  CHASE_HIP(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
   CHASE_HIP(hipEventCreate(&h->e0));
   CHASE_HIP(hipEventCreate(&h->e1));
   CHASE_TRY(dalloc(h, &h->F1, (size_t)n * h->nevex));
@@ -1005,6 +1009,9 @@ chase_ph_status chase_ph_destroy(chase_ph_t h) {
   else (void)hipDeviceSynchronize();
   for (void* q : h->allocs) (void)hipFree(q);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
+  if (h->side.fork) (void)hipEventDestroy(h->side.fork);
+  if (h->side.join) (void)hipEventDestroy(h->side.join);
+  if (h->side.st) (void)hipStreamDestroy(h->side.st);
   if (h->e0) (void)hipEventDestroy(h->e0);
   if (h->e1) (void)hipEventDestroy(h->e1);
   delete h;

@@ -476,7 +476,7 @@ void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const 
 
 }  // namespace
 
-Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
+static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
   // 32 x 32 MFMA tiles: 0 (256 x 64), 3 (128 x 64), 4 (128 x 128); 16 x 16
   // MFMA tiles, whose widths cover N = 2k with less padding: 1 (256 x 32),
@@ -511,7 +511,7 @@ Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hi
   }
 }
 
-Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
+static Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
   // 0, 1: one workgroup per CU; 2, 3: smaller K slab or tile, two per CU
   // (2 reaches 70-77% of the FP64 peak on the m = 4000 shapes); eff fitted to
@@ -529,6 +529,53 @@ Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, h
     case 2: return launch_cfg<TF64, 128, 64, 8, 2, 2, 1>(a, p, ws, s);
     default: return launch_cfg<TF64, 64, 64, 16, 2, 2, 1>(a, p, ws, s);
   }
+}
+
+// When 2k is a few columns past a multiple of 64 (e.g. k = 260), the
+// 64-wide tiles of the last tile column are mostly padding.  The launch is
+// then split by columns (H X is column-wise, and so is the fused epilogue):
+// the first k - r columns, 2(k - r) a multiple of 64, on the caller's
+// stream, and the last r <= 16 on the side stream, whose workgroups fill CU
+// slots alongside and after the main launch.  Event fork / join keep the
+// pair ordered with the caller's stream.
+template <typename R>
+Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side,
+                 Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
+  constexpr int gran = 32;
+  const int krem = a.k % gran;
+  if (!side || !side->st || !ws || krem == 0 || krem > gran / 2 || a.k < 4 * gran) return one(a, ws, ws_bytes, s);
+  using C = typename ApplyHArgs<R>::C;
+  ApplyHArgs<R> am = a, ar = a;
+  am.k = a.k - krem;
+  ar.k = krem;
+  const int64_t c0 = am.k;
+  ar.X = a.X + c0 * a.ldx;
+  ar.Y = a.Y + c0 * a.ldy;
+  if (a.P) ar.P = a.P + c0 * a.ldp;
+  if (a.Q) ar.Q = a.Q + c0 * a.ldq;
+  if (a.S) ar.S = a.S + c0 * a.lds;
+  if (a.dcol) ar.dcol = a.dcol + c0;
+  // the remainder's split-K partials (up to 16 splits) at the top of ws
+  size_t rem_bytes = (size_t)16 * a.m * 2 * krem * sizeof(C);
+  rem_bytes = std::min(ceil_div((int64_t)rem_bytes, (int64_t)256) * 256, (int64_t)(ws_bytes / 4));
+  const size_t main_bytes = (ws_bytes - rem_bytes) / 256 * 256;
+  CHASE_HIP(hipEventRecord(side->fork, s));
+  CHASE_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
+  CHASE_TRY(one(ar, static_cast<char*>(ws) + main_bytes, rem_bytes, side->st));
+  CHASE_TRY(one(am, ws, main_bytes, s));
+  CHASE_HIP(hipEventRecord(side->join, side->st));
+  CHASE_HIP(hipStreamWaitEvent(s, side->join, 0));
+  return ok();
+}
+
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side) {
+  if (a.k <= 0 || a.m <= 0) return ok();
+  return launch_split<float>(a, ws, ws_bytes, s, side, launch_one_f32);
+}
+
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side) {
+  if (a.k <= 0 || a.m <= 0) return ok();
+  return launch_split<double>(a, ws, ws_bytes, s, side, launch_one_f64);
 }
 
 }  // namespace chase

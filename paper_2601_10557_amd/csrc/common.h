@@ -103,8 +103,16 @@ struct ApplyHArgs {
 
 // ws: device workspace for split-K partial products (ws_bytes may be 0:
 // then the K range is never split).
-Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s);
-Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s);
+// Optional side stream with fork / join events for splitting a launch by
+// columns (see launch_split in apply_h.hip); null disables the split.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s,
+                       const SideStream* side = nullptr);
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s,
+                       const SideStream* side = nullptr);
 
 // ----------------------------------------------------------------------------
 // Generic complex FP64 GEMM (zgemm.hip):

@@ -88,6 +88,21 @@ def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
     assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+# 2k a few columns past a multiple of 64 (k % 32 <= 16, k >= 128): the
+# library splits the launch by columns over two streams
+@pytest.mark.parametrize("k", [132, 260])
+def test_apply_h_column_split(prob, solver, k):
+    print_case("apply_h_column_split", m=prob.m, k=k)
+    rng = np.random.default_rng(400 + k)
+    X = complex_normal(rng, (prob.n, k))
+    Y64 = to_host(solver.apply_h(to_dev(X)))
+    ref = ham.apply_h(prob.A, prob.B, X)
+    assert np.max(np.abs(Y64 - ref)) <= 1e-12 * np.max(np.abs(ref))
+    Y32 = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
+    ref32 = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
+    assert np.max(np.abs(Y32 - ref32)) <= 1e-5 * np.max(np.abs(ref32))
+
+
 def _mus(prob):
     lam, _ = dense.dense_ph_eig(prob.A, prob.B)
     return 0.95 * lam[0], lam[prob.nevex - 1], 1.02 * lam[-1]
@@ -104,6 +119,23 @@ def test_filter_fp64(prob, solver, degs):
     ref = chebyshev.chebyshev_filter(prob.A, prob.B, W, np.array(degs), mu1, mu_nevex, mu_n)
     got = to_host(Wd)
     err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.max(err) < 1e-11, err
+
+
+def test_filter_fp64_column_split(prob):
+    # 132 columns: every product of the recurrence takes the column split
+    print_case("filter_fp64_column_split", m=prob.m, k=132)
+    A, B = dev_blocks(prob)
+    wide = PHSolver(A, B, 100, 40)
+    mu1, mu_nevex, mu_n = _mus(prob)
+    rng = np.random.default_rng(7)
+    W = osolver.init_block(complex_normal(rng, (prob.n, 132)), 1e-3)
+    Wd = to_dev(W)
+    degs = [3] * 132
+    wide.filter(Wd, mu1, mu_nevex, mu_n, degs=degs, prec=FP64)
+    wide.close()
+    ref = chebyshev.chebyshev_filter(prob.A, prob.B, W, np.array(degs), mu1, mu_nevex, mu_n)
+    err = np.linalg.norm(to_host(Wd) - ref, axis=0) / np.linalg.norm(ref, axis=0)
     assert np.max(err) < 1e-11, err
 
 
