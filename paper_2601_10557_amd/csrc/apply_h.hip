@@ -382,6 +382,226 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
       }
 }
 
+// c64 H X with both operand tiles copied HBM -> LDS by the gfx950
+// direct-to-LDS load (global_load_lds_dwordx4: lane l's 16 bytes land at
+// the wave's LDS base + 16 l), so nothing is staged through registers.
+//  * Tile 256 x 64, K slabs of 8, a ring of 4 LDS stages: slabs s + 1 ..
+//    s + 3 are in flight while slab s is multiplied.
+//  * A side ([A B] columns): k-major, interleaved complex, 2 KB per k; one
+//    8-byte LDS read gives the real and imaginary fragment.
+//  * X side: slot (k pair p, column c) holds X[2p], X[2p + 1] of column c
+//    (16 bytes; one copy per k pair fills 64 columns).  The K conj of the
+//    bottom-half columns is a sign on the fragment's imaginary part, the
+//    half swap an address offset.
+//  * Rows of A past m and columns past 2k are read from clamped addresses
+//    (their outputs are never stored); in a slab that crosses m the X
+//    fragment of k >= m is replaced by 0.
+//  * The copies are issued from inline assembly, so the compiler neither
+//    waits on them nor counts them: every wave issues the same 5 copies per
+//    slab (the last slabs repeat the final one into stages that are not read
+//    again) and waits with vmcnt(10) for slab s + 1 before the barrier.
+//    Nothing else in the K loop reads global memory.
+// Needs m even, 16-byte aligned A, B and X, and even lda, ldx.
+constexpr int DMA_BM = 256, DMA_BN = 64, DMA_BK = 8, DMA_NST = 4;
+
+__device__ __forceinline__ void vm_wait10() { __builtin_amdgcn_s_waitcnt(0xF7A); }  // vmcnt(10)
+__device__ __forceinline__ void vm_wait0() { __builtin_amdgcn_s_waitcnt(0xF70); }   // vmcnt(0)
+
+// One direct-to-LDS copy of 16 bytes per lane to lds_base + 16 lane (M0 is
+// saved and restored around it).
+__device__ __forceinline__ void lds_copy16(const void* src, unsigned lds_base) {
+  unsigned keep;
+  __asm__ __volatile__(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %2\n\t"
+      "global_load_lds_dwordx4 %1, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(keep)
+      : "v"(src), "s"(lds_base)
+      : "memory");
+}
+
+// Workgroup barrier for the DMA ring: this wave's LDS reads are complete
+// (lgkmcnt 0) and the copies it must wait for have been waited for
+// explicitly (a fenced __syncthreads would also drain every copy still in
+// flight).  The empty asm statements keep the compiler from moving memory
+// accesses across the barrier.
+__device__ __forceinline__ void ring_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt / expcnt unchanged
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void apply_h_dma_kernel(
+    const ApplyHArgs<float> a, int splits, int kps, c64* ws) {
+  using Tr = TF32;
+  using R = float;
+  using C = c64;
+  constexpr int BM = DMA_BM, BN = DMA_BN, BK = DMA_BK, NST = DMA_NST, FM = 2, FN = 2, WTM = 64;
+  constexpr int ASTAGE = BK * BM;        // complex per A stage
+  constexpr int BSTAGE = (BK / 2) * BN;  // 16-byte slots per X stage
+  __shared__ __attribute__((aligned(16))) C As[NST][ASTAGE];
+  __shared__ __attribute__((aligned(16))) floatx4 Bs[NST][BSTAGE];
+
+  const int m = (int)a.m;
+  const int kc = a.k;
+  const int N2 = 2 * kc;
+  const int TM = (m + BM - 1) / BM;
+  const int TN = (N2 + BN - 1) / BN;
+  const int T = TM * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nid = xcd_remap(blockIdx.x, T * splits);
+  const int sp = nid / T;
+  const int t = nid - sp * T;
+  const int m0 = (t / TN) * BM;
+  const int n0 = (t % TN) * BN;
+  const int nkt = (m + BK - 1) / BK;
+  const int kt_beg = sp * kps;
+  const int nsl = max(0, min(2 * nkt, kt_beg + kps) - kt_beg);
+  const int wm0 = wave * WTM;
+  const int64_t rmax = a.lda - 2;  // last valid start of a row pair
+
+  // this lane's X column for the copies (clamped) and its bottom-half flag
+  const int gjc = min(n0 + lane, N2 - 1);
+  const bool cbot = gjc >= kc;
+  const int64_t xcol = cbot ? gjc - kc : gjc;
+  const unsigned as_base = (unsigned)(uintptr_t)&As[0][0];
+  const unsigned bs_base = (unsigned)(uintptr_t)&Bs[0][0];
+
+  // copies of slab kt into ring stage st: wave w takes the A k-columns
+  // 2w, 2w + 1 (two halves of 128 rows each) and the X k pair w
+  auto copy_slab = [&](int kt, int st) {
+    const int phase = kt >= nkt;
+    const int kk0 = (kt - phase * nkt) * BK;
+    const C* Mat = phase ? a.B : a.A;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = wave * 2 + (q >> 1), half = q & 1;
+      const int64_t gk = min(kk0 + kk, m - 1);
+      const int64_t r = min((int64_t)(m0 + half * 128 + lane * 2), rmax);
+      const unsigned dst = __builtin_amdgcn_readfirstlane(
+          as_base + (unsigned)(((st * BK + kk) * BM + half * 128) * sizeof(C)));
+      lds_copy16(Mat + gk * a.lda + r, dst);
+    }
+    const int krow = min(kk0 + 2 * wave, m - 2);
+    const int64_t row = (int64_t)(cbot ? 1 - phase : phase) * m + krow;
+    const unsigned dstb = __builtin_amdgcn_readfirstlane(
+        bs_base + (unsigned)((st * BSTAGE + wave * BN) * sizeof(floatx4)));
+    lds_copy16(a.X + xcol * a.ldx + row, dstb);
+  };
+
+  typename Tr::Acc accr[FM][FN], acci[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < Tr::NACC; ++r) {
+        accr[i][j][r] = R(0);
+        acci[i][j][r] = R(0);
+      }
+  const int ak = Tr::a_k(lane), arow = Tr::a_row(lane);
+  const int live = (N2 - n0 + Tr::NB - 1) / Tr::NB;
+  // sign of the imaginary part of this lane's X fragments (K conj of the
+  // bottom-half columns)
+  R bsgn[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) bsgn[j] = (n0 + j * Tr::NB + arow >= kc) ? R(-1) : R(1);
+
+  if (nsl > 0) {
+    copy_slab(kt_beg, 0);
+    copy_slab(kt_beg + min(1, nsl - 1), 1);
+    copy_slab(kt_beg + min(2, nsl - 1), 2);
+    vm_wait10();  // slab 0 landed (slabs 1 and 2 may still be in flight)
+  }
+  ring_barrier();
+
+  auto kloop = [&](auto NLc) {
+    constexpr int NL = decltype(NLc)::value;
+    for (int s = 0; s < nsl; ++s) {
+      const int st = s & (NST - 1);
+      copy_slab(kt_beg + min(s + 3, nsl - 1), (s + 3) & (NST - 1));
+      if constexpr (NL > 0) {
+        const int kt = kt_beg + s;
+        const int phase = kt >= nkt;
+        const int kk0 = (kt - phase * nkt) * BK;
+        const bool ragged = kk0 + BK > m;  // slab crosses m: zero X for k >= m
+        const C* Ast = &As[st][0];
+        const floatx4* Bst = &Bs[st][0];
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += Tr::KB) {
+          const int k = ks + ak;
+          R fa_r[FM], fa_i[FM], fb_r[NL], fb_i[NL], fb_n[NL];
+#pragma unroll
+          for (int i = 0; i < FM; ++i) {
+            const C z = Ast[k * BM + wm0 + i * Tr::MB + arow];
+            fa_r[i] = z.re;
+            fa_i[i] = z.im;
+          }
+          const R kmask = (ragged && kk0 + k >= m) ? R(0) : R(1);
+#pragma unroll
+          for (int j = 0; j < NL; ++j) {
+            const C* slot = reinterpret_cast<const C*>(&Bst[(k >> 1) * BN + j * Tr::NB + arow]);
+            const C z = slot[k & 1];
+            fb_r[j] = z.re * kmask;
+            fb_i[j] = z.im * bsgn[j] * kmask;
+            fb_n[j] = -fb_i[j];
+          }
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < NL; ++j) {
+              accr[i][j] = Tr::mfma(fa_r[i], fb_r[j], accr[i][j]);
+              acci[i][j] = Tr::mfma(fa_r[i], fb_i[j], acci[i][j]);
+            }
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < NL; ++j) {
+              accr[i][j] = Tr::mfma(fa_i[i], fb_n[j], accr[i][j]);
+              acci[i][j] = Tr::mfma(fa_i[i], fb_r[j], acci[i][j]);
+            }
+        }
+      }
+      // slab s + 1 landed for this wave: at most the copies of slabs s + 2
+      // and s + 3 (10) are still in flight
+      vm_wait10();
+      ring_barrier();
+    }
+  };
+  if (live >= FN) {
+    kloop(std::integral_constant<int, FN>{});
+  } else if (live == 1) {
+    kloop(std::integral_constant<int, 1>{});
+  } else {
+    kloop(std::integral_constant<int, 0>{});
+  }
+  vm_wait0();  // the trailing repeat copies
+
+  const int ccol = Tr::acc_col(lane);
+  C* wsp = ws + (int64_t)sp * m * N2;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < Tr::NACC; ++r) {
+        const int gr = m0 + wm0 + i * Tr::MB + Tr::acc_row(r, lane);
+        const int gc = n0 + j * Tr::NB + ccol;
+        if (gr < m && gc < N2) {
+          if (splits > 1) {
+            C z;
+            z.re = accr[i][j][r];
+            z.im = acci[i][j][r];
+            wsp[(int64_t)gc * m + gr] = z;
+          } else {
+            epilogue_store<R, C>(a, gr, gc, accr[i][j][r], acci[i][j][r]);
+          }
+        }
+      }
+}
+
 // Sum the split-K partials in a fixed order and apply the epilogue.
 template <typename R, typename C>
 __global__ void apply_h_reduce(const ApplyHArgs<R> a, int splits, const C* ws) {
@@ -414,10 +634,10 @@ struct Plan {
 template <int NCFG>
 Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG], const int (&bk)[NCFG],
                const double (&eff)[NCFG], const int (&occ)[NCFG], double split_penalty, size_t elem,
-               size_t ws_bytes) {
+               size_t ws_bytes, int ncfg = NCFG) {
   Plan best{0, 1, 1, 0};
   double best_cost = 1e300;
-  for (int c = 0; c < NCFG; ++c) {
+  for (int c = 0; c < ncfg; ++c) {
     const int64_t kt = 2 * ceil_div(m, bk[c]);
     const int64_t tiles = ceil_div(m, bm[c]) * ceil_div(n2, bn[c]);
     for (int s = 1; s <= 16; ++s) {
@@ -447,6 +667,19 @@ Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hip
     const int64_t total = a.m * 2 * (int64_t)a.k;
     const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 8192);
     hipLaunchKernelGGL((apply_h_reduce<typename Tr::R, C>), dim3(blocks), dim3(256), 0, s, a, p.splits, (const C*)ws);
+    CHASE_LAUNCH_CHECK();
+  }
+  return ok();
+}
+
+Err launch_dma(const ApplyHArgs<float>& a, const Plan& p, void* ws, hipStream_t s) {
+  const int64_t grid = p.tiles * p.splits;
+  hipLaunchKernelGGL(apply_h_dma_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, p.splits, p.kps, (c64*)ws);
+  CHASE_LAUNCH_CHECK();
+  if (p.splits > 1) {
+    const int64_t total = a.m * 2 * (int64_t)a.k;
+    const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 8192);
+    hipLaunchKernelGGL((apply_h_reduce<float, c64>), dim3(blocks), dim3(256), 0, s, a, p.splits, (const c64*)ws);
     CHASE_LAUNCH_CHECK();
   }
   return ok();
@@ -484,16 +717,20 @@ static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes,
   // CU, 5 and 6 three (LDS bound).  Wider 16 x 16 tiles need more
   // accumulators than one wave holds without extra register moves.
   // eff / occ fitted as described at make_plan.
-  static const int bm[7] = {256, 256, 256, 128, 128, 128, 128};
-  static const int bn[7] = {64, 32, 48, 64, 128, 32, 48};
-  static const int bk[7] = {16, 16, 16, 16, 16, 16, 16};
-  static const double eff[7] = {1.0, 0.8, 0.9, 0.9, 0.7, 0.8, 0.8};
-  static const int occ[7] = {2, 2, 2, 2, 2, 3, 3};
-  const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<7>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb);
-  plan_override<7>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
-  plan_log("c64", a.m, a.k, p);
+  // 7: 256 x 64 with direct-to-LDS copies of the A side (apply_h_dma_kernel)
+  static const int bm[8] = {256, 256, 256, 128, 128, 128, 128, 256};
+  static const int bn[8] = {64, 32, 48, 64, 128, 32, 48, 64};
+  static const int bk[8] = {16, 16, 16, 16, 16, 16, 16, 8};
+  static const double eff[8] = {1.0, 0.9, 0.95, 0.95, 0.9, 0.85, 0.9, 1.1};
+  static const int occ[8] = {2, 2, 2, 2, 2, 3, 3, 2};
   const bool vb2 = (a.m % 2 == 0) && (a.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0);
+  const bool dma_ok = vb2 && !a.a_conj && a.m >= 2 && (a.lda % 2 == 0) &&
+                      ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0) && ((reinterpret_cast<uintptr_t>(a.B) & 15) == 0);
+  const size_t wsb = ws ? ws_bytes : 0;
+  Plan p = make_plan<8>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb, dma_ok ? 8 : 7);
+  plan_override<8>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  if (p.cfg == 7 && !dma_ok) p.cfg = 0;
+  plan_log("c64", a.m, a.k, p);
   switch (p.cfg) {
     case 0:
       return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s)
@@ -507,7 +744,8 @@ static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes,
       return vb2 ? launch_cfg<TF32, 128, 128, 16, 2, 2, 2>(a, p, ws, s)
                  : launch_cfg<TF32, 128, 128, 16, 2, 2, 1>(a, p, ws, s);
     case 5: return launch_cfg<TF32S, 128, 32, 16, 2, 2, 1>(a, p, ws, s);
-    default: return launch_cfg<TF32S, 128, 48, 16, 4, 1, 1>(a, p, ws, s);
+    case 6: return launch_cfg<TF32S, 128, 48, 16, 4, 1, 1>(a, p, ws, s);
+    default: return launch_dma(a, p, ws, s);
   }
 }
 
