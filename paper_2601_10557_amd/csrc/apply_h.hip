@@ -769,7 +769,8 @@ static Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes
   }
 }
 
-// When 2k is a few columns past a multiple of 64 (e.g. k = 260), the
+// When 2k is a few columns past a multiple of 64 (e.g. k = 260, or k = 73
+// with k >= 64), the
 // 64-wide tiles of the last tile column are mostly padding.  The launch is
 // then split by columns (H X is column-wise, and so is the fused epilogue):
 // the first k - r columns, 2(k - r) a multiple of 64, on the caller's
@@ -781,7 +782,7 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
                  Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
   constexpr int gran = 32;
   const int krem = a.k % gran;
-  if (!side || !side->st || !ws || krem == 0 || krem > gran / 2 || a.k < 4 * gran) return one(a, ws, ws_bytes, s);
+  if (!side || !side->st || !ws || krem == 0 || krem > gran / 2 || a.k < 2 * gran) return one(a, ws, ws_bytes, s);
   using C = typename ApplyHArgs<R>::C;
   ApplyHArgs<R> am = a, ar = a;
   am.k = a.k - krem;
