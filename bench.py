@@ -181,8 +181,9 @@ def main():
                           "write_bytes_per_launch": tr["write_bytes_per_launch"],
                           "source": "profiles/apply_h_c64_traffic_mixed_vs_fp64_m4000.json"}
     roofline = {
-        "kernel": "apply_h_kernel<TF32/TF32S,...>: one c64 H X call with the fused Chebyshev epilogue "
-                  "(one launch, or a main launch plus a side-stream launch for the last k mod 32 columns)",
+        "kernel": "apply_h_dma_kernel / apply_h_kernel (c64): one H X call with the fused Chebyshev "
+                  "epilogue (one launch, or a main launch plus a side-stream launch for the last k mod 32 "
+                  "columns)",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_detail": traffic_detail,
         "launches": n32, "avg_launch_us": round(ms32 * 1e3 / max(n32, 1), 2),

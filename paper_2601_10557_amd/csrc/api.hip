@@ -84,7 +84,7 @@ struct chase_ph_s {
   bool prof = false;
   std::vector<hipEvent_t> evpool;
   struct Launch {
-    int prec;
+    int prec, k;
     double flops, bytes;
   };
   std::vector<Launch> launches;
@@ -179,7 +179,7 @@ Err prof_end(chase_ph_t h, int prec, int k, size_t elem, bool has_p, bool has_q)
   CHASE_HIP(hipEventRecord(h->evpool[i + 1], h->st));
   const double n = (double)h->n, m = (double)h->m;
   const double bytes = (2.0 * m * m + (2.0 + (has_p ? 1 : 0) + (has_q ? 1 : 0)) * n * k) * elem;
-  h->launches.push_back({prec, 8.0 * n * n * k, bytes});
+  h->launches.push_back({prec, k, 8.0 * n * n * k, bytes});
   return ok();
 }
 
@@ -1147,11 +1147,15 @@ chase_ph_status chase_ph_profile_read(chase_ph_t h, int32_t prec, double* total_
   if (hipStreamSynchronize(h->st) != hipSuccess) return finish(h, fail(CHASE_PH_ERR_HIP, "profile_read: sync"));
   double ms = 0, fl = 0, by = 0;
   int cnt = 0;
+  // CHASE_PH_PROF_DUMP=1 lists every call (precision, columns, milliseconds) on stderr
+  const char* dump = std::getenv("CHASE_PH_PROF_DUMP");
+  const bool dump_calls = dump && dump[0] == '1';
   for (size_t i = 0; i < h->launches.size(); ++i) {
     if (h->launches[i].prec != prec) continue;
     float t = 0;
     if (hipEventElapsedTime(&t, h->evpool[2 * i], h->evpool[2 * i + 1]) != hipSuccess)
       return finish(h, fail(CHASE_PH_ERR_HIP, "profile_read: elapsed time"));
+    if (dump_calls) std::fprintf(stderr, "[chase_ph] call prec=%d k=%d ms=%.4f\n", prec, h->launches[i].k, t);
     ms += t;
     fl += h->launches[i].flops;
     by += h->launches[i].bytes;

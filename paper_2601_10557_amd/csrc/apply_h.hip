@@ -385,14 +385,16 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
 // c64 H X with both operand tiles copied HBM -> LDS by the gfx950
 // direct-to-LDS load (global_load_lds_dwordx4: lane l's 16 bytes land at
 // the wave's LDS base + 16 l), so nothing is staged through registers.
-//  * Tile 256 x 64, K slabs of 8, a ring of 4 LDS stages: slabs s + 1 ..
-//    s + 3 are in flight while slab s is multiplied.
+//  * Tile 256 x BN (BN = 64 on the 32 x 32 MFMA, the main tile; BN = 32 on
+//    the 16 x 16 MFMA, for narrow launches), K slabs of 8, a ring of 4 LDS
+//    stages: slabs s + 1 .. s + 3 are in flight while slab s is multiplied.
 //  * A side ([A B] columns): k-major, interleaved complex, 2 KB per k; one
 //    8-byte LDS read gives the real and imaginary fragment.
 //  * X side: slot (k pair p, column c) holds X[2p], X[2p + 1] of column c
-//    (16 bytes; one copy per k pair fills 64 columns).  The K conj of the
-//    bottom-half columns is a sign on the fragment's imaginary part, the
-//    half swap an address offset.
+//    (16 bytes; one copy per k pair fills 64 column slots, of which a
+//    32-wide tile reads the first 32).  The K conj of the bottom-half
+//    columns is a sign on the fragment's imaginary part, the half swap an
+//    address offset.
 //  * Rows of A past m and columns past 2k are read from clamped addresses
 //    (their outputs are never stored); in a slab that crosses m the X
 //    fragment of k >= m is replaced by 0.
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
 //    again) and waits with vmcnt(10) for slab s + 1 before the barrier.
 //    Nothing else in the K loop reads global memory.
 // Needs m even, 16-byte aligned A, B and X, and even lda, ldx.
-constexpr int DMA_BM = 256, DMA_BN = 64, DMA_BK = 8, DMA_NST = 4;
+constexpr int DMA_BM = 256, DMA_XP = 64, DMA_BK = 8, DMA_NST = 4;
 
 __device__ __forceinline__ void vm_wait10() { __builtin_amdgcn_s_waitcnt(0xF7A); }  // vmcnt(10)
 __device__ __forceinline__ void vm_wait0() { __builtin_amdgcn_s_waitcnt(0xF70); }   // vmcnt(0)
@@ -433,14 +435,16 @@ __device__ __forceinline__ void ring_barrier() {
   __asm__ __volatile__("" ::: "memory");
 }
 
+template <typename Tr, int BN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void apply_h_dma_kernel(
     const ApplyHArgs<float> a, int splits, int kps, c64* ws) {
-  using Tr = TF32;
   using R = float;
   using C = c64;
-  constexpr int BM = DMA_BM, BN = DMA_BN, BK = DMA_BK, NST = DMA_NST, FM = 2, FN = 2, WTM = 64;
+  constexpr int BM = DMA_BM, BK = DMA_BK, NST = DMA_NST, XP = DMA_XP, WTM = 64;
+  constexpr int FM = WTM / Tr::MB, FN = BN / Tr::NB;
   constexpr int ASTAGE = BK * BM;        // complex per A stage
-  constexpr int BSTAGE = (BK / 2) * BN;  // 16-byte slots per X stage
+  constexpr int BSTAGE = (BK / 2) * XP;  // 16-byte slots per X stage
+  static_assert(BN <= XP && BN % Tr::NB == 0 && BK % Tr::KB == 0, "DMA tile");
   __shared__ __attribute__((aligned(16))) C As[NST][ASTAGE];
   __shared__ __attribute__((aligned(16))) floatx4 Bs[NST][BSTAGE];
 
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int krow = min(kk0 + 2 * wave, m - 2);
     const int64_t row = (int64_t)(cbot ? 1 - phase : phase) * m + krow;
     const unsigned dstb = __builtin_amdgcn_readfirstlane(
-        bs_base + (unsigned)((st * BSTAGE + wave * BN) * sizeof(floatx4)));
+        bs_base + (unsigned)((st * BSTAGE + wave * XP) * sizeof(floatx4)));
     lds_copy16(a.X + xcol * a.ldx + row, dstb);
   };
 
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           const R kmask = (ragged && kk0 + k >= m) ? R(0) : R(1);
 #pragma unroll
           for (int j = 0; j < NL; ++j) {
-            const C* slot = reinterpret_cast<const C*>(&Bst[(k >> 1) * BN + j * Tr::NB + arow]);
+            const C* slot = reinterpret_cast<const C*>(&Bst[(k >> 1) * XP + j * Tr::NB + arow]);
             const C z = slot[k & 1];
             fb_r[j] = z.re * kmask;
             fb_i[j] = z.im * bsgn[j] * kmask;
@@ -570,13 +574,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       ring_barrier();
     }
   };
-  if (live >= FN) {
-    kloop(std::integral_constant<int, FN>{});
-  } else if (live == 1) {
-    kloop(std::integral_constant<int, 1>{});
-  } else {
-    kloop(std::integral_constant<int, 0>{});
-  }
+  // K loop compiled for the number of live column fragments (at most FN)
+  const int nl = min(live, FN);
+  static_for_n<0, FN + 1>([&](auto NLc) {
+    if (nl == decltype(NLc)::value) kloop(NLc);
+  });
   vm_wait0();  // the trailing repeat copies
 
   const int ccol = Tr::acc_col(lane);
@@ -624,6 +626,10 @@ struct Plan {
   int64_t tiles;
 };
 
+// Largest K split of one launch: narrow launches (2k <= 32) need 32 splits
+// of the m / 256 row tiles to give every CU two workgroups.
+constexpr int MAX_SPLITS = 32;
+
 // Pick the tile shape and K split that minimise (rounds of 256 x occ
 // workgroups, occ sharing a CU) x occ x (K slabs per workgroup) x (outputs
 // per tile) / (relative MFMA efficiency of the shape) x (1 + split_penalty
@@ -640,7 +646,7 @@ Plan make_plan(int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCF
   for (int c = 0; c < ncfg; ++c) {
     const int64_t kt = 2 * ceil_div(m, bk[c]);
     const int64_t tiles = ceil_div(m, bm[c]) * ceil_div(n2, bn[c]);
-    for (int s = 1; s <= 16; ++s) {
+    for (int s = 1; s <= MAX_SPLITS; ++s) {
       if (s > 1 && (size_t)s * m * n2 * elem > ws_bytes) break;
       const int64_t kps = ceil_div(kt, s);
       const int64_t real_s = ceil_div(kt, kps);
@@ -672,9 +678,11 @@ Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hip
   return ok();
 }
 
+template <typename Tr, int BN>
 Err launch_dma(const ApplyHArgs<float>& a, const Plan& p, void* ws, hipStream_t s) {
   const int64_t grid = p.tiles * p.splits;
-  hipLaunchKernelGGL(apply_h_dma_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, p.splits, p.kps, (c64*)ws);
+  hipLaunchKernelGGL((apply_h_dma_kernel<Tr, BN>), dim3((unsigned)grid), dim3(256), 0, s, a, p.splits, p.kps,
+                     (c64*)ws);
   CHASE_LAUNCH_CHECK();
   if (p.splits > 1) {
     const int64_t total = a.m * 2 * (int64_t)a.k;
@@ -717,19 +725,21 @@ static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes,
   // CU, 5 and 6 three (LDS bound).  Wider 16 x 16 tiles need more
   // accumulators than one wave holds without extra register moves.
   // eff / occ fitted as described at make_plan.
-  // 7: 256 x 64 with direct-to-LDS copies of the A side (apply_h_dma_kernel)
-  static const int bm[8] = {256, 256, 256, 128, 128, 128, 128, 256};
-  static const int bn[8] = {64, 32, 48, 64, 128, 32, 48, 64};
-  static const int bk[8] = {16, 16, 16, 16, 16, 16, 16, 8};
-  static const double eff[8] = {1.0, 0.9, 0.95, 0.95, 0.9, 0.85, 0.9, 1.1};
-  static const int occ[8] = {2, 2, 2, 2, 2, 3, 3, 2};
+  // Direct-to-LDS tiles (apply_h_dma_kernel): 7 (256 x 64, 32 x 32 MFMA),
+  // 8 (256 x 32, 16 x 16 MFMA, for narrow launches; a 256 x 64 tile on the
+  // 16 x 16 MFMA would spill).
+  static const int bm[9] = {256, 256, 256, 128, 128, 128, 128, 256, 256};
+  static const int bn[9] = {64, 32, 48, 64, 128, 32, 48, 64, 32};
+  static const int bk[9] = {16, 16, 16, 16, 16, 16, 16, 8, 8};
+  static const double eff[9] = {1.0, 0.9, 0.95, 0.95, 0.9, 0.85, 0.9, 1.1, 1.0};
+  static const int occ[9] = {2, 2, 2, 2, 2, 3, 3, 2, 2};
   const bool vb2 = (a.m % 2 == 0) && (a.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.X) & 15) == 0);
   const bool dma_ok = vb2 && !a.a_conj && a.m >= 2 && (a.lda % 2 == 0) &&
                       ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0) && ((reinterpret_cast<uintptr_t>(a.B) & 15) == 0);
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<8>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb, dma_ok ? 8 : 7);
-  plan_override<8>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
-  if (p.cfg == 7 && !dma_ok) p.cfg = 0;
+  Plan p = make_plan<9>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb, dma_ok ? 9 : 7);
+  plan_override<9>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
+  if (p.cfg >= 7 && !dma_ok) p.cfg = p.cfg == 8 ? 1 : 0;
   plan_log("c64", a.m, a.k, p);
   switch (p.cfg) {
     case 0:
@@ -745,7 +755,8 @@ static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes,
                  : launch_cfg<TF32, 128, 128, 16, 2, 2, 1>(a, p, ws, s);
     case 5: return launch_cfg<TF32S, 128, 32, 16, 2, 2, 1>(a, p, ws, s);
     case 6: return launch_cfg<TF32S, 128, 48, 16, 4, 1, 1>(a, p, ws, s);
-    default: return launch_dma(a, p, ws, s);
+    case 7: return launch_dma<TF32, 64>(a, p, ws, s);
+    default: return launch_dma<TF32S, 32>(a, p, ws, s);
   }
 }
 
@@ -774,15 +785,19 @@ static Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes
 // 64-wide tiles of the last tile column are mostly padding.  The launch is
 // then split by columns (H X is column-wise, and so is the fused epilogue):
 // the first k - r columns, 2(k - r) a multiple of 64, on the caller's
-// stream, and the last r <= 16 on the side stream, whose workgroups fill CU
-// slots alongside and after the main launch.  Event fork / join keep the
-// pair ordered with the caller's stream.
+// stream, and the last r <= 16 on the side stream, queued after the main
+// launch, so that its workgroups take the CU slots the main launch frees in
+// its last round and during its split-K reduction.  Event fork / join keep
+// the pair ordered with the caller's stream.
 template <typename R>
 Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side,
                  Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
   constexpr int gran = 32;
   const int krem = a.k % gran;
-  if (!side || !side->st || !ws || krem == 0 || krem > gran / 2 || a.k < 2 * gran) return one(a, ws, ws_bytes, s);
+  // CHASE_PH_NO_SPLIT=1 launches every call whole (a tuning aid)
+  const char* nosplit = std::getenv("CHASE_PH_NO_SPLIT");
+  if (!side || !side->st || !ws || krem == 0 || krem > gran / 2 || a.k < 2 * gran || (nosplit && nosplit[0] == '1'))
+    return one(a, ws, ws_bytes, s);
   using C = typename ApplyHArgs<R>::C;
   ApplyHArgs<R> am = a, ar = a;
   am.k = a.k - krem;
@@ -794,14 +809,14 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
   if (a.Q) ar.Q = a.Q + c0 * a.ldq;
   if (a.S) ar.S = a.S + c0 * a.lds;
   if (a.dcol) ar.dcol = a.dcol + c0;
-  // the remainder's split-K partials (up to 16 splits) at the top of ws
-  size_t rem_bytes = (size_t)16 * a.m * 2 * krem * sizeof(C);
+  // the remainder's split-K partials (up to MAX_SPLITS) at the top of ws
+  size_t rem_bytes = (size_t)MAX_SPLITS * a.m * 2 * krem * sizeof(C);
   rem_bytes = std::min(ceil_div((int64_t)rem_bytes, (int64_t)256) * 256, (int64_t)(ws_bytes / 4));
   const size_t main_bytes = (ws_bytes - rem_bytes) / 256 * 256;
   CHASE_HIP(hipEventRecord(side->fork, s));
   CHASE_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
-  CHASE_TRY(one(ar, static_cast<char*>(ws) + main_bytes, rem_bytes, side->st));
   CHASE_TRY(one(am, ws, main_bytes, s));
+  CHASE_TRY(one(ar, static_cast<char*>(ws) + main_bytes, rem_bytes, side->st));
   CHASE_HIP(hipEventRecord(side->join, side->st));
   CHASE_HIP(hipStreamWaitEvent(s, side->join, 0));
   return ok();

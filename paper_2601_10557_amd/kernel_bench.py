@@ -2,12 +2,16 @@
 
     python -m paper_2601_10557_amd.kernel_bench --m 4000 --k 260 [--prec c64|c128|both]
         [--reps 5] [--calib-copy-mib 1024] [--plans "cfg,splits;cfg,splits;..."]
+        [--filter-deg D]
 
 Prints one line per (precision, k) with the best per-launch time (HIP events
 on the library's stream), TFLOP/s at 8 n^2 k flops per launch and the
-algorithmic GB/s.  ``--plans`` repeats each measurement with the tile plan
+algorithmic GB/s.  Each stage call waits for its launches, so a call starts
+on an idle device.  ``--filter-deg D`` instead times the 2 D back-to-back
+launches of one degree-D filter call (fused recurrence epilogue, as inside
+the solver) through the library's per-launch profile and prints their mean.  ``--plans`` repeats each measurement with the tile plan
 forced through ``CHASE_PH_APPLY_PLAN`` (a tuning aid; "auto" is the
-library's own choice).  ``--calib-copy-mib`` first runs a plain device-to-device
+library's own choice, "whole" its choice without the column split).  ``--calib-copy-mib`` first runs a plain device-to-device
 copy of that many MiB, a reference dispatch of known traffic for hardware
 counter calibration.  Random Hermitian A and symmetric B are drawn on the
 device; no parity is checked here (see tests/).
@@ -30,6 +34,7 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--plans", type=str, default="auto")
+    ap.add_argument("--filter-deg", type=int, default=0)
     args = ap.parse_args(argv)
     ks = [int(x) for x in args.k.split(",")]
     if args.calib_copy_mib > 0:
@@ -60,20 +65,35 @@ def main(argv=None):
             X = colmajor(torch.randn(n, k, dtype=dt, device="cuda", generator=g))
             Y = empty_cm(n, k, dt)
             for plan in args.plans.split(";"):
+                os.environ.pop("CHASE_PH_NO_SPLIT", None)
                 if plan == "auto":
                     os.environ.pop("CHASE_PH_APPLY_PLAN", None)
+                elif plan == "whole":
+                    os.environ.pop("CHASE_PH_APPLY_PLAN", None)
+                    os.environ["CHASE_PH_NO_SPLIT"] = "1"
                 else:
                     os.environ["CHASE_PH_APPLY_PLAN"] = plan
-                best = 1e30
-                for _ in range(args.reps + 1):
-                    s.apply_h(X, Y, prec=prec)
-                    best = min(best, s.last_timing()[0])
+                if args.filter_deg > 0:
+                    W = X.clone()
+                    degs = [args.filter_deg] * k
+                    s.filter(W, 10.0, 50.0, 400.0, degs=degs, prec=prec)
+                    s.profile(True)
+                    s.filter(W, 10.0, 50.0, 400.0, degs=degs, prec=prec)
+                    ms, _, _, cnt = s.profile_read(prec)
+                    s.profile(False)
+                    best = ms / max(cnt, 1)
+                else:
+                    best = 1e30
+                    for _ in range(args.reps + 1):
+                        s.apply_h(X, Y, prec=prec)
+                        best = min(best, s.last_timing()[0])
                 fl = 8.0 * n * n * k
                 by = (2.0 * m * m + 2.0 * n * k) * elem
                 print(f"{name} m={m} k={k} plan={plan}: {best * 1e3:.1f} us  {fl / best / 1e9:.2f} TFLOP/s "
                       f"({fl / best / 1e9 / peak * 100:.1f}% of {peak})  {by / best / 1e6:.1f} GB/s algorithmic",
                       flush=True)
             os.environ.pop("CHASE_PH_APPLY_PLAN", None)
+            os.environ.pop("CHASE_PH_NO_SPLIT", None)
     s.close()
 
 

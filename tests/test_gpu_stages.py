@@ -64,7 +64,7 @@ def test_apply_h_fp32(prob, solver, k):
 
 # every c64 tile shape of H X (32x32 and 16x16 MFMA tiles), with and without
 # the split-K reduction; "cfg,splits" forces the plan of each launch
-@pytest.mark.parametrize("plan", ["0,1", "0,4", "1,1", "1,5", "2,1", "2,2", "2,7", "3,1", "3,3", "4,2", "5,4", "6,1", "6,5", "7,1", "7,3", "7,6"])
+@pytest.mark.parametrize("plan", ["0,1", "0,4", "1,1", "1,5", "2,1", "2,2", "2,7", "3,1", "3,3", "4,2", "5,4", "6,1", "6,5", "7,1", "7,3", "7,6", "8,1", "8,2", "8,5"])
 @pytest.mark.parametrize("k", [37, 61])
 def test_apply_h_fp32_every_tile_plan(prob, solver, plan, k, monkeypatch):
     print_case("apply_h_fp32_plan", m=prob.m, k=k, plan=plan)
