@@ -780,12 +780,11 @@ static Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes
   }
 }
 
-// When 2k is a few columns past a multiple of 64 (e.g. k = 260, or k = 73
-// with k >= 64), the
-// 64-wide tiles of the last tile column are mostly padding.  The launch is
-// then split by columns (H X is column-wise, and so is the fused epilogue):
-// the first k - r columns, 2(k - r) a multiple of 64, on the caller's
-// stream, and the last r <= 16 on the side stream, queued after the main
+// When 2k is a few columns past a multiple of 64 (e.g. k = 260 or k = 73;
+// k >= 64), the 64-wide tiles of the last tile column are mostly padding.
+// The launch is then split by columns (H X is column-wise, and so is the
+// fused epilogue): the first k - r columns, 2(k - r) a multiple of 64, on the
+// caller's stream, and the last r <= 20 (c64; c128: 16) on the side stream, queued after the main
 // launch, so that its workgroups take the CU slots the main launch frees in
 // its last round and during its split-K reduction.  Event fork / join keep
 // the pair ordered with the caller's stream.
@@ -794,9 +793,15 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
                  Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
   constexpr int gran = 32;
   const int krem = a.k % gran;
-  // CHASE_PH_NO_SPLIT=1 launches every call whole (a tuning aid)
+  // c64: split when the last r = k mod 32 columns (2r of the 2k) fit in at
+  // most three 16-column fragments of the narrow tile (measured inside the
+  // filter on m = 4000, r = 17 and 20 gain 3-5% over the whole launch, r = 22
+  // and 26 lose 7-20%); c128: r <= 16.  Tuning aids: CHASE_PH_SPLIT_MAX=r
+  // overrides the bound, CHASE_PH_NO_SPLIT=1 launches every call whole.
   const char* nosplit = std::getenv("CHASE_PH_NO_SPLIT");
-  if (!side || !side->st || !ws || krem == 0 || krem > gran / 2 || a.k < 2 * gran || (nosplit && nosplit[0] == '1'))
+  const char* smax = std::getenv("CHASE_PH_SPLIT_MAX");
+  const int rmax = smax ? std::atoi(smax) : (sizeof(R) == 4 ? 20 : 16);
+  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < 2 * gran || (nosplit && nosplit[0] == '1'))
     return one(a, ws, ws_bytes, s);
   using C = typename ApplyHArgs<R>::C;
   ApplyHArgs<R> am = a, ar = a;

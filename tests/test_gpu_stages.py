@@ -88,9 +88,9 @@ def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
     assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-# 2k a few columns past a multiple of 64 (k % 32 <= 16, k >= 64): the
-# library splits the launch by columns over two streams
-@pytest.mark.parametrize("k", [73, 132, 260])
+# 2k a few columns past a multiple of 64 (k % 32 <= 16, or <= 20 in c64;
+# k >= 64): the library splits the launch by columns over two streams
+@pytest.mark.parametrize("k", [73, 84, 132, 145, 260])
 def test_apply_h_column_split(prob, solver, k):
     print_case("apply_h_column_split", m=prob.m, k=k)
     rng = np.random.default_rng(400 + k)
