@@ -35,3 +35,22 @@ def eigval_grad(V: np.ndarray, g: np.ndarray):
         G_A += gt * (np.outer(x, x.conj()) + np.outer(yb, yb.conj()))
         G_B += gt * (np.outer(x, y.conj()) + np.outer(yb, x))
     return G_A, G_B
+
+
+def eigval_grad_entries(V: np.ndarray, g: np.ndarray, rows, cols):
+    """Entries (rows[i], cols[j]) of the (G_A, G_B) of eigval_grad, summed
+    pair by pair without forming the m x m matrices (for sizes where they
+    do not fit on the host)."""
+    m = V.shape[0] // 2
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    GA = np.zeros((len(rows), len(cols)), dtype=np.complex128)
+    GB = np.zeros((len(rows), len(cols)), dtype=np.complex128)
+    for i in range(V.shape[1]):
+        x = V[:m, i]
+        y = V[m:, i]
+        gt = g[i] / np.real(np.vdot(x, x) - np.vdot(y, y))
+        yb = y.conj()
+        GA += gt * (np.outer(x[rows], x[cols].conj()) + np.outer(yb[rows], yb[cols].conj()))
+        GB += gt * (np.outer(x[rows], y[cols].conj()) + np.outer(yb[rows], x[cols]))
+    return GA, GB

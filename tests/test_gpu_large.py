@@ -3,9 +3,12 @@
 * adjoint workload (m = 2000): gradient of L = sum_i w_i lambda_i against the
   dense FP64 oracle gradient and against central finite differences
   (h = 1e-6) on 32 random unit-Frobenius Hermitian/symmetric directions;
-* clustered (m = 16000) and largest (m = 30000) workloads: H X in c64 and
-  c128 on sampled rows recomputed on the host from rows of A and B, and
-  Thm 4.2 (K-conj equivariance of the filter) at full size.
+* clustered (m = 16000) and largest (m = 30000) workloads, at full size:
+  - H X in c64 and c128 on sampled rows recomputed on the host from rows of
+    A and B, and Thm 4.2 (K-conj equivariance of the filter);
+  - one pass of the stage chain (c64 filter with per-vector degrees, QR,
+    oblique Rayleigh-Ritz, residuals, eigenvalue adjoint) checked on sampled
+    columns against host recomputation and the oracle's formulas.
 """
 import numpy as np
 import pytest
@@ -17,6 +20,7 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
 from oracle import adjoint, dense
+from oracle.hamiltonian import apply_s
 from paper_2601_10557_amd import FP32, FP64, PHSolver, colmajor, eigsh_ph
 from synth import config_problem
 from synth.gpu import config_problem_device
@@ -110,9 +114,18 @@ def _c64_apply_tol(m):
     return 4.0 * U32 * np.sqrt(2.0 * m)
 
 
-@pytest.mark.parametrize("cfg", [2, 4])
-def test_apply_h_full_size_sampled_rows(cfg):
-    p = config_problem_device(cfg)
+@pytest.fixture(scope="module", params=[2, 4])
+def big(request):
+    """Full-size clustered (m = 16000) and largest (m = 30000) workloads,
+    drawn on the device; pytest runs every test of one before the next."""
+    p = config_problem_device(request.param)
+    yield request.param, p
+    del p
+    torch.cuda.empty_cache()
+
+
+def test_apply_h_full_size_sampled_rows(big):
+    cfg, p = big
     print_case("apply_h_full", cfg=cfg, m=p.m)
     assert _sampled_rows_check(p, 64, FP64) < 1e-12
     e32 = _sampled_rows_check(p, 64, FP32)
@@ -134,3 +147,94 @@ def test_apply_h_full_size_sampled_rows(cfg):
     # both sides carry the rounding of 2 * deg c64 products
     assert np.max(np.abs(kx - y)) <= 2 * 3 * _c64_apply_tol(m) * np.max(np.abs(y))
     s.close()
+
+
+def test_stage_chain_full_size(big):
+    """One pass of filter -> QR -> Rayleigh-Ritz -> residuals -> adjoint at
+    full size, in the launch configuration of the solver, on sampled columns.
+
+    The filter interval comes from bounds that hold for every definite
+    problem: |lambda| <= rho(A) = max d (Section 3) and lambda >= (1 - c) min d
+    (Weyl: SH >= (1 - c) min d I).  The clustered workload runs per-vector
+    degrees spread over [10, 36]; the largest one degree 3 (time)."""
+    cfg, p = big
+    m, n, nevex, nev = p.m, p.n, p.nevex, p.nev
+    k = 2 * nevex
+    lo = (1.0 - p.coupling) * float(p.d.min())
+    mu1, mu_nevex, mu_n = 0.95 * lo, float(np.sort(p.d)[nevex]), 1.01 * float(p.d.max())
+    if p.deg_min != p.deg_max:
+        degs = np.round(np.linspace(p.deg_min, p.deg_max, nevex)).astype(int)
+    else:
+        degs = np.full(nevex, 3)
+    print_case("stage_chain_full", cfg=cfg, m=m, nevex=nevex, deg_lo=int(degs[0]), deg_hi=int(degs[-1]))
+    s = PHSolver(p.A, p.B, nev, p.nex, tol=p.tol)
+    W = p.w0_raw.clone()
+    W[m:] *= 1e-3                                    # Section 4.6
+    W32 = colmajor(W.to(torch.complex64))
+    del W
+    s.filter(W32, mu1, mu_nevex, mu_n, degs=degs.tolist(), prec=FP32)
+    W = W32.to(torch.complex128)
+    del W32
+    X = colmajor(torch.cat([W, torch.cat([W[m:], W[:m]]).conj()], dim=1))   # [W+, K conj(W+)]
+    del W
+    X0 = X.cpu().numpy()
+    R, shifted = s.qr(X)
+    ritz, Z, T = s.oblique_rr(X)
+    V, res = s.residuals(X, T, Z, ritz)
+    g = np.random.default_rng(11).standard_normal(nev)
+    GA, GB = s.eigval_backward(V[:, :nev], g)
+    rows, gcols = np.r_[0, m // 2, m - 1], np.r_[0, 7, m // 3, m - 1]
+    ga = GA[rows][:, gcols].cpu().numpy()
+    gb = GB[rows][:, gcols].cpu().numpy()
+    del GA, GB
+    torch.cuda.synchronize()
+    print_case("stage_chain_full_done", cfg=cfg, shifted_qr=shifted, ritz0=float(ritz[0]), ritz_last=float(ritz[-1]))
+    Qh, Th, Zh, Vh, Rh = (t.cpu().numpy() for t in (X, T, Z, V, R))
+    del X, T, Z, V, R
+    s.close()
+    rng = np.random.default_rng(5)
+    cols = np.unique(np.r_[0, 1, nevex - 1, nevex, k - 1, rng.choice(k, 11, replace=False)])
+    # QR: orthonormal sampled columns; X = Q R column by column, R upper
+    # triangular with a positive real diagonal
+    Gs = Qh[:, cols].conj().T @ Qh[:, cols]
+    assert np.max(np.abs(Gs - np.eye(len(cols)))) < 1e-12
+    assert np.all(np.abs(np.tril(Rh, -1)) == 0)
+    dR = np.diag(Rh)
+    assert np.all(dR.real > 0) and np.allclose(dR.imag, 0)
+    xs = np.max(np.linalg.norm(X0, axis=0))
+    for j in cols:
+        rec = Qh[:, :j + 1] @ Rh[:j + 1, j]
+        assert np.linalg.norm(rec - X0[:, j]) <= 1e-12 * xs
+    del X0
+    # T = H Q on sampled columns, from the host copies of A and B
+    Ah, Bh = p.A.cpu().numpy(), p.B.cpu().numpy()
+
+    def h_apply(Y):
+        y1, y2 = Y[:m], Y[m:]
+        return np.concatenate([Ah @ y1 + Bh @ y2, -np.conj(Bh @ y1.conj() + Ah @ y2.conj())])
+
+    tc = cols[:4]
+    HQ = h_apply(Qh[:, tc])
+    assert np.max(np.abs(Th[:, tc] - HQ)) <= 1e-12 * np.max(np.abs(HQ))
+    # Ritz values: ascending, positive, above the definiteness bound
+    assert np.all(np.diff(ritz) >= 0) and ritz[0] >= lo * (1 - 1e-12)
+    # Petrov-Galerkin condition, back-transform and residuals of sampled pairs
+    jj = np.r_[0, nevex // 2, nevex - 1]
+    Vs = Qh @ Zh[:, jj]
+    Vs /= np.linalg.norm(Vs, axis=0)
+    HV = h_apply(Vs)
+    for t, j in enumerate(jj):
+        z = Zh[:, j]
+        r = Th @ z - ritz[j] * (Qh @ z)
+        pg = Qh.conj().T @ apply_s(r[:, None])[:, 0]
+        assert np.linalg.norm(pg) <= 1e-10 * np.linalg.norm(Th @ z)
+        v = Vh[:, j]
+        ph = np.vdot(Vs[:, t], v)
+        assert abs(abs(ph) - 1) < 1e-12
+        assert np.linalg.norm(v - Vs[:, t] * ph) < 1e-12
+        rh = np.linalg.norm(HV[:, t] - ritz[j] * Vs[:, t])
+        assert abs(res[j] - rh) <= 1e-8 * rh + 1e-12 * mu_n
+    # eigenvalue adjoint on the positive Ritz pairs, sampled entries
+    ga_ref, gb_ref = adjoint.eigval_grad_entries(Vh[:, :nev], g, rows, gcols)
+    assert np.max(np.abs(ga - ga_ref)) <= 1e-11 * np.max(np.abs(ga_ref))
+    assert np.max(np.abs(gb - gb_ref)) <= 1e-11 * np.max(np.abs(gb_ref))

@@ -394,3 +394,16 @@ def test_adjoint_scale_invariance():
     a1 = adjoint.eigval_grad(V, g)
     a2 = adjoint.eigval_grad(V * np.array([2.0, 1j, -0.3])[None, :], g)
     assert np.allclose(a1[0], a2[0]) and np.allclose(a1[1], a2[1])
+
+
+def test_adjoint_sampled_entries_match_full_gradient():
+    # the entrywise sum (used at sizes where G_A, G_B do not fit on the host)
+    # equals the full gradient, which is pinned by finite differences above
+    p = small_problem(12)
+    lam, V = dense.smallest_positive(p.A, p.B, 4)
+    g = np.array([0.7, -1.1, 2.0, 0.3])
+    GA, GB = adjoint.eigval_grad(V, g)
+    rows, cols = [0, 5, 11], [2, 5, 7, 11]
+    ga, gb = adjoint.eigval_grad_entries(V, g, rows, cols)
+    assert np.allclose(ga, GA[np.ix_(rows, cols)], rtol=1e-13, atol=1e-15)
+    assert np.allclose(gb, GB[np.ix_(rows, cols)], rtol=1e-13, atol=1e-15)
