@@ -91,6 +91,7 @@ typedef struct {
   double filter_flops_fp32;/* part of filter_flops done in c64                              */
   double* resid_history;   /* optional host array (caller-owned) of max_iter * nevex        */
   int32_t resid_history_len; /* capacity of resid_history in doubles (0 if NULL)           */
+  int32_t householder_qr_used; /* times the Householder QR fallback was taken              */
 } chase_ph_info;
 
 /* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos
@@ -142,12 +143,17 @@ chase_ph_status chase_ph_filter_refined(chase_ph_t h, int32_t k, void* dW, int64
                                         int64_t ldr, const double* hLam, const int32_t* degs, double mu1,
                                         double mu_nevex, double mu_n);
 
-/* In place CholeskyQR2 of an n x k c128 block dX (Section 2: Cholesky QR
- * orthonormalisation; shifted CholeskyQR3 fallback when the first
- * factorisation breaks down).  On return dX holds Q with Q^H Q = I and,
- * if dR is non-NULL, dR (k x k c128, ldr >= k) holds the upper-triangular
- * R with positive real diagonal and X = Q R.  *used_shift (host, may be
- * NULL) is set to 1 if the fallback ran.  CHASE_PH_ERR_QR if both fail.
+/* In place orthonormalisation of an n x k c128 block dX (Section 2: Cholesky
+ * QR, with Householder QR for blocks Cholesky QR cannot handle):
+ * CholeskyQR2; the shifted CholeskyQR3 when its first factorisation breaks
+ * down; a blocked Householder QR when a factorisation of either breaks
+ * down later (a numerically rank-deficient block).  On return dX holds Q
+ * with Q^H Q = I whose first j columns span the first j columns of X for
+ * every j and, if dR is non-NULL, dR (k x k c128, ldr >= k) holds the
+ * upper-triangular R with X = Q R and a real diagonal, positive for the
+ * Cholesky variants and non-negative for the Householder one (zero where a
+ * column depends on the previous ones).  *used_shift (host, may be NULL) is
+ * set to 0 (CholeskyQR2), 1 (shifted CholeskyQR3) or 2 (Householder).
  * k <= 2 * nevex. */
 chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void* dR,
                             int64_t ldr, int32_t* used_shift);

@@ -27,7 +27,7 @@ import numpy as np
 from .chebyshev import chebyshev_filter, filter_params
 from .hamiltonian import apply_k_conj, apply_s
 from .lanczos import spectral_estimates
-from .qr import cholqr2
+from .qr import kreal_qr, orthonormalise
 from .rayleigh_ritz import oblique_rr
 from .residuals import back_transform, residual_norms
 
@@ -78,7 +78,11 @@ def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3
         locked = Yp.shape[1]
         W = chebyshev_filter(A, B, W, degs, mu1, mu_nevex, mu_n)
         X = np.concatenate([apply_s(Yp), apply_s(apply_k_conj(Yp)), W, apply_k_conj(W)], axis=1)
-        Q, _, shifted = cholqr2(X)
+        Q, _, shifted = orthonormalise(X)
+        if shifted == 2:
+            # rank-deficient block: K-real basis of the same K-invariant span
+            # (the locked pairs' part first), completed by K-real directions
+            Q = kreal_qr(np.concatenate([apply_s(Yp), W], axis=1), lead=locked)
         Q = Q[:, 2 * locked:]
         lam, Z, _ = oblique_rr(A, B, Q)
         V = back_transform(Q, Z)

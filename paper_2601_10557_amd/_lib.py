@@ -39,7 +39,7 @@ class Info(C.Structure):
         ("t_qr", C.c_double), ("t_rr", C.c_double), ("t_resid", C.c_double),
         ("t_total", C.c_double), ("filter_flops", C.c_double), ("rr_flops", C.c_double),
         ("filter_flops_fp32", C.c_double), ("resid_history", C.POINTER(C.c_double)),
-        ("resid_history_len", C.c_int32),
+        ("resid_history_len", C.c_int32), ("householder_qr_used", C.c_int32),
     ]
 
 

@@ -62,6 +62,7 @@ struct chase_ph_s {
   c128* Ev = nullptr;
   c128* Ys = nullptr;
   c128* Zp = nullptr;  // kmax x kmax/2
+  HouseholderWs hhw;   // Householder QR (last-resort orthonormalisation); Q in Xt
   // solver state
   c128* Ylock = nullptr;  // n x nev
   c128* Wk = nullptr;     // n x nevex
@@ -399,7 +400,30 @@ Err cholqr_pass(chase_ph_t h, int k, int kp, const c128* Xin, int64_t ldin, c128
   return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout, -1, true, GEMM_B_UPPER);
 }
 
-Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift) {
+// Householder QR of X in place; with npre = 2, X is the output of two
+// Cholesky-QR passes with factors L1, L2 and R also takes L2^H L1^H.
+Err householder_fallback(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int npre) {
+  const int kp = pad64(k);
+  CHASE_TRY(householder_qr(X, ldx, h->n, k, R ? h->G : nullptr, kp, h->hhw, h->st));
+  if (!R) return ok();
+  if (npre == 0) {
+    CHASE_HIP(hipMemcpy2DAsync(R, ldr * sizeof(c128), h->G, kp * sizeof(c128), k * sizeof(c128), k,
+                               hipMemcpyDeviceToDevice, h->st));
+    return ok();
+  }
+  CHASE_TRY(gemm(h, 0, 1, k, k, k, {1, 0}, h->G, kp, h->L2, kp, {0, 0}, h->Tk, kp, -1, false));
+  return gemm(h, 0, 1, k, k, k, {1, 0}, h->Tk, kp, h->L1, kp, {0, 0}, R, ldr, -1, false);
+}
+
+// CholeskyQR2; shifted CholeskyQR3 when its first factorisation breaks
+// down; Householder QR when a factorisation of either breaks down later
+// (*used_shift = 0, 1, 2).  A pass that breaks down leaves X untouched, so
+// the Householder QR runs on the input block or, after two completed
+// passes of the shifted variant, on their output (same leading spans).
+// With householder = false the breakdown is only reported (*used_shift = 2,
+// X unspecified): the solver then orthonormalises the K-real form instead.
+Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift,
+            bool householder = true) {
   if (used_shift) *used_shift = 0;
   if (k == 0) return ok();
   const int kp = pad64(k);
@@ -409,8 +433,12 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
   int nf = 2;
   if (!failed) {
     CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
-    if (failed) return fail(CHASE_PH_ERR_QR, "CholeskyQR2: second factorisation failed");
+    if (failed) {
+      if (used_shift) *used_shift = 2;
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0) : ok();
+    }
   } else {
+    if (used_shift) *used_shift = 1;
     // shifted CholeskyQR3: s = 11 (n k + k (k + 1)) u ||X||_F^2
     CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
     CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, X, ldx, X, ldx, {0, 0}, h->G, kp, -1, true, GEMM_LOWER_ONLY));
@@ -420,15 +448,19 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
     CHASE_HIP(hipStreamSynchronize(h->st));
     const double shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * U_ROUND * fro2;
     CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed));
-    if (failed) return fail(CHASE_PH_ERR_QR, "shifted CholeskyQR: factorisation failed");
-    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
-    if (failed) return fail(CHASE_PH_ERR_QR, "shifted CholeskyQR3: second factorisation failed");
+    if (!failed) CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
+    if (failed) {
+      if (used_shift) *used_shift = 2;
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0) : ok();
+    }
     CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L3, 0.0, &failed));
-    if (failed) return fail(CHASE_PH_ERR_QR, "shifted CholeskyQR3: third factorisation failed");
+    if (failed) {
+      if (used_shift) *used_shift = 2;
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 2) : ok();
+    }
     CHASE_HIP(hipMemcpy2DAsync(X, ldx * sizeof(c128), h->Xt, n * sizeof(c128), n * sizeof(c128), k,
                                hipMemcpyDeviceToDevice, h->st));
     nf = 3;
-    if (used_shift) *used_shift = 1;
   }
   if (R) {
     // R = L_nf^H ... L_1^H
@@ -744,9 +776,21 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       }
     }
     int used = 0;
-    CHASE_TRY(qr_impl(h, kxn, Xn, n, nullptr, 0, &used));
+    CHASE_TRY(qr_impl(h, kxn, Xn, n, nullptr, 0, &used, false));
+    if (used == 2) {
+      // Numerically rank-deficient block: Householder QR of the real
+      // coordinates of the K-real parts of all pairs, locked ones first.  The
+      // basis it completes the block with is K-real too, so the span stays
+      // K-invariant (Thm 4.5 keeps the Ritz values in +/- pairs), and the
+      // locked span keeps its leading columns.
+      const int kall = 2 * locked + 2 * kw;
+      CHASE_TRY(kreal_build(h->Ylock, n, locked, h->Wk, n, kw, h->Xs, n, m, h->st));
+      CHASE_TRY(householder_qr(h->Xs, n, n, kall, nullptr, 0, h->hhw, h->st));
+      CHASE_TRY(kreal_unpack(h->Xs, n, m, kall, h->st));
+    }
     lq = locked;
-    inf.shifted_qr_used += used;
+    inf.shifted_qr_used += used == 1;
+    inf.householder_qr_used += used == 2;
     CHASE_TRY(tm.stop(&inf.t_qr));
     // oblique RR on the non-locked part (Alg. 2)
     const c128* Q = h->Xs + (int64_t)2 * locked * n;
@@ -922,6 +966,16 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, &h->Tq, (size_t)n * h->kmax));
   CHASE_TRY(dalloc(h, &h->Vt, (size_t)n * h->nevex));
   CHASE_TRY(dalloc(h, &h->TZ, (size_t)n * h->nevex));
+  CHASE_TRY(dalloc(h, &h->hhw.Vb, (size_t)n * HH_PANEL));
+  CHASE_TRY(dalloc(h, &h->hhw.Tb, (size_t)HH_PANEL * h->kmax));
+  CHASE_TRY(dalloc(h, &h->hhw.W1, (size_t)HH_PANEL * h->kmax));
+  CHASE_TRY(dalloc(h, &h->hhw.W2, (size_t)HH_PANEL * h->kmax));
+  CHASE_TRY(dalloc(h, &h->hhw.taus, (size_t)h->kmax));
+  CHASE_TRY(dalloc(h, &h->hhw.part, (size_t)HH_PARTS));
+  CHASE_TRY(dalloc(h, &h->hhw.dpart, (size_t)HH_PARTS * HH_PANEL));
+  CHASE_TRY(dalloc(h, &h->hhw.dsign, (size_t)h->kmax));
+  h->hhw.Q = h->Xt;
+  h->hhw.kmax = h->kmax;
   CHASE_TRY(dalloc(h, &h->G, kp2));
   CHASE_TRY(dalloc(h, &h->L1, kp2));
   CHASE_TRY(dalloc(h, &h->L2, kp2));
@@ -958,6 +1012,8 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, (char**)&h->ws, h->ws_bytes));
   h->dws.gemm_ws = h->ws;
   h->dws.gemm_ws_bytes = h->ws_bytes;
+  h->hhw.gemm_ws = h->ws;
+  h->hhw.gemm_ws_bytes = h->ws_bytes;
   if (p->precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
   return ok();
 }

@@ -31,4 +31,28 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
 Err select_positive(const c128* G, const c128* V, int k, int kp, c128* Ysel, double* dlam, DenseWs& ws,
                     hipStream_t s, int* npos, int* nneg);
 
+// Householder QR (householder.hip): panels of HH_PANEL columns, row-parallel
+// launches of HH_PARTS one-wave workgroups.
+constexpr int HH_PANEL = 32;
+constexpr int HH_PARTS = 512;
+struct HouseholderWs {
+  c128* Q = nullptr;        // n x kmax (ld n): the accumulated basis
+  c128* Vb = nullptr;       // n x HH_PANEL (ld n): explicit reflectors of one panel
+  c128* Tb = nullptr;       // HH_PANEL x kmax: compact WY factor of every panel
+  c128* W1 = nullptr;       // HH_PANEL x kmax
+  c128* W2 = nullptr;       // HH_PANEL x kmax
+  c128* taus = nullptr;     // kmax
+  double* part = nullptr;   // HH_PARTS
+  c128* dpart = nullptr;    // HH_PARTS x HH_PANEL
+  double* dsign = nullptr;  // kmax
+  int kmax = 0;
+  void* gemm_ws = nullptr;  // split-K partials of the GEMMs (may be null)
+  size_t gemm_ws_bytes = 0;
+};
+// In place: X (n x k, ld ldx) -> Q with Q^H Q = I and, if R is non-null,
+// R (k x k, ld ldr) upper triangular with a real non-negative diagonal and
+// X = Q R (any rank; k <= n, k <= w.kmax).
+Err householder_qr(c128* X, int64_t ldx, int64_t n, int k, c128* R, int64_t ldr, const HouseholderWs& w,
+                   hipStream_t s);
+
 }  // namespace chase

@@ -6,6 +6,12 @@ namespace chase {
 
 Err build_search_block(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx,
                        int64_t m, hipStream_t s);
+// Real coordinates (in the real parts; imaginary parts 0) of the K-real
+// pair vectors u, v of S y_j (j < L) and w_j (j < kw): n x (2L + 2kw).
+Err kreal_build(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx, int64_t m,
+                hipStream_t s);
+// In place: orthonormal real coordinates -> orthonormal K-real vectors.
+Err kreal_unpack(c128* X, int64_t ldx, int64_t m, int k, hipStream_t s);
 Err convert_to_c64(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s);
 Err convert_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s);
 Err make_shadow(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32, int64_t m,

@@ -245,7 +245,78 @@ __global__ void scale_c64_kernel(const c64* src, int64_t lds, c64* dst, int64_t 
   }
 }
 
+// Real coordinates of the K-real parts of the search block's pairs.  For a
+// vector x = [x1; x2] with J x = K conj(x) = [conj(x2); conj(x1)], the
+// vectors u = (x + J x) / 2 and v = (x - J x) / (2i) satisfy J u = u,
+// J v = v and span {x, J x} = span {u, v}.  A K-real vector [a; conj(a)] is
+// stored by its real coordinates [Re a; Im a] (n reals, held in the real
+// parts of a c128 column with zero imaginary parts); inner products of
+// K-real vectors are twice the real inner products of their coordinates.
+// Columns: u of S y_j (j < L), v of S y_j, u of w_j (j < kw), v of w_j.
+__global__ void kreal_build_kernel(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X,
+                                   int64_t ldx, int64_t m) {
+  const int cols = 2 * L + 2 * kw;
+  const int64_t total = m * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t / m);
+    const int64_t i = t % m;
+    c128 x1, x2;
+    bool vpart;
+    if (c < 2 * L) {
+      const int j = c < L ? c : c - L;
+      x1 = Y[(int64_t)j * ldy + i];
+      const c128 y2 = Y[(int64_t)j * ldy + m + i];
+      x2 = c128{-y2.re, -y2.im};  // S y
+      vpart = c >= L;
+    } else {
+      const int j = c - 2 * L < kw ? c - 2 * L : c - 2 * L - kw;
+      x1 = W[(int64_t)j * ldw + i];
+      x2 = W[(int64_t)j * ldw + m + i];
+      vpart = c - 2 * L >= kw;
+    }
+    // top half a of u (x1 + conj(x2)) / 2 or of v (x1 - conj(x2)) / (2i)
+    c128 a;
+    if (!vpart) {
+      a = c128{0.5 * (x1.re + x2.re), 0.5 * (x1.im - x2.im)};
+    } else {
+      const double dr = x1.re - x2.re, di = x1.im + x2.im;
+      a = c128{0.5 * di, -0.5 * dr};
+    }
+    X[(int64_t)c * ldx + i] = c128{a.re, 0.0};
+    X[(int64_t)c * ldx + m + i] = c128{a.im, 0.0};
+  }
+}
+
+// In place: real coordinates [r1; r2] of unit length -> the unit K-real
+// vector [a; conj(a)] / sqrt(2) with a = r1 + i r2.
+__global__ void kreal_unpack_kernel(c128* X, int64_t ldx, int64_t m, int k) {
+  const int64_t total = m * k;
+  const double h = 0.70710678118654752440;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / m, i = t % m;
+    const double r1 = X[c * ldx + i].re, r2 = X[c * ldx + m + i].re;
+    X[c * ldx + i] = c128{h * r1, h * r2};
+    X[c * ldx + m + i] = c128{h * r1, -h * r2};
+  }
+}
+
 }  // namespace
+
+Err kreal_build(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx, int64_t m,
+                hipStream_t s) {
+  const int64_t total = m * (2 * L + 2 * kw);
+  if (total == 0) return ok();
+  hipLaunchKernelGGL(kreal_build_kernel, dim3(grid_for(total)), dim3(256), 0, s, Y, ldy, L, W, ldw, kw, X, ldx, m);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err kreal_unpack(c128* X, int64_t ldx, int64_t m, int k, hipStream_t s) {
+  if (m * k == 0) return ok();
+  hipLaunchKernelGGL(kreal_unpack_kernel, dim3(grid_for(m * k)), dim3(256), 0, s, X, ldx, m, k);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
 
 Err scale_c64(const c64* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, float a, hipStream_t s) {
   if (rows * cols == 0) return ok();

@@ -83,6 +83,7 @@ class SolveInfo:
     rr_flops: float
     filter_flops_fp32: float
     resid_history: Optional[np.ndarray] = None
+    householder_qr_used: int = 0
 
 
 class PHSolver:
@@ -196,14 +197,16 @@ class PHSolver:
         return W
 
     def qr(self, X: torch.Tensor, want_r: bool = True):
-        """In place CholeskyQR2 of X (n x k c128, column-major); returns (R, shifted)."""
+        """In place orthonormalisation of X (n x k c128, column-major): CholeskyQR2,
+        shifted CholeskyQR3 or Householder QR.  Returns (R, variant) with
+        variant 0, 1 or 2 respectively (truthy when a fallback ran)."""
         assert X.stride(0) == 1
         k = X.shape[1]
         R = empty_cm(k, k, torch.complex128, X.device) if want_r else None
         used = C.c_int32(0)
         self._check(lib().chase_ph_qr(self._h, k, _ptr(X), _ld(X), _ptr(R), k if want_r else 0,
                                       C.byref(used)))
-        return R, bool(used.value)
+        return R, int(used.value)
 
     def oblique_rr(self, Q: torch.Tensor):
         """Alg. 2 on orthonormal Q (n x k): returns (ritz[k/2], Zpos k x k/2, T = H Q)."""

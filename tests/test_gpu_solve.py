@@ -77,6 +77,21 @@ def test_solve_per_vector_degrees(cfg0):
     _check_solution(p, ev, V, res, lam, 1e-10)
 
 
+def test_solve_zero_start_column_takes_householder_qr(cfg0):
+    # a zero column in the start block stays zero through the filter, so the
+    # first search block is rank deficient: QR falls back to Householder and
+    # the solve still reaches the dense oracle's eigenvalues
+    p, lam = cfg0
+    print_case("solve_householder", cfg=0, m=p.m)
+    w0 = np.array(p.w0_raw, copy=True)
+    w0[:, 5] = 0
+    A, B = dev_blocks(p)
+    s = PHSolver(A, B, p.nev, p.nex, deg=p.deg, tol=p.tol, precision=FP64)
+    ev, V, res, info = s.solve(to_dev(w0), to_dev(p.lanczos_raw))
+    assert info.householder_qr_used >= 1
+    _check_solution(p, ev, V, res, lam, 1e-10)
+
+
 def test_solve_b_zero_is_tda():
     # Section 1.1: B = 0 reduces to A X = X Omega
     p = make_problem(200, lambda rng, m: rng.uniform(1.0, 5.0, m), 0.3, 8, 6, 12, 1e-10, seed=3)

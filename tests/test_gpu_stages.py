@@ -226,9 +226,61 @@ def test_qr_shifted_fallback(solver, prob):
     Xd = to_dev(X)
     R, shifted = solver.qr(Xd)
     Q, R = to_host(Xd), to_host(R)
-    assert shifted
+    assert shifted == 1
     assert np.max(np.abs(Q.conj().T @ Q - np.eye(k))) < 1e-12
     assert np.max(np.abs(Q @ R - X)) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def solver80(prob):
+    """Handle with nevex = 40: QR blocks of up to 80 columns."""
+    A, B = dev_blocks(prob)
+    return PHSolver(A, B, 20, 20)
+
+
+def test_qr_householder_fallback_unique_part(solver80, prob):
+    # zero last column: both Cholesky variants break down, and the leading
+    # 69 columns of the Householder QR are the unique QR (three panels, the
+    # last one ragged)
+    print_case("qr_householder_unique", m=prob.m, k=70)
+    rng = np.random.default_rng(31)
+    X = complex_normal(rng, (prob.n, 70))
+    X[:, 69] = 0
+    Xd = to_dev(X)
+    R, variant = solver80.qr(Xd)
+    Q, R = to_host(Xd), to_host(R)
+    Qo, Ro, vo = oqr.orthonormalise(X)
+    assert variant == 2 and vo == 2
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(70))) < 1e-12
+    assert np.max(np.abs(Q @ R - X)) < 1e-12 * np.max(np.abs(X))
+    assert np.max(np.abs(np.tril(R, -1))) == 0.0
+    d = np.diag(R)
+    assert np.all(d.imag == 0) and np.all(d.real >= 0)
+    assert d[69] == 0
+    assert np.max(np.abs(Q[:, :69] - Qo[:, :69])) < 1e-11
+    assert np.max(np.abs(R[:69, :] - Ro[:69, :])) < 1e-11 * np.max(np.abs(Ro))
+
+
+def test_qr_householder_fallback_rank_deficient(solver80, prob):
+    # a zero column in the first panel and a repeated one in the second
+    # (k = 45: a full panel of 32 and a ragged one of 13)
+    print_case("qr_householder_deficient", m=prob.m, k=45)
+    rng = np.random.default_rng(32)
+    X = complex_normal(rng, (prob.n, 45))
+    X[:, 3] = 0
+    X[:, 40] = X[:, 7]
+    Xd = to_dev(X)
+    R, variant = solver80.qr(Xd)
+    Q, R = to_host(Xd), to_host(R)
+    Qo, _, vo = oqr.orthonormalise(X)
+    assert variant == 2 and vo == 2
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(45))) < 1e-12
+    assert np.max(np.abs(Q @ R - X)) < 1e-12 * np.max(np.abs(X))
+    d = np.diag(R)
+    assert np.all(d.imag == 0) and np.all(d.real >= 0)
+    assert d[3] == 0 and abs(d[40]) < 1e-12 * np.max(np.abs(X))
+    assert np.all(np.delete(d.real, [3, 40]) > 1e-3 * np.max(np.abs(X)))
+    assert np.max(np.abs(Q[:, :3] - Qo[:, :3])) < 1e-12
 
 
 @pytest.mark.parametrize("kh", [2, 20])

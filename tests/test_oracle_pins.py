@@ -330,6 +330,20 @@ def test_solver_matches_dense():
     assert np.all(np.real(np.diag(D)) > 0)
 
 
+def test_solver_zero_start_column_uses_kreal_qr():
+    # a zero start column keeps the first search block rank deficient; the
+    # K-real Householder basis keeps the span K-invariant and the iteration
+    # still reaches the dense eigenvalues
+    p = small_problem(60, nev=6, nex=4, deg=10, tol=1e-10)
+    w0 = np.array(p.w0_raw, copy=True)
+    w0[:, 2] = 0
+    lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, p.deg, p.tol, w0, p.lanczos_raw)
+    assert info["shifted_qr"][0] == 2
+    ref, _ = dense.smallest_positive(p.A, p.B, p.nev)
+    assert info["converged"]
+    assert np.allclose(lam, ref, rtol=1e-10, atol=0)
+
+
 def test_solver_b_zero_case():
     p = small_problem(50, nev=5, nex=4, deg=10, tol=1e-10)
     lam, V, info = solver.solve(p.A, np.zeros_like(p.B), p.nev, p.nex, p.deg, p.tol,
@@ -407,3 +421,80 @@ def test_adjoint_sampled_entries_match_full_gradient():
     ga, gb = adjoint.eigval_grad_entries(V, g, rows, cols)
     assert np.allclose(ga, GA[np.ix_(rows, cols)], rtol=1e-13, atol=1e-15)
     assert np.allclose(gb, GB[np.ix_(rows, cols)], rtol=1e-13, atol=1e-15)
+
+
+def test_householder_qr_matches_unique_qr():
+    # full column rank: the QR with a positive real diagonal is unique, so
+    # the Householder route and CholeskyQR2 must agree
+    rng = np.random.default_rng(21)
+    X = complex_normal(rng, (60, 12))
+    Qh, Rh = qr.householder_qr(X)
+    Qc, Rc, shifted = qr.cholqr2(X)
+    assert not shifted
+    assert np.max(np.abs(Qh - Qc)) < 1e-12
+    assert np.max(np.abs(Rh - Rc)) < 1e-12 * np.max(np.abs(Rc))
+    assert np.allclose(np.diag(Rh).imag, 0) and np.all(np.diag(Rh).real > 0)
+
+
+def test_orthonormalise_rank_deficient_block():
+    # a zero column and a repeated column: both Cholesky variants break down
+    # and the Householder QR still returns an orthonormal Q with X = Q R
+    rng = np.random.default_rng(22)
+    X = complex_normal(rng, (50, 10))
+    X[:, 3] = 0
+    X[:, 7] = X[:, 2]
+    with pytest.raises(np.linalg.LinAlgError):
+        qr.cholqr2(X)
+    Q, R, variant = qr.orthonormalise(X)
+    assert variant == 2
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(10))) < 1e-13
+    assert np.max(np.abs(Q @ R - X)) < 1e-13 * np.max(np.abs(X))
+    assert np.max(np.abs(np.tril(R, -1))) < 1e-13 * np.max(np.abs(X))
+    d = np.diag(R)
+    assert np.allclose(d.imag, 0) and np.all(d.real >= 0)
+    assert d[3] == 0 and abs(d[7]) < 1e-13 * np.max(np.abs(X))
+    # leading columns before the first dependent one: the unique QR
+    Qu, Ru = qr.householder_qr(X[:, :3])
+    assert np.max(np.abs(Q[:, :3] - Qu)) < 1e-13
+
+
+def _j(X):
+    """J X = K conj(X): swap the halves of the rows and conjugate."""
+    m = X.shape[0] // 2
+    return np.concatenate([X[m:], X[:m]], axis=0).conj()
+
+
+def test_kreal_qr_basis():
+    rng = np.random.default_rng(23)
+    G = complex_normal(rng, (40, 7))
+    Q = qr.kreal_qr(G, lead=3)
+    assert Q.shape == (40, 14)
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(14))) < 1e-13
+    assert np.max(np.abs(_j(Q) - Q)) < 1e-15                       # every column K-real
+    span = np.concatenate([G, _j(G)], axis=1)
+    assert np.max(np.abs(Q @ (Q.conj().T @ span) - span)) < 1e-13 * np.max(np.abs(span))
+    lead = np.concatenate([G[:, :3], _j(G[:, :3])], axis=1)        # first 6 columns: the lead pairs
+    Q6 = Q[:, :6]
+    assert np.max(np.abs(Q6 @ (Q6.conj().T @ lead) - lead)) < 1e-13 * np.max(np.abs(lead))
+
+
+def test_kreal_qr_rank_deficient_keeps_pm_pairs():
+    # a zero generator: the completed basis is still orthonormal, K-real and
+    # K-invariant, so the oblique Rayleigh-Ritz values stay in +/- pairs
+    # (Thm 4.5) with a balanced count
+    p = small_problem(10)
+    rng = np.random.default_rng(24)
+    G = complex_normal(rng, (p.n, 4))
+    G[:, 1] = 0
+    Q = qr.kreal_qr(G)
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(8))) < 1e-13
+    assert np.max(np.abs(_j(Q) - Q)) < 1e-15
+    span = np.concatenate([G, _j(G)], axis=1)
+    assert np.max(np.abs(Q @ (Q.conj().T @ span) - span)) < 1e-13 * np.max(np.abs(span))
+    H = ham.assemble_h(p.A, p.B)
+    S = np.diag(np.r_[np.ones(p.m), -np.ones(p.m)])
+    ev = np.linalg.eigvals(np.linalg.solve(Q.conj().T @ S @ Q, Q.conj().T @ S @ H @ Q))
+    assert np.max(np.abs(ev.imag)) < 1e-8
+    ev = np.sort(ev.real)
+    assert np.sum(ev > 0) == 4
+    assert np.max(np.abs(ev + ev[::-1])) < 1e-9 * np.max(np.abs(ev))
