@@ -106,6 +106,7 @@ def main():
     import torch
     from synth import config_problem
     from paper_2601_10557_amd import FP32, FP64, MIXED, PHSolver, colmajor
+    from paper_2601_10557_amd.solver import mfma_probe
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -135,6 +136,9 @@ def main():
         mixed.solve(W0, Lz)
         fp64.solve(W0, Lz)
         log(f"warmup {i} done")
+    # measured matrix-core ceilings (outside the timed region)
+    probe32, probe64 = mfma_probe(0), mfma_probe(1)
+    log(f"mfma probe: f32 {probe32:.1f} TFLOP/s, f64 {probe64:.1f} TFLOP/s")
 
     torch.cuda.synchronize()
     mixed.profile(True)
@@ -186,11 +190,12 @@ def main():
                   "columns)",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_detail": traffic_detail,
+        "measured_mfma_peak": round(probe32, 1), "frac_of_measured": round(achieved / probe32, 4) if probe32 > 0 else None,
         "launches": n32, "avg_launch_us": round(ms32 * 1e3 / max(n32, 1), 2),
         "avg_flops_per_launch": fl32 / max(n32, 1),
         "algorithmic_gbs": round(by32 / (ms32 * 1e-3) / 1e9, 1) if ms32 > 0 else 0.0,
         "fp64_kernel": {"achieved": round(fl64 / (ms64 * 1e-3) / 1e12, 3) if ms64 > 0 else 0.0,
-                        "peak": PEAK_FP64_TFLOPS, "launches": n64,
+                        "peak": PEAK_FP64_TFLOPS, "measured_mfma_peak": round(probe64, 1), "launches": n64,
                         "avg_launch_us": round(ms64 * 1e3 / max(n64, 1), 2)},
     }
     cpu = None

@@ -213,6 +213,18 @@ chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* 
  * number of apply_h kernel launches it contained. */
 chase_ph_status chase_ph_last_timing(chase_ph_t h, double* ms, int32_t* launches);
 
+/* Matrix-core throughput probe (no handle; runs on the current device and
+ * its null stream, allocates and frees a small output buffer): every wave
+ * of 8 four-wave workgroups per CU issues 4 x iters MFMAs (iters rounded up
+ * to a multiple of 8) on register
+ * operands with four independent accumulators.  kind 0:
+ * v_mfma_f32_32x32x2f32, kind 1: v_mfma_f64_16x16x4f64.  *tflops (host)
+ * gets the best of three timed launches after a warm-up.  Returns 0, or 1
+ * for bad arguments, 2 if the buffer cannot be allocated, 3 on a HIP
+ * error.  A measured ceiling to set the H X kernels against, beside the
+ * published peaks (157.3 and 78.6 TFLOP/s). */
+int32_t chase_ph_mfma_probe(int32_t kind, int32_t iters, double* tflops);
+
 /* Per-launch timing of the H X kernels, for roofline reporting.  With
  * enable = 1 every subsequent apply_h kernel launch on this handle (stage
  * calls, the filter, Lanczos and the Rayleigh-Ritz product inside solve) is

@@ -47,7 +47,7 @@ EXPORTS = [
     "chase_ph_default_params", "chase_ph_create", "chase_ph_destroy", "chase_ph_last_error",
     "chase_ph_apply_h", "chase_ph_filter", "chase_ph_qr", "chase_ph_oblique_rr",
     "chase_ph_residuals", "chase_ph_solve", "chase_ph_eigval_backward", "chase_ph_last_timing",
-    "chase_ph_profile", "chase_ph_profile_read", "chase_ph_filter_refined",
+    "chase_ph_profile", "chase_ph_profile_read", "chase_ph_filter_refined", "chase_ph_mfma_probe",
 ]
 
 
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.chase_ph_last_timing.argtypes = [vp, pd, pi]
     lib.chase_ph_profile.argtypes = [vp, i32]
     lib.chase_ph_profile_read.argtypes = [vp, i32, pd, pd, pd, pi]
+    lib.chase_ph_mfma_probe.argtypes = [i32, i32, pd]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if fn.restype is C.c_int or name not in ("chase_ph_default_params", "chase_ph_last_error"):

@@ -2,14 +2,17 @@
 
     python -m paper_2601_10557_amd.kernel_bench --m 4000 --k 260 [--prec c64|c128|both]
         [--reps 5] [--calib-copy-mib 1024] [--plans "cfg,splits;cfg,splits;..."]
-        [--filter-deg D]
+        [--filter-deg D] [--mfma-probe]
 
 Prints one line per (precision, k) with the best per-launch time (HIP events
 on the library's stream), TFLOP/s at 8 n^2 k flops per launch and the
 algorithmic GB/s.  Each stage call waits for its launches, so a call starts
 on an idle device.  ``--filter-deg D`` instead times the 2 D back-to-back
 launches of one degree-D filter call (fused recurrence epilogue, as inside
-the solver) through the library's per-launch profile and prints their mean.  ``--plans`` repeats each measurement with the tile plan
+the solver) through the library's per-launch profile and prints their mean.
+``--mfma-probe`` first prints the matrix-core throughput measured by
+``chase_ph_mfma_probe`` (f32 and f64), the ceiling the H X kernels are set
+against beside the published peaks.  ``--plans`` repeats each measurement with the tile plan
 forced through ``CHASE_PH_APPLY_PLAN`` (a tuning aid; "auto" is the
 library's own choice, "whole" its choice without the column split).  ``--calib-copy-mib`` first runs a plain device-to-device
 copy of that many MiB, a reference dispatch of known traffic for hardware
@@ -24,6 +27,7 @@ import os
 import torch
 
 from . import FP32, FP64, PHSolver, colmajor, empty_cm
+from .solver import mfma_probe
 
 
 def main(argv=None):
@@ -35,7 +39,12 @@ def main(argv=None):
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--plans", type=str, default="auto")
     ap.add_argument("--filter-deg", type=int, default=0)
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="also print the measured matrix-core throughput (f32 and f64)")
     args = ap.parse_args(argv)
+    if args.mfma_probe:
+        for kind, name, peak in ((0, "v_mfma_f32_32x32x2f32", 157.3), (1, "v_mfma_f64_16x16x4f64", 78.6)):
+            print(f"mfma probe {name}: {mfma_probe(kind):.1f} TFLOP/s (published peak {peak})", flush=True)
     ks = [int(x) for x in args.k.split(",")]
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20

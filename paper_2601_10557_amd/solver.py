@@ -58,6 +58,17 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def mfma_probe(kind: int, iters: int = 10000) -> float:
+    """Measured matrix-core throughput in TFLOP/s (kind 0: FP32
+    v_mfma_f32_32x32x2f32, 1: FP64 v_mfma_f64_16x16x4f64) on the current
+    device; see chase_ph_mfma_probe."""
+    out = C.c_double(0.0)
+    st = lib().chase_ph_mfma_probe(int(kind), int(iters), C.byref(out))
+    if st != 0:
+        raise ChasePHError(_lib.ERR_HIP, f"chase_ph_mfma_probe failed ({st})")
+    return out.value
+
+
 def default_params() -> _lib.Params:
     p = _lib.Params()
     lib().chase_ph_default_params(C.byref(p))
