@@ -55,7 +55,8 @@ typedef enum {
                       /* later ones in the residual-correction form of chase_ph_filter_refined*/
                       /* (FP64 residuals and recombination); QR, Rayleigh-Ritz, residuals   */
                       /* and locking always in FP64                                          */
-  CHASE_PH_FP32 = 2   /* stage calls only: run one apply_h / filter in c64                   */
+  CHASE_PH_FP32 = 2,  /* stage calls only: run one apply_h / filter in c64                   */
+  CHASE_PH_FP64_KREAL = 3 /* chase_ph_apply_h only: c128 with every column of X K-real        */
 } chase_ph_precision;
 
 /* Solver parameters (Alg. 3 inputs plus the paper's defaults).  Fill with
@@ -87,7 +88,7 @@ typedef struct {
   double mu1, mu_nevex0, mu_n; /* Lanczos spectral estimates                                */
   double t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds (stream-timed)       */
   double filter_flops;     /* 16 n^2 per active column per degree                           */
-  double rr_flops;         /* 8 n^2 k + 12 n k^2 + CholeskyQR2 16 n k^2 per iteration        */
+  double rr_flops;         /* 4 n^2 k (H Q on K-real columns) + 12 n k^2 + CholeskyQR2 16 n k^2 */
   double filter_flops_fp32;/* part of filter_flops done in c64                              */
   double* resid_history;   /* optional host array (caller-owned) of max_iter * nevex        */
   int32_t resid_history_len; /* capacity of resid_history in doubles (0 if NULL)           */
@@ -114,8 +115,12 @@ const char* chase_ph_last_error(chase_ph_t h);
 /* Y = H X for an n x k block (Section 1, eq. 1.1; the product behind every
  * GEMM of Alg. 2 and eq. 4.1).  prec: CHASE_PH_FP64 -> dX, dY are c128 and
  * the c128 A, B are used; CHASE_PH_FP32 -> dX, dY are c64 and the c64
- * copies of A, B are used (created on first use).  dX and dY must not
- * overlap.  0 <= k; ldx, ldy >= n. */
+ * copies of A, B are used (created on first use); CHASE_PH_FP64_KREAL ->
+ * as CHASE_PH_FP64 for a block whose columns are K-real (x = [a; conj(a)],
+ * K conj(x) = x), for which H x = [t; -conj(t)] with t = [A B] x: half the
+ * products (the bottom half of dX is not read; the solver's Rayleigh-Ritz
+ * basis is of this kind).  dX and dY must not overlap.  0 <= k;
+ * ldx, ldy >= n. */
 chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_t ldx,
                                  void* dY, int64_t ldy, int32_t prec);
 

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchase_ph.so")
 
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_DEFINITE, ERR_QR, ERR_SINGULAR_QSQ, ERR_NO_CONVERGENCE = range(8)
-FP64, MIXED, FP32 = 0, 1, 2
+FP64, MIXED, FP32, FP64_KREAL = 0, 1, 2, 3
 
 STATUS_NAMES = {
     0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_NOT_DEFINITE",

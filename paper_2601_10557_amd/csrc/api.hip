@@ -174,28 +174,29 @@ Err prof_begin(chase_ph_t h) {
   return ok();
 }
 
-Err prof_end(chase_ph_t h, int prec, int k, size_t elem, bool has_p, bool has_q) {
+// kreal: the call ran on K-real columns (half the products: 4 n^2 k flops).
+Err prof_end(chase_ph_t h, int prec, int k, size_t elem, bool has_p, bool has_q, bool kreal = false) {
   if (!h->prof || h->launches.size() >= PROF_MAX) return ok();
   const size_t i = 2 * h->launches.size();
   CHASE_HIP(hipEventRecord(h->evpool[i + 1], h->st));
   const double n = (double)h->n, m = (double)h->m;
   const double bytes = (2.0 * m * m + (2.0 + (has_p ? 1 : 0) + (has_q ? 1 : 0)) * n * k) * elem;
-  h->launches.push_back({prec, k, 8.0 * n * n * k, bytes});
+  h->launches.push_back({prec, k, (kreal ? 4.0 : 8.0) * n * n * k, bytes});
   return ok();
 }
 
 // Y = alpha H X + beta P + gamma Q on k columns
 Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ldy, double alpha = 1,
             const c128* P = nullptr, int64_t ldp = 0, double beta = 0, const c128* Q = nullptr, int64_t ldq = 0,
-            double gamma = 0) {
+            double gamma = 0, int kreal = 0) {
   ApplyHArgs<double> a{};
   a.A = h->A; a.B = h->B; a.lda = h->ld; a.a_conj = h->p.a_conj; a.m = h->m; a.k = k;
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
-  a.alpha = alpha; a.beta = beta; a.gamma = gamma;
+  a.alpha = alpha; a.beta = beta; a.gamma = gamma; a.kreal = kreal;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
   CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st, &h->side));
-  return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr);
+  return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr, kreal != 0);
 }
 
 Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy, float alpha = 1,
@@ -475,11 +476,21 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
 }
 
 // Alg. 2 (inverse Rayleigh quotient); see chase_ph_oblique_rr.
+// kreal_q: every column of Q is K-real, so T = H Q takes half the products.
+// In a K-real basis the quotient G below is i times a real antisymmetric
+// matrix, whose zero diagonal slows the Jacobi sweeps down; the columns 2j
+// and 2j + 1 of Q and T (the two K-real vectors of one pair) are therefore
+// recombined as (q_2j +- i q_2j+1) / sqrt(2) (unitary: the Ritz pairs do not
+// change), which gives G a nonzero diagonal.  Q is modified in place then.
 Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128* Zpos, int64_t ldz, c128* T,
-            int64_t ldt) {
+            int64_t ldt, bool kreal_q = false) {
   const int kp = pad64(k);
   const int64_t m = h->m, n = h->n;
-  CHASE_TRY(apply64(h, k, Q, ldq, T, ldt));                                   // T = H Q
+  CHASE_TRY(apply64(h, k, Q, ldq, T, ldt, 1, nullptr, 0, 0, nullptr, 0, 0, kreal_q ? 1 : 0));  // T = H Q
+  if (kreal_q) {
+    CHASE_TRY(pair_mix(const_cast<c128*>(Q), ldq, n, k / 2, h->st));
+    CHASE_TRY(pair_mix(T, ldt, n, k / 2, h->st));  // = H (Q after the mix)
+  }
   CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
   CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m, true,
                  GEMM_LOWER_ONLY));  // M = Q^H S T (Hermitian; the Cholesky reads the lower triangle)
@@ -775,17 +786,55 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
         CHASE_TRY(gemm(h, 0, 0, n, kxn, 2 * lq, {-1, 0}, h->Xs, n, h->G, h->kp, {1, 0}, Xn, n));  // X -= Qp C
       }
     }
+    // The basis is built from K-real vectors: each pair (x, J x) of the
+    // block, J x = K conj(x), is replaced by u = (x + J x) / 2 and
+    // v = (x - J x) / (2i), which span the same space and are K-real, and
+    // the Cholesky QR runs on their real coordinates.  The orthonormal basis
+    // is then K-real too, so H Q takes half the products (H [a; conj(a)] =
+    // [t; -conj(t)], t = [A B] [a; conj(a)]) and the span is the one the
+    // complex block would give.
+    // The coordinates go to Tq (free until the Rayleigh-Ritz step), the
+    // pair of each generator in adjacent columns.
+    CHASE_TRY(kreal_pairs(Xn, n, ln, kw, m, h->Tq, n, h->st));
     int used = 0;
-    CHASE_TRY(qr_impl(h, kxn, Xn, n, nullptr, 0, &used, false));
+    CHASE_TRY(qr_impl(h, kxn, h->Tq, n, nullptr, 0, &used, false));
+    if (used != 2) {
+      CHASE_TRY(kreal_unpack(h->Tq, n, m, kxn, h->st));
+      CHASE_HIP(hipMemcpy2DAsync(Xn, n * sizeof(c128), h->Tq, n * sizeof(c128), n * sizeof(c128), kxn,
+                                 hipMemcpyDeviceToDevice, h->st));
+    }
     if (used == 2) {
       // Numerically rank-deficient block: Householder QR of the real
-      // coordinates of the K-real parts of all pairs, locked ones first.  The
-      // basis it completes the block with is K-real too, so the span stays
-      // K-invariant (Thm 4.5 keeps the Ritz values in +/- pairs), and the
-      // locked span keeps its leading columns.
+      // coordinates of the K-real parts of all pairs, locked ones first, so
+      // that the locked span keeps its leading columns.  Its completion
+      // directions would be K-real, hence S-neutral, which leaves Q^H S Q
+      // nearly singular and slows the oblique Rayleigh-Ritz down; so every
+      // unlocked pair whose coordinates R shows dependent (|R_jj| <= 1e3 u
+      // max |R_ii|) gets the coordinates of the unit vectors e_r and
+      // i e_r in the top half (the S-definite pair [e_r; 0], [0; e_r] once
+      // recombined, Section 4.6), and the QR is repeated.
       const int kall = 2 * locked + 2 * kw;
       CHASE_TRY(kreal_build(h->Ylock, n, locked, h->Wk, n, kw, h->Xs, n, m, h->st));
-      CHASE_TRY(householder_qr(h->Xs, n, n, kall, nullptr, 0, h->hhw, h->st));
+      CHASE_TRY(householder_qr(h->Xs, n, n, kall, h->G, h->kp, h->hhw, h->st));
+      std::vector<c128> rdiag(kall);
+      CHASE_HIP(hipMemcpy2DAsync(rdiag.data(), sizeof(c128), h->G, (h->kp + 1) * sizeof(c128), sizeof(c128), kall,
+                                 hipMemcpyDeviceToHost, h->st));
+      CHASE_HIP(hipStreamSynchronize(h->st));
+      double rmax = 0;
+      for (const c128& z : rdiag) rmax = std::max(rmax, std::fabs(z.re));
+      std::vector<int> refill;
+      for (int q = locked; q < locked + kw; ++q)
+        if (std::fabs(rdiag[2 * q].re) <= 1e3 * U_ROUND * rmax || std::fabs(rdiag[2 * q + 1].re) <= 1e3 * U_ROUND * rmax)
+          refill.push_back(q);
+      if (!refill.empty()) {
+        CHASE_TRY(kreal_build(h->Ylock, n, locked, h->Wk, n, kw, h->Xs, n, m, h->st));
+        for (size_t t = 0; t < refill.size(); ++t) {
+          const int64_t r = ((int64_t)refill[t] * 7919) % m;
+          CHASE_TRY(unit_column(h->Xs + (int64_t)2 * refill[t] * n, n, r, h->st));
+          CHASE_TRY(unit_column(h->Xs + (int64_t)(2 * refill[t] + 1) * n, n, m + r, h->st));
+        }
+        CHASE_TRY(householder_qr(h->Xs, n, n, kall, nullptr, 0, h->hhw, h->st));
+      }
       CHASE_TRY(kreal_unpack(h->Xs, n, m, kall, h->st));
     }
     lq = locked;
@@ -796,14 +845,14 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     const c128* Q = h->Xs + (int64_t)2 * locked * n;
     const int kq = 2 * kw;
     CHASE_TRY(tm.start());
-    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n));
+    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n, true));
     CHASE_TRY(tm.stop(&inf.t_rr));
     // half back-transform and residuals (Section 4.5)
     CHASE_TRY(tm.start());
     CHASE_TRY(resid_impl(h, kq, kw, Q, n, h->Tq, n, h->Zp, h->kmax, nullptr, h->Vt, n, res.data(),
                          mixed ? h->Rv : nullptr));
     CHASE_TRY(tm.stop(&inf.t_resid));
-    inf.rr_flops += 8.0 * n * n * kq + 12.0 * n * (double)kq * kq + qr_flops;
+    inf.rr_flops += 4.0 * n * n * kq + 12.0 * n * (double)kq * kq + qr_flops;
     if (inf.resid_history && hist_pos + kw <= inf.resid_history_len) {
       std::copy(res.begin(), res.begin() + kw, inf.resid_history + hist_pos);
       hist_pos += kw;
@@ -1089,7 +1138,7 @@ chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_
                                  int32_t prec) {
   CHECK_HANDLE(h);
   if (k < 0 || (k > 0 && (!dX || !dY)) || ldx < h->n || ldy < h->n ||
-      (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32))
+      (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32 && prec != CHASE_PH_FP64_KREAL))
     return finish(h, fail(CHASE_PH_ERR_ARG, "apply_h: bad arguments"));
   if (k == 0) return CHASE_PH_OK;
   Err e = ok();
@@ -1098,7 +1147,8 @@ chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_
     e = ensure_shadow(h);
     if (!e) e = apply32(h, k, (const c64*)dX, ldx, (c64*)dY, ldy);
   } else {
-    e = apply64(h, k, (const c128*)dX, ldx, (c128*)dY, ldy);
+    e = apply64(h, k, (const c128*)dX, ldx, (c128*)dY, ldy, 1, nullptr, 0, 0, nullptr, 0, 0,
+                prec == CHASE_PH_FP64_KREAL ? 1 : 0);
   }
   if (e) return finish(h, e);
   float ms = 0;

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
 
   const int m = (int)a.m;
   const int kc = a.k;
-  const int N2 = 2 * kc;
+  const int N2 = a.kreal ? kc : 2 * kc;
   const int TM = (m + BM - 1) / BM;
   const int TN = (N2 + BN - 1) / BN;
   const int T = TM * TN;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
       const int kk = (el % (BK / VB)) * VB;
       const int gj = n0 + j, gk = kk0 + kk;
       const bool ok = gj < N2 && gk < m;
-      const bool bot = gj >= kc;
+      const bool bot = !a.kreal && gj >= kc;
       const int64_t col = bot ? gj - kc : gj;
       const int64_t row = (int64_t)(bot ? 1 - phase : phase) * m + gk;
       const int64_t idx = ok ? col * a.ldx + row : 0;
@@ -377,6 +377,7 @@ __global__ __launch_bounds__(64 * WGM* WGN) __attribute__((amdgpu_waves_per_eu(2
             wsp[(int64_t)gc * m + gr] = z;
           } else {
             epilogue_store<R, C>(a, gr, gc, accr[i][j][r], acci[i][j][r]);
+            if (a.kreal) epilogue_store<R, C>(a, gr, gc + kc, accr[i][j][r], acci[i][j][r]);
           }
         }
       }
@@ -608,7 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 template <typename R, typename C>
 __global__ void apply_h_reduce(const ApplyHArgs<R> a, int splits, const C* ws) {
   const int m = (int)a.m;
-  const int64_t total = (int64_t)m * 2 * a.k;
+  const int64_t total = (int64_t)m * (a.kreal ? 1 : 2) * a.k;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int gc = (int)(t / m), gr = (int)(t % m);
     R sr = 0, si = 0;
@@ -618,6 +619,7 @@ __global__ void apply_h_reduce(const ApplyHArgs<R> a, int splits, const C* ws) {
       si += z.im;
     }
     epilogue_store<R, C>(a, gr, gc, sr, si);
+    if (a.kreal) epilogue_store<R, C>(a, gr, gc + a.k, sr, si);
   }
 }
 
@@ -670,7 +672,7 @@ Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hip
                      s, a, p.splits, p.kps, (C*)ws);
   CHASE_LAUNCH_CHECK();
   if (p.splits > 1) {
-    const int64_t total = a.m * 2 * (int64_t)a.k;
+    const int64_t total = a.m * (a.kreal ? 1 : 2) * (int64_t)a.k;
     const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 8192);
     hipLaunchKernelGGL((apply_h_reduce<typename Tr::R, C>), dim3(blocks), dim3(256), 0, s, a, p.splits, (const C*)ws);
     CHASE_LAUNCH_CHECK();
@@ -719,6 +721,7 @@ void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const 
 
 static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.k <= 0 || a.m <= 0) return ok();
+  if (a.kreal) return fail(CHASE_PH_ERR_ARG, "apply_h: K-real columns are a c128 mode");
   // 32 x 32 MFMA tiles: 0 (256 x 64), 3 (128 x 64), 4 (128 x 128); 16 x 16
   // MFMA tiles, whose widths cover N = 2k with less padding: 1 (256 x 32),
   // 2 (256 x 48), 5 (128 x 32), 6 (128 x 48).  All fit two workgroups per
@@ -769,8 +772,9 @@ static Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes
   static const double eff[4] = {1.0, 0.8, 1.2, 0.8};
   static const int occ[4] = {1, 1, 2, 2};
   const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<4>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.02, sizeof(c128), wsb);
-  plan_override<4>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c128), wsb);
+  const int64_t n2 = (a.kreal ? 1 : 2) * (int64_t)a.k;
+  Plan p = make_plan<4>(a.m, n2, bm, bn, bk, eff, occ, 0.02, sizeof(c128), wsb);
+  plan_override<4>(p, a.m, n2, bm, bn, bk, sizeof(c128), wsb);
   plan_log("c128", a.m, a.k, p);
   switch (p.cfg) {
     case 0: return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
@@ -801,7 +805,8 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
   const char* nosplit = std::getenv("CHASE_PH_NO_SPLIT");
   const char* smax = std::getenv("CHASE_PH_SPLIT_MAX");
   const int rmax = smax ? std::atoi(smax) : (sizeof(R) == 4 ? 20 : 16);
-  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < 2 * gran || (nosplit && nosplit[0] == '1'))
+  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < 2 * gran || a.kreal ||
+      (nosplit && nosplit[0] == '1'))
     return one(a, ws, ws_bytes, s);
   using C = typename ApplyHArgs<R>::C;
   ApplyHArgs<R> am = a, ar = a;

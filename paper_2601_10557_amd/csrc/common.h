@@ -99,6 +99,10 @@ struct ApplyHArgs {
   const C* S;       // may be null
   int64_t lds;
   const R* dcol;    // k per-column scalars for S (device)
+  // 1: every column of X is K-real (x = [a; conj(a)]), so K conj(X) = X and
+  // H x = [t; -conj(t)] with t = [A B] x: the product runs on the k columns
+  // of X only and the epilogue writes both halves (c128 path, no P/Q/S)
+  int kreal = 0;
 };
 
 // ws: device workspace for split-K partial products (ws_bytes may be 0:

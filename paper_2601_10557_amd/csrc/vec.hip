@@ -252,7 +252,7 @@ __global__ void scale_c64_kernel(const c64* src, int64_t lds, c64* dst, int64_t 
 // stored by its real coordinates [Re a; Im a] (n reals, held in the real
 // parts of a c128 column with zero imaginary parts); inner products of
 // K-real vectors are twice the real inner products of their coordinates.
-// Columns: u of S y_j (j < L), v of S y_j, u of w_j (j < kw), v of w_j.
+// Columns 2j, 2j + 1: u, v of S y_j (j < L), then u, v of w_j (j < kw).
 __global__ void kreal_build_kernel(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X,
                                    int64_t ldx, int64_t m) {
   const int cols = 2 * L + 2 * kw;
@@ -260,19 +260,16 @@ __global__ void kreal_build_kernel(const c128* Y, int64_t ldy, int L, const c128
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(t / m);
     const int64_t i = t % m;
+    const int j = c / 2;
+    const bool vpart = c & 1;
     c128 x1, x2;
-    bool vpart;
-    if (c < 2 * L) {
-      const int j = c < L ? c : c - L;
+    if (j < L) {
       x1 = Y[(int64_t)j * ldy + i];
       const c128 y2 = Y[(int64_t)j * ldy + m + i];
       x2 = c128{-y2.re, -y2.im};  // S y
-      vpart = c >= L;
     } else {
-      const int j = c - 2 * L < kw ? c - 2 * L : c - 2 * L - kw;
-      x1 = W[(int64_t)j * ldw + i];
-      x2 = W[(int64_t)j * ldw + m + i];
-      vpart = c - 2 * L >= kw;
+      x1 = W[(int64_t)(j - L) * ldw + i];
+      x2 = W[(int64_t)(j - L) * ldw + m + i];
     }
     // top half a of u (x1 + conj(x2)) / 2 or of v (x1 - conj(x2)) / (2i)
     c128 a;
@@ -285,6 +282,49 @@ __global__ void kreal_build_kernel(const c128* Y, int64_t ldy, int L, const c128
     X[(int64_t)c * ldx + i] = c128{a.re, 0.0};
     X[(int64_t)c * ldx + m + i] = c128{a.im, 0.0};
   }
+}
+
+// Search block [G1, G1', G2, G2'] (widths L, L, kw, kw; the primed columns
+// are the J-partners of the unprimed ones) -> real coordinates in dst,
+// columns 2q and 2q + 1 for the q-th generator x (q < L + kw): those of
+// u = (x + J x) / 2 and of v = (x - J x) / (2i) (J x is formed from x; the
+// partner columns are not read).
+__global__ void kreal_pairs_kernel(const c128* X, int64_t ldx, int L, int kw, int64_t m, c128* D, int64_t ldd) {
+  const int pairs = L + kw;
+  const int64_t total = m * pairs;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(t / m);
+    const int64_t i = t % m;
+    const int g = q < L ? q : L + q;  // generator column
+    const c128 x1 = X[(int64_t)g * ldx + i], x2 = X[(int64_t)g * ldx + m + i];
+    const double ur = 0.5 * (x1.re + x2.re), ui = 0.5 * (x1.im - x2.im);
+    const double dr = x1.re - x2.re, di = x1.im + x2.im;
+    c128* du = D + (int64_t)(2 * q) * ldd;
+    c128* dv = D + (int64_t)(2 * q + 1) * ldd;
+    du[i] = c128{ur, 0.0};
+    du[m + i] = c128{ui, 0.0};
+    dv[i] = c128{0.5 * di, 0.0};
+    dv[m + i] = c128{-0.5 * dr, 0.0};
+  }
+}
+
+// In place, columns 2j and 2j + 1 (j < npair): (x, y) -> ((x + i y),
+// (x - i y)) / sqrt(2), a unitary change of basis.
+__global__ void pair_mix_kernel(c128* X, int64_t ldx, int64_t n, int npair) {
+  const int64_t total = n * npair;
+  const double h = 0.70710678118654752440;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / n, i = t % n;
+    const c128 x = X[2 * j * ldx + i], y = X[(2 * j + 1) * ldx + i];
+    X[2 * j * ldx + i] = c128{h * (x.re - y.im), h * (x.im + y.re)};
+    X[(2 * j + 1) * ldx + i] = c128{h * (x.re + y.im), h * (x.im - y.re)};
+  }
+}
+
+// x = e_r (n entries).
+__global__ void unit_column_kernel(c128* x, int64_t n, int64_t r) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = c128{i == r ? 1.0 : 0.0, 0.0};
 }
 
 // In place: real coordinates [r1; r2] of unit length -> the unit K-real
@@ -307,6 +347,27 @@ Err kreal_build(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, i
   const int64_t total = m * (2 * L + 2 * kw);
   if (total == 0) return ok();
   hipLaunchKernelGGL(kreal_build_kernel, dim3(grid_for(total)), dim3(256), 0, s, Y, ldy, L, W, ldw, kw, X, ldx, m);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err kreal_pairs(const c128* X, int64_t ldx, int L, int kw, int64_t m, c128* D, int64_t ldd, hipStream_t s) {
+  const int64_t total = m * (L + kw);
+  if (total == 0) return ok();
+  hipLaunchKernelGGL(kreal_pairs_kernel, dim3(grid_for(total)), dim3(256), 0, s, X, ldx, L, kw, m, D, ldd);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err unit_column(c128* x, int64_t n, int64_t r, hipStream_t s) {
+  hipLaunchKernelGGL(unit_column_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, r);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err pair_mix(c128* X, int64_t ldx, int64_t n, int npair, hipStream_t s) {
+  if (n * npair == 0) return ok();
+  hipLaunchKernelGGL(pair_mix_kernel, dim3(grid_for(n * npair)), dim3(256), 0, s, X, ldx, n, npair);
   CHASE_LAUNCH_CHECK();
   return ok();
 }

@@ -76,6 +76,21 @@ def test_apply_h_fp32_every_tile_plan(prob, solver, plan, k, monkeypatch):
     assert np.max(np.abs(Y - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("k", [1, 37, 70])
+def test_apply_h_fp64_kreal(prob, solver80, k):
+    # K-real columns x = [a; conj(a)]: H x = [t; -conj(t)] from half the
+    # products, against the oracle's H X and the general c128 mode
+    print_case("apply_h_fp64_kreal", m=prob.m, k=k)
+    rng = np.random.default_rng(500 + k)
+    a = complex_normal(rng, (prob.m, k))
+    X = np.concatenate([a, a.conj()], axis=0)
+    Y = to_host(solver80.apply_h(to_dev(X), prec=_lib.FP64_KREAL))
+    ref = ham.apply_h(prob.A, prob.B, X)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    Yg = to_host(solver80.apply_h(to_dev(X), prec=FP64))
+    assert np.max(np.abs(Y - Yg)) <= 1e-13 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("plan", ["0,1", "0,3", "1,2", "2,1", "2,4", "3,1", "3,5"])
 @pytest.mark.parametrize("k", [37, 61])
 def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
