@@ -126,7 +126,7 @@ Err h2d(chase_ph_t h, void* dst, const void* src, size_t bytes) {
 }
 
 // Structure flags of gemm(): see ZgemmArgs.
-constexpr int GEMM_LOWER_ONLY = 1, GEMM_A_LOWER = 2, GEMM_B_UPPER = 4;
+constexpr int GEMM_LOWER_ONLY = 1, GEMM_A_LOWER = 2, GEMM_B_UPPER = 4, GEMM_REAL = 8;
 
 Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alpha, const c128* A, int64_t lda,
          const c128* B, int64_t ldb, c128 beta, c128* C, int64_t ldc, int64_t kneg = -1, bool split = true,
@@ -135,6 +135,7 @@ Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alp
   g.lower_only = (flags & GEMM_LOWER_ONLY) != 0;
   g.a_lower = (flags & GEMM_A_LOWER) != 0;
   g.b_upper = (flags & GEMM_B_UPPER) != 0;
+  g.real_data = (flags & GEMM_REAL) != 0;
   g.transA = ta; g.transB = tb;
   g.M = M; g.N = N; g.K = K;
   g.alpha = alpha; g.beta = beta;
@@ -389,16 +390,19 @@ Err filter_any(chase_ph_t h, int k, void* dW, int64_t ldw, const std::vector<int
 }
 
 // One Cholesky-QR pass: Xout = Xin L^{-H} with L L^H = Xin^H Xin + shift I.
+// real: Xin is real (held in c128), and so are the Gram matrix, L and Xout.
 Err cholqr_pass(chase_ph_t h, int k, int kp, const c128* Xin, int64_t ldin, c128* Xout, int64_t ldout, c128* Lbuf,
-                double shift, bool* failed) {
+                double shift, bool* failed, bool real = false) {
+  const int rf = real ? GEMM_REAL : 0;
   CHASE_TRY(fill_padded(Lbuf, kp, k, 0.0, 1.0, true, h->st));
   // Gram matrix: the Cholesky reads its lower triangle only
-  CHASE_TRY(gemm(h, 1, 0, k, k, h->n, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp, -1, true, GEMM_LOWER_ONLY));
+  CHASE_TRY(gemm(h, 1, 0, k, k, h->n, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp, -1, true,
+                 GEMM_LOWER_ONLY | rf));
   if (shift != 0.0) CHASE_TRY(add_diag(Lbuf, kp, k, shift, h->st));
   CHASE_TRY(cholesky_lower(Lbuf, kp, h->dws, h->st, failed));
   if (*failed) return ok();
   CHASE_TRY(tri_inverse_lower(Lbuf, h->Li, kp, h->dws, h->st));
-  return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout, -1, true, GEMM_B_UPPER);
+  return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout, -1, true, GEMM_B_UPPER | rf);
 }
 
 // Householder QR of X in place; with npre = 2, X is the output of two
@@ -424,16 +428,16 @@ Err householder_fallback(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int
 // With householder = false the breakdown is only reported (*used_shift = 2,
 // X unspecified): the solver then orthonormalises the K-real form instead.
 Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift,
-            bool householder = true) {
+            bool householder = true, bool real = false) {
   if (used_shift) *used_shift = 0;
   if (k == 0) return ok();
   const int kp = pad64(k);
   const int64_t n = h->n;
   bool failed = false;
-  CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, 0.0, &failed));
+  CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, 0.0, &failed, real));
   int nf = 2;
   if (!failed) {
-    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
+    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real));
     if (failed) {
       if (used_shift) *used_shift = 2;
       return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0) : ok();
@@ -442,19 +446,20 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
     if (used_shift) *used_shift = 1;
     // shifted CholeskyQR3: s = 11 (n k + k (k + 1)) u ||X||_F^2
     CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
-    CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, X, ldx, X, ldx, {0, 0}, h->G, kp, -1, true, GEMM_LOWER_ONLY));
+    CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, X, ldx, X, ldx, {0, 0}, h->G, kp, -1, true,
+                   GEMM_LOWER_ONLY | (real ? GEMM_REAL : 0)));
     CHASE_TRY(trace(h->G, kp, k, h->dws.dscalar, h->st));
     double fro2 = 0;
     CHASE_HIP(hipMemcpyAsync(&fro2, h->dws.dscalar, sizeof(double), hipMemcpyDeviceToHost, h->st));
     CHASE_HIP(hipStreamSynchronize(h->st));
     const double shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * U_ROUND * fro2;
-    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed));
-    if (!failed) CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed));
+    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed, real));
+    if (!failed) CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real));
     if (failed) {
       if (used_shift) *used_shift = 2;
       return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0) : ok();
     }
-    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L3, 0.0, &failed));
+    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L3, 0.0, &failed, real));
     if (failed) {
       if (used_shift) *used_shift = 2;
       return householder ? householder_fallback(h, k, X, ldx, R, ldr, 2) : ok();
@@ -797,7 +802,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     // pair of each generator in adjacent columns.
     CHASE_TRY(kreal_pairs(Xn, n, ln, kw, m, h->Tq, n, h->st));
     int used = 0;
-    CHASE_TRY(qr_impl(h, kxn, h->Tq, n, nullptr, 0, &used, false));
+    CHASE_TRY(qr_impl(h, kxn, h->Tq, n, nullptr, 0, &used, false, true));
     if (used != 2) {
       CHASE_TRY(kreal_unpack(h->Tq, n, m, kxn, h->st));
       CHASE_HIP(hipMemcpy2DAsync(Xn, n * sizeof(c128), h->Tq, n * sizeof(c128), n * sizeof(c128), kxn,

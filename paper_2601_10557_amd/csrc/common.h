@@ -144,6 +144,10 @@ struct ZgemmArgs {
   //  a_lower:    op(A) is lower triangular (op(A)[i][k] = 0 for k > i);
   //  b_upper:    op(B) is upper triangular (op(B)[k][j] = 0 for k > j).
   int lower_only = 0, a_lower = 0, b_upper = 0;
+  // real_data: A, B and alpha have zero imaginary parts (real matrices held
+  // in c128), so only the real-by-real MFMA of each step is issued (a
+  // quarter of the work); C gets zero imaginary parts (beta real).
+  int real_data = 0;
 };
 // workspace: device buffer of ws_bytes (may be 0 => no split-K)
 Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s);

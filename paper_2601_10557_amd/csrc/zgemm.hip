@@ -5,7 +5,8 @@
 // Q2^H Q2), the back-transforms Q Z and T Z, the triangular products of the
 // Cholesky / inverse / Jacobi kernels (batched) and the adjoint contraction.
 // Tall-skinny inner products (K >> M, N) are split along K into a workspace
-// and reduced in a fixed order (deterministic).
+// and reduced in a fixed order (deterministic).  Real matrices held in c128
+// (real_data) take only the real-by-real MFMA of each step.
 #include "common.h"
 
 namespace chase {
@@ -32,11 +33,13 @@ struct ZgemmDev {
   int64_t ldc, strideC;
   int64_t kneg;
   int lower_only, a_lower, b_upper;
+  int real_data;
   int splits;
   int64_t kchunk;  // K range per split (multiple of BK)
   c128* ws;        // splits * batch * M * N partials (split-K only)
 };
 
+template <bool REAL>
 __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
   __shared__ double As[2][2][BK][LDS_A];
   __shared__ double Bs[2][2][BK][LDS_B];
@@ -145,20 +148,27 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
         fb_i[j] = Bs[buf][1][ks + lk][wn0 + 16 * j + lr];
         fb_n[j] = -fb_i[j];
       }
+      if constexpr (REAL) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
-          ci[i][j] = mfma64(fa_r[i], fb_i[j], ci[i][j]);
-        }
+          for (int j = 0; j < 2; ++j) cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
+      } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          cr[i][j] = mfma64(fa_i[i], fb_n[j], cr[i][j]);
-          ci[i][j] = mfma64(fa_i[i], fb_r[j], ci[i][j]);
-        }
+          for (int j = 0; j < 2; ++j) {
+            cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
+            ci[i][j] = mfma64(fa_r[i], fb_i[j], ci[i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cr[i][j] = mfma64(fa_i[i], fb_n[j], cr[i][j]);
+            ci[i][j] = mfma64(fa_i[i], fb_r[j], ci[i][j]);
+          }
+      }
     }
     if (kt + 1 < KT) store(buf ^ 1);
     __syncthreads();
@@ -229,6 +239,7 @@ Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   g.C = a.C; g.ldc = a.ldc; g.strideC = a.strideC;
   g.kneg = a.kneg;
   g.lower_only = a.lower_only; g.a_lower = a.a_lower; g.b_upper = a.b_upper;
+  g.real_data = a.real_data;
   const int64_t tiles = ceil_div(a.M, BM) * ceil_div(a.N, BN);
   const int64_t tm = ceil_div(a.M, BM);
   const int64_t work_tiles = a.lower_only ? tm * (tm + 1) / 2 : tiles;  // tiles that compute
@@ -246,8 +257,12 @@ Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   splits = (int)ceil_div(std::max<int64_t>(a.K, 1), g.kchunk);
   g.splits = splits;
   g.ws = (c128*)ws;
-  hipLaunchKernelGGL(zgemm_kernel, dim3((unsigned)tiles, (unsigned)a.batch, (unsigned)splits),
-                     dim3(NT), 0, s, g);
+  if (a.real_data)
+    hipLaunchKernelGGL(zgemm_kernel<true>, dim3((unsigned)tiles, (unsigned)a.batch, (unsigned)splits), dim3(NT), 0,
+                       s, g);
+  else
+    hipLaunchKernelGGL(zgemm_kernel<false>, dim3((unsigned)tiles, (unsigned)a.batch, (unsigned)splits), dim3(NT), 0,
+                       s, g);
   CHASE_LAUNCH_CHECK();
   if (splits > 1) {
     const int64_t total = (int64_t)a.batch * a.M * a.N;
