@@ -784,23 +784,26 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     c128* Xn = h->Xs + (int64_t)2 * lq * n;
     const int kxn = 2 * ln + 2 * kw;
     const double qr_flops = 16.0 * n * (double)kxn * kxn + 64.0 * n * (double)lq * kxn;
-    CHASE_TRY(build_search_block(h->Ylock + (int64_t)lq * n, n, ln, h->Wk, n, kw, Xn, n, m, h->st));
-    if (lq > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        CHASE_TRY(gemm(h, 1, 0, 2 * lq, kxn, n, {1, 0}, h->Xs, n, Xn, n, {0, 0}, h->G, h->kp));    // C = Qp^H X
-        CHASE_TRY(gemm(h, 0, 0, n, kxn, 2 * lq, {-1, 0}, h->Xs, n, h->G, h->kp, {1, 0}, Xn, n));  // X -= Qp C
-      }
-    }
     // The basis is built from K-real vectors: each pair (x, J x) of the
     // block, J x = K conj(x), is replaced by u = (x + J x) / 2 and
     // v = (x - J x) / (2i), which span the same space and are K-real, and
-    // the Cholesky QR runs on their real coordinates.  The orthonormal basis
+    // the projection and the Cholesky QR run on their real coordinates
+    // (inner products of K-real vectors are real).  The orthonormal basis
     // is then K-real too, so H Q takes half the products (H [a; conj(a)] =
     // [t; -conj(t)], t = [A B] [a; conj(a)]) and the span is the one the
-    // complex block would give.
-    // The coordinates go to Tq (free until the Rayleigh-Ritz step), the
-    // pair of each generator in adjacent columns.
-    CHASE_TRY(kreal_pairs(Xn, n, ln, kw, m, h->Tq, n, h->st));
+    // complex block would give.  The coordinates go to Tq (free until the
+    // Rayleigh-Ritz step), the pair of each generator in adjacent columns;
+    // those of the locked basis, for the projection, to Xt.
+    CHASE_TRY(kreal_build(h->Ylock + (int64_t)lq * n, n, ln, h->Wk, n, kw, h->Tq, n, m, h->st));
+    if (lq > 0) {
+      CHASE_TRY(kreal_coords(h->Xs, n, m, 2 * lq, h->Xt, n, h->st));
+      for (int pass = 0; pass < 2; ++pass) {
+        CHASE_TRY(gemm(h, 1, 0, 2 * lq, kxn, n, {1, 0}, h->Xt, n, h->Tq, n, {0, 0}, h->G, h->kp, -1, true,
+                       GEMM_REAL));  // C = Qp^T X
+        CHASE_TRY(gemm(h, 0, 0, n, kxn, 2 * lq, {-1, 0}, h->Xt, n, h->G, h->kp, {1, 0}, h->Tq, n, -1, true,
+                       GEMM_REAL));  // X -= Qp C
+      }
+    }
     int used = 0;
     CHASE_TRY(qr_impl(h, kxn, h->Tq, n, nullptr, 0, &used, false, true));
     if (used != 2) {

@@ -4,17 +4,13 @@
 
 namespace chase {
 
-Err build_search_block(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx,
-                       int64_t m, hipStream_t s);
 // Real coordinates (in the real parts; imaginary parts 0) of the K-real
 // pair vectors u, v of S y_j (j < L) and w_j (j < kw): n x (2L + 2kw),
 // columns 2q, 2q + 1 for the q-th generator.
 Err kreal_build(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx, int64_t m,
                 hipStream_t s);
-// [G1, G1', G2, G2'] (widths L, L, kw, kw; primed = J-partners) -> D
-// (n x 2(L + kw)): columns 2q, 2q + 1 = real coordinates of u, v of the q-th
-// generator.
-Err kreal_pairs(const c128* X, int64_t ldx, int L, int kw, int64_t m, c128* D, int64_t ldd, hipStream_t s);
+// Real coordinates sqrt(2) [Re a; Im a] of unit K-real columns [a; conj(a)].
+Err kreal_coords(const c128* Q, int64_t ldq, int64_t m, int k, c128* D, int64_t ldd, hipStream_t s);
 // x = e_r (n entries).
 Err unit_column(c128* x, int64_t n, int64_t r, hipStream_t s);
 // In place, columns 2j and 2j + 1: (x, y) -> (x + i y, x - i y) / sqrt(2).

@@ -1,6 +1,8 @@
-// Elementwise and column-reduction kernels of the solver loop: assembling
-// the search block with the S / K conj structure folded in (Section 4.3,
-// eq. 4.5; Thm 4.2), c128 <-> c64 conversion of the filter block, the fused
+// Elementwise and column-reduction kernels of the solver loop: the real
+// coordinates of the K-real pairs of the search block [S Y, S K conj(Y), W,
+// K conj(W)] (Section 4.3, eq. 4.5; Thm 4.2) and their inverse, the pair
+// recombination before the Rayleigh-Ritz quotient, c128 <-> c64 conversion
+// of the filter block, the fused
 // residual / normalisation of the half back-transform (Section 4.5),
 // S-inner products of the Lanczos estimates (Section 4.1) and the operand
 // build of the eigenvalue adjoint.
@@ -13,35 +15,6 @@ namespace chase {
 namespace {
 
 inline int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 8192)); }
-
-// X = [S Y, S K conj(Y), W, K conj(W)]   (Y: n x L, W: n x kw)
-__global__ void build_x_kernel(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X,
-                               int64_t ldx, int64_t m) {
-  const int64_t n = 2 * m;
-  const int cols = 2 * L + 2 * kw;
-  const int64_t total = n * cols;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(t / n);
-    const int64_t i = t % n;
-    c128 z;
-    if (c < L) {
-      z = Y[(int64_t)c * ldy + i];
-      if (i >= m) { z.re = -z.re; z.im = -z.im; }
-    } else if (c < 2 * L) {
-      const int64_t src = i < m ? i + m : i - m;
-      z = Y[(int64_t)(c - L) * ldy + src];
-      z.im = -z.im;
-      if (i >= m) { z.re = -z.re; z.im = -z.im; }
-    } else if (c < 2 * L + kw) {
-      z = W[(int64_t)(c - 2 * L) * ldw + i];
-    } else {
-      const int64_t src = i < m ? i + m : i - m;
-      z = W[(int64_t)(c - 2 * L - kw) * ldw + src];
-      z.im = -z.im;
-    }
-    X[(int64_t)c * ldx + i] = z;
-  }
-}
 
 __global__ void to_c64_kernel(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols) {
   const int64_t total = rows * cols;
@@ -284,30 +257,6 @@ __global__ void kreal_build_kernel(const c128* Y, int64_t ldy, int L, const c128
   }
 }
 
-// Search block [G1, G1', G2, G2'] (widths L, L, kw, kw; the primed columns
-// are the J-partners of the unprimed ones) -> real coordinates in dst,
-// columns 2q and 2q + 1 for the q-th generator x (q < L + kw): those of
-// u = (x + J x) / 2 and of v = (x - J x) / (2i) (J x is formed from x; the
-// partner columns are not read).
-__global__ void kreal_pairs_kernel(const c128* X, int64_t ldx, int L, int kw, int64_t m, c128* D, int64_t ldd) {
-  const int pairs = L + kw;
-  const int64_t total = m * pairs;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(t / m);
-    const int64_t i = t % m;
-    const int g = q < L ? q : L + q;  // generator column
-    const c128 x1 = X[(int64_t)g * ldx + i], x2 = X[(int64_t)g * ldx + m + i];
-    const double ur = 0.5 * (x1.re + x2.re), ui = 0.5 * (x1.im - x2.im);
-    const double dr = x1.re - x2.re, di = x1.im + x2.im;
-    c128* du = D + (int64_t)(2 * q) * ldd;
-    c128* dv = D + (int64_t)(2 * q + 1) * ldd;
-    du[i] = c128{ur, 0.0};
-    du[m + i] = c128{ui, 0.0};
-    dv[i] = c128{0.5 * di, 0.0};
-    dv[m + i] = c128{-0.5 * dr, 0.0};
-  }
-}
-
 // In place, columns 2j and 2j + 1 (j < npair): (x, y) -> ((x + i y),
 // (x - i y)) / sqrt(2), a unitary change of basis.
 __global__ void pair_mix_kernel(c128* X, int64_t ldx, int64_t n, int npair) {
@@ -318,6 +267,19 @@ __global__ void pair_mix_kernel(c128* X, int64_t ldx, int64_t n, int npair) {
     const c128 x = X[2 * j * ldx + i], y = X[(2 * j + 1) * ldx + i];
     X[2 * j * ldx + i] = c128{h * (x.re - y.im), h * (x.im + y.re)};
     X[(2 * j + 1) * ldx + i] = c128{h * (x.re + y.im), h * (x.im - y.re)};
+  }
+}
+
+// Real coordinates sqrt(2) [Re a; Im a] of unit K-real columns [a; conj(a)]
+// (the inverse of kreal_unpack).
+__global__ void kreal_coords_kernel(const c128* Q, int64_t ldq, int64_t m, int k, c128* D, int64_t ldd) {
+  const int64_t total = m * k;
+  const double r2 = 1.41421356237309504880;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / m, i = t % m;
+    const c128 a = Q[c * ldq + i];
+    D[c * ldd + i] = c128{r2 * a.re, 0.0};
+    D[c * ldd + m + i] = c128{r2 * a.im, 0.0};
   }
 }
 
@@ -351,10 +313,9 @@ Err kreal_build(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, i
   return ok();
 }
 
-Err kreal_pairs(const c128* X, int64_t ldx, int L, int kw, int64_t m, c128* D, int64_t ldd, hipStream_t s) {
-  const int64_t total = m * (L + kw);
-  if (total == 0) return ok();
-  hipLaunchKernelGGL(kreal_pairs_kernel, dim3(grid_for(total)), dim3(256), 0, s, X, ldx, L, kw, m, D, ldd);
+Err kreal_coords(const c128* Q, int64_t ldq, int64_t m, int k, c128* D, int64_t ldd, hipStream_t s) {
+  if (m * k == 0) return ok();
+  hipLaunchKernelGGL(kreal_coords_kernel, dim3(grid_for(m * k)), dim3(256), 0, s, Q, ldq, m, k, D, ldd);
   CHASE_LAUNCH_CHECK();
   return ok();
 }
@@ -390,15 +351,6 @@ Err combine_correction(c128* W, int64_t ldw, const c64* D, int64_t ldd, const do
                        hipStream_t s) {
   if (k == 0) return ok();
   hipLaunchKernelGGL(combine_kernel, dim3(grid_for(n * k)), dim3(256), 0, s, W, ldw, D, ldd, dpw, ce, n, k);
-  CHASE_LAUNCH_CHECK();
-  return ok();
-}
-
-Err build_search_block(const c128* Y, int64_t ldy, int L, const c128* W, int64_t ldw, int kw, c128* X, int64_t ldx,
-                       int64_t m, hipStream_t s) {
-  const int64_t total = 2 * m * (2 * L + 2 * kw);
-  if (total == 0) return ok();
-  hipLaunchKernelGGL(build_x_kernel, dim3(grid_for(total)), dim3(256), 0, s, Y, ldy, L, W, ldw, kw, X, ldx, m);
   CHASE_LAUNCH_CHECK();
   return ok();
 }
