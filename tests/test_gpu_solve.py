@@ -102,6 +102,20 @@ def test_solve_b_zero_is_tda():
     assert np.max(np.abs(to_host(V)[200:])) < 1e-8
 
 
+@pytest.mark.parametrize("m,nev,nex,prec", [(301, 1, 3, FP64), (257, 5, 3, MIXED), (130, 12, 4, FP64)])
+def test_solve_small_and_odd_shapes(m, nev, nex, prec):
+    # odd m (no direct-to-LDS tiles), a single wanted pair, m not a multiple
+    # of any tile: the solver still reaches the dense eigenvalues (the CPU
+    # oracle converges on the same draws in 32, 33 and 8 iterations)
+    p = make_problem(m, lambda rng, mm: rng.uniform(1.0, 5.0, mm), 0.3, nev, nex, 12, 1e-10, seed=7)
+    print_case("solve_shape", m=m, nev=nev, nex=nex, prec=prec)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    tol = 1e-10 if prec == FP64 else 1e-9
+    p.tol = tol
+    _, (ev, V, res, info) = _solve(p, precision=prec, max_iter=40)
+    _check_solution(p, ev, V, res, lam, tol)
+
+
 def test_solve_no_convergence_partial(cfg0):
     p, lam = cfg0
     A, B = dev_blocks(p)
