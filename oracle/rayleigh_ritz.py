@@ -47,7 +47,10 @@ def oblique_rr(A, B, Q, return_all: bool = False):
     G = 0.5 * (G + G.conj().T)                          # = L^{-1} N L^{-H}  (lines 6-7)
     theta, Y = np.linalg.eigh(G)                         # line 8
     Z = scipy.linalg.solve_triangular(L.conj().T, Y, lower=False)      # line 9: L^{-H} Y
-    pos = theta > 0
+    # Theta ~ 0 belongs to a direction where Q^H S Q is singular (Section 6):
+    # only eigenvalues resolved away from zero, theta > 1e3 u ||G||_F, count
+    # as positive (fewer than k/2 of them sends the solver to the back-up).
+    pos = theta > 1e3 * np.finfo(float).eps / 2 * np.linalg.norm(G)
     lam_pos = 1.0 / theta[pos]
     Z_pos = Z[:, pos]
     order = np.argsort(lam_pos)
@@ -55,4 +58,61 @@ def oblique_rr(A, B, Q, return_all: bool = False):
     Z_pos = Z_pos[:, order]
     if return_all:
         return lam_pos, Z_pos, T, np.sort(1.0 / theta)
+    return lam_pos, Z_pos, T
+
+
+# Threshold below which a diagonal entry of Q^H S Q is replaced in the
+# back-up dual basis (Section 6 allows replacing zero entries; any nonzero
+# value keeps Q_L^H Q = I).  Reading: |d_i| < 1e-8 is taken as zero and
+# replaced by 1.
+BACKUP_DIAG_MIN = 1e-8
+
+
+def backup_quotient(Q, T):
+    """Non-hermitian back-up Rayleigh quotient of Section 6.
+
+    With ``N = Q^H S Q`` and ``D = diag(N)`` (entries below BACKUP_DIAG_MIN in
+    modulus replaced by 1), the dual basis is
+    ``Q_L = [S Q - Q (N - D)] D^{-1}`` and the quotient
+    ``G = D^{-1} [Q^H S H Q - (N - D) Q^H H Q]`` (``T = H Q`` given).
+    Returns ``(G, d)`` with d the diagonal used.
+    """
+    Q = np.asarray(Q, dtype=np.complex128)
+    T = np.asarray(T, dtype=np.complex128)
+    N = Q.conj().T @ apply_s(Q)                          # Q^H S Q
+    d = np.real(np.diag(N)).copy()
+    d[np.abs(d) < BACKUP_DIAG_MIN] = 1.0
+    E = N - np.diag(d)                                   # N - D
+    P = Q.conj().T @ apply_s(T)                          # Q^H S H Q
+    C = Q.conj().T @ T                                   # Q^H H Q
+    G = (P - E @ C) / d[:, None]                         # D^{-1} [P - (N - D) C]
+    return G, d
+
+
+def oblique_rr_backup(A, B, Q, return_all: bool = False):
+    """Rayleigh-Ritz with the back-up quotient of Section 6 (for a Q^H S Q
+    that is singular): general eigenproblem ``G y = lambda y``, real parts
+    kept.  The back-up dual basis need not be K-symmetric, so the +/- split
+    of Thm 4.5 can fail (a replaced zero of diag(Q^H S Q) gives both values
+    of an S-neutral pair one sign).  Reading: the positive half is the k/2
+    eigenvalues with the smallest positive real parts, completed by the
+    largest non-positive ones if fewer than k/2 are positive; ascending by
+    real part.
+
+    Returns ``(lam_pos, Z_pos, T)`` as ``oblique_rr``: real parts, the
+    matching eigenvectors of G (Ritz vectors are ``Q Z_pos``) and ``T = H Q``;
+    with ``return_all`` also the complex eigenvalues and all eigenvectors.
+    """
+    Q = np.asarray(Q, dtype=np.complex128)
+    k = Q.shape[1]
+    T = apply_h(A, B, Q)
+    G, _ = backup_quotient(Q, T)
+    w, Y = np.linalg.eig(G)
+    order = np.argsort(w.real, kind="stable")
+    start = min(int(np.sum(w.real <= 0)), k - k // 2)
+    sel = order[start:start + k // 2]
+    lam_pos = w[sel].real
+    Z_pos = Y[:, sel]
+    if return_all:
+        return lam_pos, Z_pos, T, w, Y
     return lam_pos, Z_pos, T

@@ -28,7 +28,7 @@ from .chebyshev import chebyshev_filter, filter_params
 from .hamiltonian import apply_k_conj, apply_s
 from .lanczos import spectral_estimates
 from .qr import kreal_qr, orthonormalise
-from .rayleigh_ritz import oblique_rr
+from .rayleigh_ritz import oblique_rr, oblique_rr_backup
 from .residuals import back_transform, residual_norms
 
 
@@ -56,9 +56,13 @@ def next_degrees(lam, resid, tol, mu1, mu_nevex, mu_n, deg_min, deg_max):
 
 
 def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3,
-          lanczos_steps=26, deg_min=None, deg_max=None, opt_deg=False):
+          lanczos_steps=26, deg_min=None, deg_max=None, opt_deg=False, rr_backup=0):
     """Return ``(lam, V, info)``: the nev smallest positive eigenvalues found
-    (ascending), unit right eigenvectors (n x nev) and an info dict."""
+    (ascending), unit right eigenvectors (n x nev) and an info dict.
+
+    rr_backup: 0 uses the back-up quotient of Section 6 only when Q^H S Q is
+    singular (fewer than k/2 positive eigenvalues of Alg. 2's quotient);
+    1 uses it in every iteration."""
     A = np.asarray(A, dtype=np.complex128)
     B = np.asarray(B, dtype=np.complex128)
     m = A.shape[0]
@@ -73,7 +77,7 @@ def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3
     lam_locked = []
     degs = np.full(nevex, deg, dtype=int)
     info = dict(mu1=mu1, mu_nevex0=mu_nevex, mu_n=mu_n, iterations=0,
-                locked_history=[], resid_history=[], shifted_qr=[], converged=False)
+                locked_history=[], resid_history=[], shifted_qr=[], backup_rr=[], converged=False)
     for it in range(max_iter):
         locked = Yp.shape[1]
         W = chebyshev_filter(A, B, W, degs, mu1, mu_nevex, mu_n)
@@ -84,7 +88,13 @@ def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3
             # (the locked pairs' part first), completed by K-real directions
             Q = kreal_qr(np.concatenate([apply_s(Yp), W], axis=1), lead=locked)
         Q = Q[:, 2 * locked:]
-        lam, Z, _ = oblique_rr(A, B, Q)
+        k = Q.shape[1]
+        used_backup = bool(rr_backup)
+        if not used_backup:
+            lam, Z, _ = oblique_rr(A, B, Q)
+            used_backup = len(lam) != k // 2
+        if used_backup:
+            lam, Z, _ = oblique_rr_backup(A, B, Q)
         V = back_transform(Q, Z)
         r = residual_norms(A, B, V, lam)
         nlock = 0
@@ -98,6 +108,7 @@ def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3
         info["locked_history"].append(Yp.shape[1])
         info["resid_history"].append(r.copy())
         info["shifted_qr"].append(shifted)
+        info["backup_rr"].append(used_backup)
         if Yp.shape[1] >= nev:
             info["converged"] = True
             break

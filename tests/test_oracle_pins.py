@@ -316,6 +316,101 @@ def test_rr_ritz_values_in_field_of_values_interval():
     assert lmin <= 1.0 + 1e-12
 
 
+def _backup_dual_basis(Q):
+    # Q_L = [S Q - Q (Q^H S Q - D)] D^{-1}, D = diag(Q^H S Q) (Section 6),
+    # written from the dual-basis equation, not from the quotient
+    N = Q.conj().T @ ham.apply_s(Q)
+    d = np.real(np.diag(N)).copy()
+    d[np.abs(d) < rayleigh_ritz.BACKUP_DIAG_MIN] = 1.0
+    return (ham.apply_s(Q) - Q @ (N - np.diag(d))) / d[None, :]
+
+
+def test_backup_quotient_is_dual_projection():
+    # the quotient equation of Section 6 equals Q_L^H H Q for the dual basis
+    # equation, and Q_L^H Q = I
+    p = small_problem(30)
+    Q = _search_basis(p, 6, seed=7)
+    H = ham.assemble_h(p.A, p.B)
+    G, _ = rayleigh_ritz.backup_quotient(Q, H @ Q)
+    QL = _backup_dual_basis(Q)
+    assert np.abs(QL.conj().T @ Q - np.eye(12)).max() < 1e-12
+    assert np.abs(G - QL.conj().T @ H @ Q).max() < 1e-12 * np.abs(G).max()
+
+
+def test_backup_petrov_galerkin_residuals():
+    # every eigenpair of the back-up quotient leaves a residual orthogonal to
+    # range(Q_L) (the oblique projection condition), complex values included
+    p = small_problem(30)
+    Q = _search_basis(p, 5, seed=8)
+    _, _, T, w, Y = rayleigh_ritz.oblique_rr_backup(p.A, p.B, Q, return_all=True)
+    QL = _backup_dual_basis(Q)
+    R = T @ Y - (Q @ Y) * w[None, :]
+    assert np.abs(QL.conj().T @ R).max() < 1e-11 * np.abs(T).max()
+    # a filtered basis: real parts split +/- and the positive half lies
+    # near the Alg. 2 values
+    lam_rr, _, _ = rayleigh_ritz.oblique_rr(p.A, p.B, Q)
+    lam_bk, _, _ = rayleigh_ritz.oblique_rr_backup(p.A, p.B, Q)
+    assert np.all(lam_bk > 0) and np.sum(w.real < 0) == 5
+    assert np.allclose(lam_bk, lam_rr, rtol=1e-2)
+
+
+def test_backup_exact_invariant_subspace():
+    p = small_problem(24)
+    lam, Vp = dense.dense_ph_eig(p.A, p.B)
+    X = np.concatenate([Vp[:, :5], ham.apply_k_conj(Vp[:, :5])], axis=1)
+    Q, _, _ = qr.cholqr2(X)
+    lr, Z, _, w, _ = rayleigh_ritz.oblique_rr_backup(p.A, p.B, Q, return_all=True)
+    assert np.allclose(lr, lam[:5], rtol=1e-11)
+    assert np.max(np.abs(w.imag)) < 1e-11 * np.max(np.abs(w))
+    V = residuals.back_transform(Q, Z)
+    assert np.max(residuals.residual_norms(p.A, p.B, V, lr)) < 1e-11
+
+
+def _decoupled_problem(m, seed=0):
+    # A, B block diagonal with a 2 x 2 leading block: coordinates 0, 1 (and
+    # m, m + 1) do not couple to the rest
+    rng = np.random.default_rng(seed)
+    X = complex_normal(rng, (m, m))
+    A = X @ X.conj().T / m + 2.0 * np.eye(m)
+    C = complex_normal(rng, (m, m))
+    B = 0.15 * (C + C.T)
+    A[:2, 2:] = 0; A[2:, :2] = 0
+    B[:2, 2:] = 0; B[2:, :2] = 0
+    return A, B
+
+
+def test_backup_recovers_pairs_when_qsq_singular():
+    # range(Q) = an exact +/- eigenpair of the trailing block plus the two
+    # S-neutral, mutually S-orthogonal vectors [e0; e1], [e1; e0]: Q^H S Q has
+    # a 2 x 2 zero block, Alg. 2 resolves one positive value only, the
+    # back-up quotient (zero diagonal entries replaced) gives both, and the
+    # exact pair among them
+    m = 10
+    A, B = _decoupled_problem(m)
+    H = ham.assemble_h(A, B)
+    idx = np.r_[2:m, m + 2:2 * m]
+    w, V = np.linalg.eig(H[np.ix_(idx, idx)])
+    j = int(np.argmin(np.where(w.real > 0, w.real, np.inf)))
+    v = np.zeros(2 * m, complex)
+    v[idx] = V[:, j]
+    v /= np.linalg.norm(v)
+    e = np.zeros((2 * m, 2), complex)
+    e[0, 0] = e[m + 1, 0] = 1 / np.sqrt(2)
+    e[1, 1] = e[m, 1] = 1 / np.sqrt(2)
+    Q = np.concatenate([v[:, None], ham.apply_k_conj(v[:, None]), e], axis=1)
+    Q, _ = np.linalg.qr(Q)
+    N = Q.conj().T @ ham.apply_s(Q)
+    assert np.linalg.matrix_rank(N, tol=1e-10) == 2
+    lam_rr, _, _ = rayleigh_ritz.oblique_rr(A, B, Q)
+    assert len(lam_rr) == 1
+    lam_bk, Z, _ = rayleigh_ritz.oblique_rr_backup(A, B, Q)
+    assert len(lam_bk) == 2
+    i = int(np.argmin(np.abs(lam_bk - w[j].real)))
+    assert abs(lam_bk[i] - w[j].real) < 1e-12 * abs(w[j])
+    Vb = residuals.back_transform(Q, Z[:, i:i + 1])
+    assert residuals.residual_norms(A, B, Vb, lam_bk[i:i + 1])[0] < 1e-12
+
+
 # ------------------------------------------------------------- solver
 def test_solver_matches_dense():
     p = small_problem(60, nev=6, nex=4, deg=10, tol=1e-10)
@@ -358,6 +453,18 @@ def test_solver_per_vector_degrees():
                                 p.lanczos_raw, deg_min=4, deg_max=16, opt_deg=True)
     ref, _ = dense.smallest_positive(p.A, p.B, p.nev)
     assert np.allclose(lam, ref, rtol=1e-10)
+
+
+def test_solver_backup_rr_every_iteration():
+    # the back-up quotient of Section 6 in every iteration still converges to
+    # the dense eigenvalues (no quadratic convergence, so more iterations)
+    p = small_problem(40, nev=4, nex=4)
+    rng = np.random.default_rng(0)
+    lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, 12, 1e-9, complex_normal(rng, (80, 8)),
+                                complex_normal(rng, (80, 4)), max_iter=40, rr_backup=1)
+    assert info["converged"] and all(info["backup_rr"])
+    exact, _ = dense.smallest_positive(p.A, p.B, p.nev)
+    assert np.allclose(lam, exact, rtol=1e-9)
 
 
 def test_solver_max_iter_partial():
