@@ -78,6 +78,9 @@ typedef struct {
   int32_t lanczos_steps;/* per run, even (Section 4.1; 26)                                  */
   int32_t lanczos_vecs; /* independent Lanczos runs (4)                                     */
   int32_t a_conj;       /* 1: the buffer dA holds conj(A) column-major (= A row-major)      */
+  int32_t rr_backup;    /* 0: the non-hermitian back-up quotient of Section 6 only when     */
+                        /* Alg. 2 resolves fewer than k/2 positive Ritz values (Q^H S Q     */
+                        /* singular); 1: the back-up quotient in every iteration            */
 } chase_ph_params;
 
 typedef struct {
@@ -93,6 +96,7 @@ typedef struct {
   double* resid_history;   /* optional host array (caller-owned) of max_iter * nevex        */
   int32_t resid_history_len; /* capacity of resid_history in doubles (0 if NULL)           */
   int32_t householder_qr_used; /* times the Householder QR fallback was taken              */
+  int32_t backup_rr_used;  /* iterations whose Rayleigh-Ritz used the back-up quotient      */
 } chase_ph_info;
 
 /* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos
@@ -176,6 +180,23 @@ chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void
 chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq,
                                     double* hRitz, void* dZpos, int64_t ldz, void* dT,
                                     int64_t ldt);
+
+/* Rayleigh-Ritz with the non-hermitian back-up quotient of Section 6, for
+ * a block where Alg. 2 fails because Q^H S Q is singular; same arguments
+ * and outputs as chase_ph_oblique_rr.  With N = Q^H S Q and D = diag(N)
+ * (entries below 1e-8 in modulus replaced by 1, which keeps the dual basis
+ * Q_L = [S Q - Q (N - D)] D^{-1} bi-orthogonal to Q):
+ *   T = H Q;  G = D^{-1} [Q^H S T - (N - D) Q^H T];  G Y = Y W (general
+ *   eigenproblem: Hessenberg reduction, shifted QR, back-substitution).
+ * The Ritz values are complex and their real parts are kept: hRitz gets the
+ * k/2 smallest positive real parts ascending, followed, if fewer than k/2
+ * are positive (the back-up dual basis need not keep the +/- symmetry of
+ * Thm 4.5), by the largest non-positive ones descending; dZpos the
+ * matching columns of Y.  The solver never locks a non-positive value.  CHASE_PH_ERR_SINGULAR_QSQ if the QR iteration does not
+ * converge (30 iterations per eigenvalue, 10 k in total). */
+chase_ph_status chase_ph_oblique_rr_backup(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq,
+                                           double* hRitz, void* dZpos, int64_t ldz, void* dT,
+                                           int64_t ldt);
 
 /* Half back-transform and residuals (Section 4.5): for the first kk
  * columns of dZpos, V = Q Z (normalised to unit 2-norm, written to dV,

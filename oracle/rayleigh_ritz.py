@@ -94,10 +94,11 @@ def oblique_rr_backup(A, B, Q, return_all: bool = False):
     that is singular): general eigenproblem ``G y = lambda y``, real parts
     kept.  The back-up dual basis need not be K-symmetric, so the +/- split
     of Thm 4.5 can fail (a replaced zero of diag(Q^H S Q) gives both values
-    of an S-neutral pair one sign).  Reading: the positive half is the k/2
-    eigenvalues with the smallest positive real parts, completed by the
-    largest non-positive ones if fewer than k/2 are positive; ascending by
-    real part.
+    of an S-neutral pair one sign, and poorly resolved directions give
+    unpaired values).  Reading: the positive half is the k/2 eigenvalues with
+    the smallest positive real parts, ascending, followed, if fewer than k/2
+    are positive, by the largest non-positive ones, descending (the solver
+    never locks those).
 
     Returns ``(lam_pos, Z_pos, T)`` as ``oblique_rr``: real parts, the
     matching eigenvectors of G (Ritz vectors are ``Q Z_pos``) and ``T = H Q``;
@@ -109,8 +110,9 @@ def oblique_rr_backup(A, B, Q, return_all: bool = False):
     G, _ = backup_quotient(Q, T)
     w, Y = np.linalg.eig(G)
     order = np.argsort(w.real, kind="stable")
-    start = min(int(np.sum(w.real <= 0)), k - k // 2)
-    sel = order[start:start + k // 2]
+    p = int(np.sum(w.real <= 0))
+    npos = min(k // 2, k - p)
+    sel = np.concatenate([order[p:p + npos], order[p - (k // 2 - npos):p][::-1]])
     lam_pos = w[sel].real
     Z_pos = Y[:, sel]
     if return_all:

@@ -10,10 +10,11 @@ Steps per outer iteration, in Alg. 3's order:
  7. lock converged pairs; mu_nevex <- largest positive Ritz    (Sections 2, 4.1)
 
 Readings (the paper is silent): a contiguous prefix of the wanted pairs
-with residual <= tol is locked each iteration; mu_1 and mu_n stay at their
-Lanczos values; mu_nevex follows the largest non-converged positive Ritz
-value but never increases (Section 4.1: the update gradually narrows the
-filtering interval), i.e. mu_nevex <- min(mu_nevex, lambda~_last); per-vector degrees follow the Chebyshev convergence-factor
+with residual <= tol and a positive Ritz value is locked each iteration;
+mu_1 and mu_n stay at their Lanczos values; mu_nevex follows the largest
+non-converged positive Ritz value but never increases (Section 4.1: the
+update gradually narrows the filtering interval), i.e.
+mu_nevex <- min(mu_nevex, max lambda~); per-vector degrees follow the Chebyshev convergence-factor
 bound ``d_j = ceil(ln(r_j / tol) / ln rho_j)`` clamped to [deg_min, deg_max]
 with ``rho_j = |t_j| + sqrt(t_j^2 - 1)``, ``t_j = (lambda_j^2 - c) / e``
 (Section 6.1 defers the rule to Winkelmann et al. 2019).
@@ -98,12 +99,13 @@ def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3
         V = back_transform(Q, Z)
         r = residual_norms(A, B, V, lam)
         nlock = 0
-        while nlock < nev - locked and r[nlock] <= tol:
+        while nlock < nev - locked and r[nlock] <= tol and lam[nlock] > 0:
             nlock += 1
         Yp = np.concatenate([Yp, V[:, :nlock]], axis=1)
         lam_locked.extend(lam[:nlock].tolist())
         W = V[:, nlock:]
-        mu_nevex = min(mu_nevex, float(lam[-1]))
+        if np.max(lam) > 0:
+            mu_nevex = min(mu_nevex, float(np.max(lam)))
         info["iterations"] = it + 1
         info["locked_history"].append(Yp.shape[1])
         info["resid_history"].append(r.copy())

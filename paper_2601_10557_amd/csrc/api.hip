@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "dense.h"
+#include "geev.h"
 #include "vec.h"
 
 using namespace chase;
@@ -63,6 +64,8 @@ struct chase_ph_s {
   c128* Ys = nullptr;
   c128* Zp = nullptr;  // kmax x kmax/2
   HouseholderWs hhw;   // Householder QR (last-resort orthonormalisation); Q in Xt
+  GeevWs gw;           // general eigenproblem of the back-up Rayleigh quotient
+  c128* Wev = nullptr; // kmax complex Ritz values of the back-up quotient
   // solver state
   c128* Ylock = nullptr;  // n x nev
   c128* Wk = nullptr;     // n x nevex
@@ -480,7 +483,38 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
   return ok();
 }
 
+// Back-up Rayleigh quotient of Section 6 on Q and T = H Q; see
+// chase_ph_oblique_rr_backup.  Buffers: P and then G in G, Q^H T in Tk,
+// N and then N - D in Nb, D in dres, Schur vectors in Ev, eigenvectors of T
+// in Li (transposed work copy in L3), eigenvectors of G in Ys.
+Err rr_backup(chase_ph_t h, int k, const c128* Q, int64_t ldq, const c128* T, int64_t ldt, double* ritz, c128* Zpos,
+              int64_t ldz) {
+  const int kp = pad64(k);
+  const int64_t m = h->m, n = h->n;
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m));   // Q^H S H Q
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->Tk, kp));     // Q^H H Q
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, Q, ldq, {0, 0}, h->Nb, kp, m));  // N = Q^H S Q
+  CHASE_TRY(backup_diag(h->Nb, kp, k, BACKUP_DIAG_MIN, h->dres, h->st));            // D; Nb <- N - D
+  CHASE_TRY(gemm(h, 0, 0, k, k, k, {-1, 0}, h->Nb, kp, h->Tk, kp, {1, 0}, h->G, kp, -1, false));
+  CHASE_TRY(scale_rows_inv(h->G, kp, k, h->dres, h->st));                           // G = D^{-1} [...]
+  int qs = 0;
+  CHASE_TRY(nonsym_eig(h->G, h->Ev, kp, k, h->Wev, h->L3, h->Li, h->gw, h->st, &qs));
+  if (qs != 0)
+    return fail(CHASE_PH_ERR_SINGULAR_QSQ, "back-up Rayleigh quotient: QR iteration did not converge for k = " +
+                                               std::to_string(k));
+  CHASE_TRY(gemm(h, 0, 0, k, k, k, {1, 0}, h->Ev, kp, h->Li, kp, {0, 0}, h->Ys, kp, -1, false));  // Z Y
+  CHASE_TRY(select_by_real_part(h->Wev, k, h->Ys, kp, h->dperm, h->dlam, Zpos, ldz, h->st));
+  if (ritz) {
+    CHASE_HIP(hipMemcpyAsync(ritz, h->dlam, sizeof(double) * (k / 2), hipMemcpyDeviceToHost, h->st));
+    CHASE_HIP(hipStreamSynchronize(h->st));
+  }
+  return ok();
+}
+
 // Alg. 2 (inverse Rayleigh quotient); see chase_ph_oblique_rr.
+// backup: -1 never uses the back-up quotient of Section 6 (a singular
+// Q^H S Q is reported), 0 uses it when Alg. 2 resolves fewer than k/2
+// positive values, 1 always (*used_backup reports which ran).
 // kreal_q: every column of Q is K-real, so T = H Q takes half the products.
 // In a K-real basis the quotient G below is i times a real antisymmetric
 // matrix, whose zero diagonal slows the Jacobi sweeps down; the columns 2j
@@ -488,7 +522,7 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
 // recombined as (q_2j +- i q_2j+1) / sqrt(2) (unitary: the Ritz pairs do not
 // change), which gives G a nonzero diagonal.  Q is modified in place then.
 Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128* Zpos, int64_t ldz, c128* T,
-            int64_t ldt, bool kreal_q = false) {
+            int64_t ldt, bool kreal_q = false, int backup = -1, bool* used_backup = nullptr) {
   const int kp = pad64(k);
   const int64_t m = h->m, n = h->n;
   CHASE_TRY(apply64(h, k, Q, ldq, T, ldt, 1, nullptr, 0, 0, nullptr, 0, 0, kreal_q ? 1 : 0));  // T = H Q
@@ -496,6 +530,8 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
     CHASE_TRY(pair_mix(const_cast<c128*>(Q), ldq, n, k / 2, h->st));
     CHASE_TRY(pair_mix(T, ldt, n, k / 2, h->st));  // = H (Q after the mix)
   }
+  if (used_backup) *used_backup = backup == 1;
+  if (backup == 1) return rr_backup(h, k, Q, ldq, T, ldt, ritz, Zpos, ldz);
   CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
   CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m, true,
                  GEMM_LOWER_ONLY));  // M = Q^H S T (Hermitian; the Cholesky reads the lower triangle)
@@ -513,6 +549,10 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
   CHASE_TRY(jacobi_eigh(h->G, h->Ev, kp, h->dws, h->st, 40, &sweeps));
   int npos = 0, nneg = 0;
   CHASE_TRY(select_positive(h->G, h->Ev, k, kp, h->Ys, h->dlam, h->dws, h->st, &npos, &nneg));
+  if ((npos != k / 2 || nneg != k / 2) && backup == 0) {
+    if (used_backup) *used_backup = true;
+    return rr_backup(h, k, Q, ldq, T, ldt, ritz, Zpos, ldz);
+  }
   if (npos != k / 2 || nneg != k / 2)
     return fail(CHASE_PH_ERR_SINGULAR_QSQ, "Q^H S Q numerically singular: " + std::to_string(npos) + " positive / " +
                                                std::to_string(nneg) + " negative resolved Ritz values for k = " +
@@ -853,7 +893,9 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     const c128* Q = h->Xs + (int64_t)2 * locked * n;
     const int kq = 2 * kw;
     CHASE_TRY(tm.start());
-    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n, true));
+    bool used_backup = false;
+    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n, true, p.rr_backup ? 1 : 0, &used_backup));
+    inf.backup_rr_used += used_backup;
     CHASE_TRY(tm.stop(&inf.t_rr));
     // half back-transform and residuals (Section 4.5)
     CHASE_TRY(tm.start());
@@ -866,8 +908,10 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       hist_pos += kw;
     }
     // locking: contiguous prefix of the wanted pairs with residual <= tol
+    // (and a positive Ritz value: the back-up quotient may complete the
+    // positive half with non-positive values, which come last)
     int nlock = 0;
-    while (nlock < nev - locked && res[nlock] <= p.tol) ++nlock;
+    while (nlock < nev - locked && res[nlock] <= p.tol && ritz[nlock] > 0) ++nlock;
     if (nlock > 0)
       CHASE_HIP(hipMemcpy2DAsync(h->Ylock + (int64_t)locked * n, n * sizeof(c128), h->Vt, n * sizeof(c128),
                                  n * sizeof(c128), nlock, hipMemcpyDeviceToDevice, h->st));
@@ -882,7 +926,8 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     }
     locked += nlock;
     // largest non-converged positive Ritz value; the interval only narrows (Section 4.1)
-    mu_nevex = std::min(mu_nevex, ritz[kw - 1]);
+    const double lmax = *std::max_element(ritz.begin(), ritz.begin() + kw);
+    if (lmax > 0) mu_nevex = std::min(mu_nevex, lmax);
     inf.iterations = it + 1;
     if (locked >= nev) {
       *converged = true;
@@ -1033,6 +1078,10 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, &h->hhw.dsign, (size_t)h->kmax));
   h->hhw.Q = h->Xt;
   h->hhw.kmax = h->kmax;
+  CHASE_TRY(dalloc(h, &h->gw.v, (size_t)h->kmax));
+  CHASE_TRY(dalloc(h, &h->gw.tau, 1));
+  CHASE_TRY(dalloc(h, &h->gw.status, 1));
+  CHASE_TRY(dalloc(h, &h->Wev, (size_t)h->kmax));
   CHASE_TRY(dalloc(h, &h->G, kp2));
   CHASE_TRY(dalloc(h, &h->L1, kp2));
   CHASE_TRY(dalloc(h, &h->L2, kp2));
@@ -1103,7 +1152,7 @@ chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const 
   if (!p || !dA || !dB || p->m <= 0 || ld < p->m || p->nev <= 0 || p->nex < 0 || p->nev + p->nex > p->m ||
       p->deg < 1 || p->max_iter < 1 || !(p->tol > 0) || p->lanczos_steps < 2 || p->lanczos_steps % 2 != 0 ||
       p->lanczos_vecs < 1 || (p->precision != CHASE_PH_FP64 && p->precision != CHASE_PH_MIXED) ||
-      (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)))
+      (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)) || (p->rr_backup != 0 && p->rr_backup != 1))
     return CHASE_PH_ERR_ARG;
   chase_ph_t h = new (std::nothrow) chase_ph_s;
   if (!h) return CHASE_PH_ERR_ALLOC;
@@ -1215,6 +1264,14 @@ chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int
   if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
     return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr: bad arguments"));
   return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt));
+}
+
+chase_ph_status chase_ph_oblique_rr_backup(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq, double* hRitz,
+                                           void* dZpos, int64_t ldz, void* dT, int64_t ldt) {
+  CHECK_HANDLE(h);
+  if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
+    return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr_backup: bad arguments"));
+  return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt, false, 1));
 }
 
 chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const void* dQ, int64_t ldq, const void* dT,

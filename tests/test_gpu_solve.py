@@ -77,6 +77,15 @@ def test_solve_per_vector_degrees(cfg0):
     _check_solution(p, ev, V, res, lam, 1e-10)
 
 
+def test_solve_backup_rr_every_iteration(cfg0):
+    # the non-hermitian back-up quotient of Section 6 in every iteration
+    p, lam = cfg0
+    print_case("solve_backup_rr", cfg=0, m=p.m)
+    _, (ev, V, res, info) = _solve(p, precision=FP64, rr_backup=True, max_iter=40)
+    _check_solution(p, ev, V, res, lam, 1e-10)
+    assert info.backup_rr_used == info.iterations
+
+
 def test_solve_zero_start_column_takes_householder_qr(cfg0):
     # a zero column in the start block stays zero through the filter, so the
     # first search block is rank deficient: QR falls back to Householder and

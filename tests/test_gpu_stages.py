@@ -19,6 +19,7 @@ from paper_2601_10557_amd import FP32, FP64, ChasePHError, PHSolver, empty_cm
 from paper_2601_10557_amd import _lib
 from synth import make_problem, complex_normal
 from gpu_helpers import align_columns, dev_blocks, print_case, to_dev, to_host
+from cases import decoupled_singular_case
 
 
 def problem(m=300, seed=0, coupling=0.4, nev=12, nex=8):
@@ -327,6 +328,70 @@ def test_rr_exact_invariant_subspace(prob, solver):
     Q, _, _ = oqr.cholqr2(X)
     ritz, Z, T = solver.oblique_rr(to_dev(Q))
     assert np.allclose(ritz, lam[:6], rtol=1e-12)
+
+
+def _unit_ritz(Q, Z):
+    V = Q @ Z
+    return V / np.linalg.norm(V, axis=0)[None, :]
+
+
+@pytest.mark.parametrize("kh", [1, 2, 20, 40])
+def test_oblique_rr_backup_matches_oracle(prob, solver, solver80, kh):
+    # Section 6 back-up quotient on a filtered search block; k = 2 .. 80
+    # (Hessenberg reduction over ragged 64-row groups, QR iteration, back-
+    # substitution over two 64-thread groups at k = 80)
+    s = solver if kh <= 20 else solver80
+    print_case("oblique_rr_backup", m=prob.m, k=2 * kh)
+    X = _search_block(prob, kh, seed=6)
+    Q, _, _ = oqr.cholqr2(X)
+    lam_ref, Z_ref, T_ref = rayleigh_ritz.oblique_rr_backup(prob.A, prob.B, Q)
+    Qd = to_dev(Q)
+    ritz, Z, T = s.oblique_rr_backup(Qd)
+    assert np.allclose(ritz, lam_ref, rtol=1e-10, atol=0)
+    assert np.max(np.abs(to_host(T) - T_ref)) < 1e-12 * np.max(np.abs(T_ref))
+    Vref = _unit_ritz(Q, Z_ref)
+    V = align_columns(_unit_ritz(Q, to_host(Z)), Vref)
+    assert np.max(np.abs(V - Vref)) < 1e-8
+    Vr, res = s.residuals(Qd, T, Z, ritz)
+    rref = ores.residual_norms(prob.A, prob.B, ores.back_transform(Q, Z_ref), lam_ref)
+    assert np.allclose(res, rref, rtol=1e-6, atol=1e-12)
+
+
+def test_oblique_rr_backup_exact_invariant_subspace(prob, solver):
+    lam, Vp = dense.dense_ph_eig(prob.A, prob.B)
+    X = np.concatenate([Vp[:, :6], ham.apply_k_conj(Vp[:, :6])], axis=1)
+    Q, _, _ = oqr.cholqr2(X)
+    ritz, Z, T = solver.oblique_rr_backup(to_dev(Q))
+    assert np.allclose(ritz, lam[:6], rtol=1e-11)
+
+
+def test_oblique_rr_backup_recovers_exact_pair_when_qsq_singular():
+    # Q^H S Q with a 2 x 2 zero block: Alg. 2 reports the singularity, the
+    # back-up quotient returns the exact pair in range(Q)
+    A, B, Q, lam_exact = decoupled_singular_case()
+    print_case("oblique_rr_backup_singular", m=A.shape[0], k=4)
+    p = make_problem(A.shape[0], lambda rng, mm: rng.uniform(1.0, 2.0, mm), 0.1, 1, 1, 4, 1e-8)
+    p.A, p.B = A, B
+    Ad, Bd = dev_blocks(p)
+    s = PHSolver(Ad, Bd, 1, 1)
+    with pytest.raises(ChasePHError) as e:
+        s.oblique_rr(to_dev(Q))
+    assert e.value.status == _lib.ERR_SINGULAR_QSQ
+    lam_ref, Z_ref, _ = rayleigh_ritz.oblique_rr_backup(A, B, Q)
+    ritz, Z, T = s.oblique_rr_backup(to_dev(Q))
+    assert np.allclose(ritz, lam_ref, rtol=1e-12)
+    assert np.min(np.abs(ritz - lam_exact)) < 1e-12 * lam_exact
+
+
+def test_oblique_rr_backup_on_s_neutral_basis(prob, solver):
+    # Q^H S Q = 0: every diagonal entry is replaced by 1
+    m, k = prob.m, 4
+    Q = np.zeros((prob.n, k), dtype=np.complex128)
+    for j in range(k):
+        Q[j, j] = Q[m + j, j] = 1 / np.sqrt(2)
+    lam_ref, _, _ = rayleigh_ritz.oblique_rr_backup(prob.A, prob.B, Q)
+    ritz, _, _ = solver.oblique_rr_backup(to_dev(Q))
+    assert np.allclose(ritz, lam_ref, rtol=1e-12)
 
 
 def test_backward_matches_oracle(prob, solver):

@@ -12,6 +12,7 @@ import scipy.linalg
 
 from oracle import adjoint, chebyshev, dense, hamiltonian as ham, lanczos, qr, rayleigh_ritz, residuals, solver
 from synth import make_problem, config_problem, complex_normal
+from cases import decoupled_singular_case
 
 
 def small_problem(m, seed=0, coupling=0.4, lo=1.0, hi=5.0, nev=4, nex=3, deg=10, tol=1e-10):
@@ -366,47 +367,21 @@ def test_backup_exact_invariant_subspace():
     assert np.max(residuals.residual_norms(p.A, p.B, V, lr)) < 1e-11
 
 
-def _decoupled_problem(m, seed=0):
-    # A, B block diagonal with a 2 x 2 leading block: coordinates 0, 1 (and
-    # m, m + 1) do not couple to the rest
-    rng = np.random.default_rng(seed)
-    X = complex_normal(rng, (m, m))
-    A = X @ X.conj().T / m + 2.0 * np.eye(m)
-    C = complex_normal(rng, (m, m))
-    B = 0.15 * (C + C.T)
-    A[:2, 2:] = 0; A[2:, :2] = 0
-    B[:2, 2:] = 0; B[2:, :2] = 0
-    return A, B
-
-
 def test_backup_recovers_pairs_when_qsq_singular():
     # range(Q) = an exact +/- eigenpair of the trailing block plus the two
     # S-neutral, mutually S-orthogonal vectors [e0; e1], [e1; e0]: Q^H S Q has
     # a 2 x 2 zero block, Alg. 2 resolves one positive value only, the
     # back-up quotient (zero diagonal entries replaced) gives both, and the
     # exact pair among them
-    m = 10
-    A, B = _decoupled_problem(m)
-    H = ham.assemble_h(A, B)
-    idx = np.r_[2:m, m + 2:2 * m]
-    w, V = np.linalg.eig(H[np.ix_(idx, idx)])
-    j = int(np.argmin(np.where(w.real > 0, w.real, np.inf)))
-    v = np.zeros(2 * m, complex)
-    v[idx] = V[:, j]
-    v /= np.linalg.norm(v)
-    e = np.zeros((2 * m, 2), complex)
-    e[0, 0] = e[m + 1, 0] = 1 / np.sqrt(2)
-    e[1, 1] = e[m, 1] = 1 / np.sqrt(2)
-    Q = np.concatenate([v[:, None], ham.apply_k_conj(v[:, None]), e], axis=1)
-    Q, _ = np.linalg.qr(Q)
+    A, B, Q, lam_exact = decoupled_singular_case()
     N = Q.conj().T @ ham.apply_s(Q)
     assert np.linalg.matrix_rank(N, tol=1e-10) == 2
     lam_rr, _, _ = rayleigh_ritz.oblique_rr(A, B, Q)
     assert len(lam_rr) == 1
     lam_bk, Z, _ = rayleigh_ritz.oblique_rr_backup(A, B, Q)
     assert len(lam_bk) == 2
-    i = int(np.argmin(np.abs(lam_bk - w[j].real)))
-    assert abs(lam_bk[i] - w[j].real) < 1e-12 * abs(w[j])
+    i = int(np.argmin(np.abs(lam_bk - lam_exact)))
+    assert abs(lam_bk[i] - lam_exact) < 1e-12 * lam_exact
     Vb = residuals.back_transform(Q, Z[:, i:i + 1])
     assert residuals.residual_norms(A, B, Vb, lam_bk[i:i + 1])[0] < 1e-12
 
