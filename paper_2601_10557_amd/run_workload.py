@@ -1,7 +1,7 @@
 """One solve of a named synthetic workload, drawn on the device.
 
     python -m paper_2601_10557_amd.run_workload --config 4 [--precision mixed|fp64]
-        [--max-iter 30] [--backward] [--samples 6]
+        [--max-iter 30] [--backward] [--samples 6] [--rr-backup]
 
 Builds the workload with ``synth.gpu`` (seeded, seed 0 by default), runs
 ``chase_ph_solve`` and prints one JSON line: wall time, phase times, filter
@@ -9,7 +9,8 @@ TFLOP/s, iterations, the first and last eigenvalue, the largest residual
 the solver reports, and ``host_residuals``: ``||H v - lambda v||`` for a few
 returned pairs recomputed on the host from copies of A and B (numpy).  With
 ``--backward`` it also times ``chase_ph_eigval_backward`` for random loss
-weights on the returned pairs.  Per-iteration progress goes to stderr with
+weights on the returned pairs; ``--rr-backup`` runs the non-hermitian
+back-up Rayleigh quotient (Section 6) in every iteration.  Per-iteration progress goes to stderr with
 ``CHASE_PH_VERBOSE=1``.
 """
 from __future__ import annotations
@@ -32,6 +33,7 @@ def main(argv=None):
     ap.add_argument("--max-iter", type=int, default=30)
     ap.add_argument("--backward", action="store_true")
     ap.add_argument("--samples", type=int, default=6)
+    ap.add_argument("--rr-backup", action="store_true")
     args = ap.parse_args(argv)
     from synth.gpu import config_problem_device
 
@@ -41,7 +43,8 @@ def main(argv=None):
     gen_s = time.perf_counter() - t0
     prec = MIXED if args.precision == "mixed" else FP64
     s = PHSolver(p.A, p.B, p.nev, p.nex, deg=p.deg, tol=p.tol, precision=prec, max_iter=args.max_iter,
-                 opt_deg=p.deg_min != p.deg_max, deg_min=p.deg_min, deg_max=p.deg_max)
+                 opt_deg=p.deg_min != p.deg_max, deg_min=p.deg_min, deg_max=p.deg_max,
+                 rr_backup=args.rr_backup)
     t0 = time.perf_counter()
     ev, V, res, info = s.solve(colmajor(p.w0_raw), colmajor(p.lanczos_raw), raise_on_noconv=False)
     torch.cuda.synchronize()
@@ -52,7 +55,8 @@ def main(argv=None):
                phases_s=dict(lanczos=round(info.t_lanczos, 3), filter=round(info.t_filter, 3),
                              qr=round(info.t_qr, 3), rr=round(info.t_rr, 3), resid=round(info.t_resid, 3)),
                filter_tflops=round(info.filter_flops / info.t_filter / 1e12, 2) if info.t_filter > 0 else 0.0,
-               shifted_qr=info.shifted_qr_used, householder_qr=info.householder_qr_used)
+               shifted_qr=info.shifted_qr_used, householder_qr=info.householder_qr_used,
+               backup_rr=info.backup_rr_used)
     if len(ev):
         out.update(lambda_first=float(ev[0]), lambda_last=float(ev[-1]), max_resid=float(np.max(res)))
     if args.backward and len(ev):

@@ -335,12 +335,21 @@ def _unit_ritz(Q, Z):
     return V / np.linalg.norm(V, axis=0)[None, :]
 
 
-@pytest.mark.parametrize("kh", [1, 2, 20, 40])
-def test_oblique_rr_backup_matches_oracle(prob, solver, solver80, kh):
-    # Section 6 back-up quotient on a filtered search block; k = 2 .. 80
+@pytest.fixture(scope="module")
+def solver260(prob):
+    """Handle with nevex = 130: Rayleigh-Ritz blocks of up to 260 columns."""
+    A, B = dev_blocks(prob)
+    s = PHSolver(A, B, 100, 30)
+    yield s
+    s.close()
+
+
+@pytest.mark.parametrize("kh", [1, 2, 20, 40, 130])
+def test_oblique_rr_backup_matches_oracle(prob, solver, solver80, solver260, kh):
+    # Section 6 back-up quotient on a filtered search block; k = 2 .. 260
     # (Hessenberg reduction over ragged 64-row groups, QR iteration, back-
-    # substitution over two 64-thread groups at k = 80)
-    s = solver if kh <= 20 else solver80
+    # substitution over up to five 64-thread groups)
+    s = solver if kh <= 20 else (solver80 if kh <= 40 else solver260)
     print_case("oblique_rr_backup", m=prob.m, k=2 * kh)
     X = _search_block(prob, kh, seed=6)
     Q, _, _ = oqr.cholqr2(X)
