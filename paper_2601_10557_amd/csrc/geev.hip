@@ -12,8 +12,9 @@
 //      leaves the upper-triangular Schur factor T in place and accumulates
 //      the rotations into Z.  One workgroup: every Givens step of a bulge
 //      chase is one barrier; all threads derive the same rotation from the
-//      same two entries, then update disjoint entries of the two rows, the
-//      two columns and Z;
+//      same two entries (handed over in LDS by the step that produced
+//      them), then update disjoint entries of the two rows, the two columns
+//      and Z;
 //   3. eigenvectors of T by back-substitution (one thread per eigenvector,
 //      tiny pivots raised to ulp |lambda|), then V = Z Y by the c128 GEMM.
 // The selection of the positive half runs on the device too.
@@ -192,6 +193,7 @@ __device__ __forceinline__ c128 wilkinson(c128 a, c128 b, c128 cc, c128 d) {
 __global__ __launch_bounds__(QR_THREADS) void hqr_kernel(c128* H, c128* Z, int64_t ld, int k, c128* w, int* status,
                                                          int max_sweeps) {
   __shared__ int s_l;
+  __shared__ c128 s_xy[2][2];  // next rotation's inputs, by step parity
   const int tid = threadIdx.x;
   auto at = [&](int r, int c) -> c128& { return H[(int64_t)c * ld + r]; };
   int hi = k - 1, its = 0, total = 0;
@@ -226,14 +228,19 @@ __global__ __launch_bounds__(QR_THREADS) void hqr_kernel(c128* H, c128* Z, int64
     } else {
       mu = wilkinson(at(hi - 1, hi - 1), at(hi - 1, hi), at(hi, hi - 1), at(hi, hi));
     }
+    // the first rotation's inputs, read by every thread before any update
+    const c128 x0 = zsub(at(l, l), mu), y0 = at(l + 1, l);
+    __syncthreads();
     for (int j = l; j < hi; ++j) {
-      const c128 x = j == l ? zsub(at(l, l), mu) : at(j, j - 1);
-      const c128 y = j == l ? at(l + 1, l) : at(j + 1, j - 1);
+      // later rotations take (H[j][j-1], H[j+1][j-1]) from the slot the
+      // previous step filled, so that this step's updates of those entries
+      // cannot race with their reads
+      const c128 x = j == l ? x0 : s_xy[j & 1][0];
+      const c128 y = j == l ? y0 : s_xy[j & 1][1];
       double c;
       c128 s;
       givens(x, y, c, s);
       const c128 sc = zconj(s);
-      __syncthreads();  // x, y read by every thread before any update
       // rows j, j+1 (left rotation) over columns cs .. k-1 except j, j+1
       const int cs = j == l ? l : j - 1;
       const int rmax = min(j + 2, hi);
@@ -250,8 +257,10 @@ __global__ __launch_bounds__(QR_THREADS) void hqr_kernel(c128* H, c128* Z, int64
           const int r = t - nrow;
           if (r == j || r == j + 1) continue;
           const c128 a = at(r, j), b = at(r, j + 1);
-          at(r, j) = zadd(zscale(c, a), zmul(sc, b));
+          const c128 rj = zadd(zscale(c, a), zmul(sc, b));
+          at(r, j) = rj;
           at(r, j + 1) = zsub(zscale(c, b), zmul(s, a));
+          if (r == j + 2) s_xy[(j + 1) & 1][1] = rj;  // the bulge, next step's y
         } else if (t < nrow + ncol + k) {
           const int r = t - nrow - ncol;
           c128* z0 = Z + (int64_t)j * ld + r;
@@ -266,8 +275,10 @@ __global__ __launch_bounds__(QR_THREADS) void hqr_kernel(c128* H, c128* Z, int64
           const c128 b01 = zadd(zscale(c, a01), zmul(s, a11)), b11 = zsub(zscale(c, a11), zmul(sc, a01));
           at(j, j) = zadd(zscale(c, b00), zmul(sc, b01));
           at(j, j + 1) = zsub(zscale(c, b01), zmul(s, b00));
-          at(j + 1, j) = zadd(zscale(c, b10), zmul(sc, b11));
+          const c128 n10 = zadd(zscale(c, b10), zmul(sc, b11));
+          at(j + 1, j) = n10;
           at(j + 1, j + 1) = zsub(zscale(c, b11), zmul(s, b10));
+          s_xy[(j + 1) & 1][0] = n10;  // next step's x
         }
       }
       __syncthreads();
@@ -282,7 +293,8 @@ __global__ __launch_bounds__(QR_THREADS) void hqr_kernel(c128* H, c128* Z, int64
 // (T - t_ii I) y = 0 with y_i = 1, y_c = 0 for c > i, by back-substitution
 // from row i - 1 up; a pivot |t_rr - t_ii| below smin = max(ulp |t_ii|,
 // safmin) is replaced by smin.  The work vector is stored transposed
-// (Yt[i + c k], coalesced across the threads of a block); the column is
+// (Yt[i + c k], coalesced across the threads of a block) and rescaled by
+// 1e-150 when an entry exceeds 1e150; the column is
 // finally written to Y (ld ldy).
 __global__ __launch_bounds__(64) void trevc_kernel(const c128* T, int64_t ld, int k, c128* Yt, c128* Y,
                                                    int64_t ldy) {
@@ -299,7 +311,13 @@ __global__ __launch_bounds__(64) void trevc_kernel(const c128* T, int64_t ld, in
     for (int c = r + 1; c <= i; ++c) acc = zadd(acc, zmul(T[(int64_t)c * ld + r], Yt[(int64_t)c * k + i]));
     c128 d = zsub(T[(int64_t)r * ld + r], lam);
     if (zabs1(d) < smin) d = c128{smin, 0.0};
-    Yt[(int64_t)r * k + i] = zscale(-1.0, zdiv(acc, d));
+    const c128 yr = zscale(-1.0, zdiv(acc, d));
+    Yt[(int64_t)r * k + i] = yr;
+    // repeated tiny pivots (equal eigenvalues) make y grow geometrically:
+    // scale the entries found so far down before they can overflow (the
+    // eigenvector is defined up to scale)
+    if (zabs1(yr) > 1e150)
+      for (int c = r; c <= i; ++c) Yt[(int64_t)c * k + i] = zscale(1e-150, Yt[(int64_t)c * k + i]);
   }
   if (act)
     for (int c = 0; c < k; ++c) Y[(int64_t)i * ldy + c] = c <= i ? Yt[(int64_t)c * k + i] : c128{0.0, 0.0};
