@@ -170,8 +170,11 @@ Err prof_begin(chase_ph_t h) {
   if (!h->prof || h->launches.size() >= PROF_MAX) return ok();
   const size_t i = 2 * h->launches.size();
   while (h->evpool.size() < i + 2) {
+    // timing only: no system-scope fence on record (which would write back
+    // and invalidate the caches around every timed launch); the times are
+    // read after the caller has synchronised the device
     hipEvent_t e;
-    CHASE_HIP(hipEventCreate(&e));
+    CHASE_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     h->evpool.push_back(e);
   }
   CHASE_HIP(hipEventRecord(h->evpool[i], h->st));
