@@ -45,3 +45,57 @@ def test_default_params_are_the_papers():
     assert p.max_iter == vals["max_iter"]
     assert p.deg_min == vals["deg_min"] and p.deg_max == vals["deg_max"]
     assert p.lanczos_steps % 2 == 0 and abs(p.lanczos_steps - vals["lanczos_steps_default"]) <= 1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # no host fallback: a missing library is an import error
+    from paper_2601_10557_amd import _lib
+    try:
+        _lib.load(str(tmp_path / "libchase_ph.so"))
+    except ImportError as e:
+        assert "no fallback" in str(e)
+    else:
+        raise AssertionError("load() of a missing library did not raise")
+
+
+def _struct_fields(name):
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1] if not decl.startswith("double*") else decl[len("double*"):]
+        for n in names.split(","):
+            fields.append(n.strip().lstrip("*"))
+    return fields
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Field order, offsets and sizes of the ctypes mirrors against the C
+    compiler's layout of the header structs."""
+    import shutil
+    import subprocess
+    from paper_2601_10557_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    assert cc, "no C compiler"
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for cname, pyt in (("chase_ph_params", _lib.Params), ("chase_ph_info", _lib.Info)):
+        names = _struct_fields(cname)
+        assert names == [f for f, _ in pyt._fields_], (cname, names)
+        src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for n in names:
+            src.append(f'printf("{cname}.{n} %zu\\n", offsetof({cname}, {n}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, str(c), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                               text=True).stdout.split("\n") if line)
+    for cname, pyt in (("chase_ph_params", _lib.Params), ("chase_ph_info", _lib.Info)):
+        assert int(out[cname]) == ctypes.sizeof(pyt), cname
+        for f, _ in pyt._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(pyt, f).offset, (cname, f)
