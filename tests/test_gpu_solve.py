@@ -77,13 +77,19 @@ def test_solve_per_vector_degrees(cfg0):
     _check_solution(p, ev, V, res, lam, 1e-10)
 
 
-def test_solve_backup_rr_every_iteration(cfg0):
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_solve_backup_rr_every_iteration(cfg0, prec):
     # the non-hermitian back-up quotient of Section 6 in every iteration
     p, lam = cfg0
-    print_case("solve_backup_rr", cfg=0, m=p.m)
-    _, (ev, V, res, info) = _solve(p, precision=FP64, rr_backup=True, max_iter=40)
-    _check_solution(p, ev, V, res, lam, 1e-10)
-    assert info.backup_rr_used == info.iterations
+    print_case("solve_backup_rr", cfg=0, m=p.m, prec=prec)
+    tol0 = p.tol
+    p.tol = 1e-10 if prec == FP64 else 1e-9
+    try:
+        _, (ev, V, res, info) = _solve(p, precision=prec, rr_backup=True, max_iter=40)
+        _check_solution(p, ev, V, res, lam, p.tol)
+        assert info.backup_rr_used == info.iterations
+    finally:
+        p.tol = tol0
 
 
 def test_solve_zero_start_column_takes_householder_qr(cfg0):
