@@ -456,8 +456,7 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
                    GEMM_LOWER_ONLY | (real ? GEMM_REAL : 0)));
     CHASE_TRY(trace(h->G, kp, k, h->dws.dscalar, h->st));
     double fro2 = 0;
-    CHASE_HIP(hipMemcpyAsync(&fro2, h->dws.dscalar, sizeof(double), hipMemcpyDeviceToHost, h->st));
-    CHASE_HIP(hipStreamSynchronize(h->st));
+    CHASE_TRY(d2h_small(&fro2, h->dws.dscalar, sizeof(double), h->dws, h->st));
     const double shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * U_ROUND * fro2;
     CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed, real));
     if (!failed) CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real));
@@ -508,8 +507,7 @@ Err rr_backup(chase_ph_t h, int k, const c128* Q, int64_t ldq, const c128* T, in
   CHASE_TRY(gemm(h, 0, 0, k, k, k, {1, 0}, h->Ev, kp, h->Li, kp, {0, 0}, h->Ys, kp, -1, false));  // Z Y
   CHASE_TRY(select_by_real_part(h->Wev, k, h->Ys, kp, h->dperm, h->dlam, Zpos, ldz, h->st));
   if (ritz) {
-    CHASE_HIP(hipMemcpyAsync(ritz, h->dlam, sizeof(double) * (k / 2), hipMemcpyDeviceToHost, h->st));
-    CHASE_HIP(hipStreamSynchronize(h->st));
+    CHASE_TRY(d2h_small(ritz, h->dlam, sizeof(double) * (k / 2), h->dws, h->st));
   }
   return ok();
 }
@@ -562,8 +560,7 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
                                                std::to_string(k));
   CHASE_TRY(gemm(h, 1, 0, k, k / 2, k, {1, 0}, h->Li, kp, h->Ys, kp, {0, 0}, Zpos, ldz, -1, false));  // Z = L^{-H} Y
   if (ritz) {
-    CHASE_HIP(hipMemcpyAsync(ritz, h->dlam, sizeof(double) * (k / 2), hipMemcpyDeviceToHost, h->st));
-    CHASE_HIP(hipStreamSynchronize(h->st));
+    CHASE_TRY(d2h_small(ritz, h->dlam, sizeof(double) * (k / 2), h->dws, h->st));
   }
   return ok();
 }
@@ -576,8 +573,7 @@ Err resid_impl(chase_ph_t h, int k, int kk, const c128* Q, int64_t ldq, const c1
   CHASE_TRY(gemm(h, 0, 0, n, kk, k, {1, 0}, T, ldt, Zpos, ldz, {0, 0}, h->TZ, n, -1, false));
   if (ritz_host) CHASE_TRY(h2d(h, h->dlam, ritz_host, sizeof(double) * kk));
   CHASE_TRY(residual_norms(V, ldv, h->TZ, n, h->dlam, n, kk, h->dres, Rout, n, h->st));
-  CHASE_HIP(hipMemcpyAsync(resid, h->dres, sizeof(double) * kk, hipMemcpyDeviceToHost, h->st));
-  CHASE_HIP(hipStreamSynchronize(h->st));
+  CHASE_TRY(d2h_small(resid, h->dres, sizeof(double) * kk, h->dws, h->st));
   return ok();
 }
 
@@ -1114,6 +1110,10 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_TRY(dalloc(h, &h->dws.flag, 4));
   CHASE_TRY(dalloc(h, &h->dws.pflag, (size_t)h->kp / 8 + 1));
   CHASE_TRY(dalloc(h, &h->dws.dscalar, 4));
+  // pinned host staging for the small reads of every iteration (flags,
+  // counts, Ritz values, residuals: at most kmax doubles)
+  h->dws.hpin_bytes = std::max<size_t>(4096, sizeof(double) * (size_t)h->kmax);
+  CHASE_HIP(hipHostMalloc(&h->dws.hpin, h->dws.hpin_bytes, hipHostMallocDefault));
   // zgemm split-K partials (up to 8 k x k blocks) and apply_h split-K
   // partials (up to 8 x m x 2 nevex complex), within [16 MiB, 1 GiB]
   h->ws_bytes = std::max(kp2 * sizeof(c128) * 8, (size_t)8 * h->m * h->kmax * sizeof(c128));
@@ -1173,6 +1173,7 @@ chase_ph_status chase_ph_destroy(chase_ph_t h) {
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
   for (void* q : h->allocs) (void)hipFree(q);
+  if (h->dws.hpin) (void)hipHostFree(h->dws.hpin);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->side.fork) (void)hipEventDestroy(h->side.fork);
   if (h->side.join) (void)hipEventDestroy(h->side.join);

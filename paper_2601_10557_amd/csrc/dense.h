@@ -14,7 +14,14 @@ struct DenseWs {
   double* dscalar = nullptr;  // 4 doubles
   void* gemm_ws = nullptr;     // split-K partials of the batched GEMMs (may be null)
   size_t gemm_ws_bytes = 0;
+  void* hpin = nullptr;        // pinned host staging for small device-to-host reads (may be null)
+  size_t hpin_bytes = 0;
 };
+
+// Copy bytes from device memory to host memory and wait for it: through the
+// pinned staging buffer of ws when it is large enough (a direct transfer,
+// no pageable staging on the runtime's side), else straight to host.
+Err d2h_small(void* host, const void* dev, size_t bytes, const DenseWs& ws, hipStream_t s);
 
 int pad64(int k);
 // M = diag(inner) on the first k, pad on the rest; off-diagonals zeroed

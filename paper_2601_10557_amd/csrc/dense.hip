@@ -10,6 +10,7 @@
 //    32 x 32 complex products.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 #include <vector>
 
@@ -557,6 +558,15 @@ __global__ void select_kernel(const c128* G, const c128* V, int64_t ld, int k, i
 }  // namespace
 
 // ---------------------------------------------------------------------------
+Err d2h_small(void* host, const void* dev, size_t bytes, const DenseWs& ws, hipStream_t s) {
+  if (bytes == 0) return ok();
+  void* dst = (ws.hpin && bytes <= ws.hpin_bytes) ? ws.hpin : host;
+  CHASE_HIP(hipMemcpyAsync(dst, dev, bytes, hipMemcpyDeviceToHost, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  if (dst != host) std::memcpy(host, dst, bytes);
+  return ok();
+}
+
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 2048)); }
 
 static Err frob_norm(const c128* G, int kp, DenseWs& ws, hipStream_t s, double* host_out) {
@@ -565,9 +575,7 @@ static Err frob_norm(const c128* G, int kp, DenseWs& ws, hipStream_t s, double* 
   CHASE_LAUNCH_CHECK();
   hipLaunchKernelGGL(frob_sum_kernel, dim3(1), dim3(256), 0, s, (const double*)part, kp, ws.dscalar);
   CHASE_LAUNCH_CHECK();
-  CHASE_HIP(hipMemcpyAsync(host_out, ws.dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
-  CHASE_HIP(hipStreamSynchronize(s));
-  return ok();
+  return d2h_small(host_out, ws.dscalar, sizeof(double), ws, s);
 }
 
 Err fill_padded(c128* M, int kp, int k, double inner, double pad, bool zero_all, hipStream_t s) {
@@ -612,8 +620,7 @@ Err cholesky_lower(c128* M, int kp, DenseWs& ws, hipStream_t s, bool* failed) {
   hipLaunchKernelGGL(zero_upper_kernel, dim3(grid_for((int64_t)kp * kp)), dim3(256), 0, s, M, (int64_t)kp, kp);
   CHASE_LAUNCH_CHECK();
   int f = 0;
-  CHASE_HIP(hipMemcpyAsync(&f, ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  CHASE_HIP(hipStreamSynchronize(s));
+  CHASE_TRY(d2h_small(&f, ws.flag, sizeof(int), ws, s));
   *failed = f != 0;
   return ok();
 }
@@ -674,8 +681,7 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
       CHASE_LAUNCH_CHECK();
     }
     int cnt = 0;
-    CHASE_HIP(hipMemcpyAsync(&cnt, ws.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    CHASE_HIP(hipStreamSynchronize(s));
+    CHASE_TRY(d2h_small(&cnt, ws.flag, sizeof(int), ws, s));
     if (cnt == 0) break;
   }
   if (sweeps_out) *sweeps_out = sweep;
@@ -694,8 +700,7 @@ Err select_positive(const c128* G, const c128* V, int k, int kp, c128* Ysel, dou
                      ws.flag + 1);
   CHASE_LAUNCH_CHECK();
   int h[2] = {0, 0};
-  CHASE_HIP(hipMemcpyAsync(h, ws.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  CHASE_HIP(hipStreamSynchronize(s));
+  CHASE_TRY(d2h_small(h, ws.flag, 2 * sizeof(int), ws, s));
   *npos = h[0];
   *nneg = h[1];
   return ok();
