@@ -50,6 +50,21 @@ def _solve(p, **kw):
     return s, s.solve(to_dev(p.w0_raw), to_dev(p.lanczos_raw))
 
 
+def test_lanczos_estimates_match_oracle(cfg0):
+    # Section 4.1 spectral estimates of the solver (26 steps x 4 runs on the
+    # gamma-scaled starts) against the oracle's on the same starts; rounding
+    # perturbations of the starts move them by ~1e-13 relative
+    from oracle import lanczos, solver as osolver
+    p, _ = cfg0
+    print_case("lanczos_estimates", cfg=0, m=p.m)
+    A, B = dev_blocks(p)
+    s = PHSolver(A, B, p.nev, p.nex, deg=p.deg, tol=p.tol, max_iter=1)
+    _, _, _, info = s.solve(to_dev(p.w0_raw), to_dev(p.lanczos_raw), raise_on_noconv=False)
+    s.close()
+    ref = lanczos.spectral_estimates(p.A, p.B, osolver.init_block(p.lanczos_raw, 1e-3), 26, p.nev + p.nex)
+    assert np.allclose([info.mu1, info.mu_nevex0, info.mu_n], ref, rtol=1e-9, atol=0)
+
+
 def test_solve_fp64_config0(cfg0):
     p, lam = cfg0
     print_case("solve_fp64", cfg=0, m=p.m)

@@ -449,8 +449,40 @@ def test_solver_max_iter_partial():
     assert not info["converged"] and info["iterations"] == 1
 
 
+@pytest.mark.parametrize("steps", [3, 5, 6])
+def test_lanczos_gauss_quadrature_moments(steps):
+    # s steps of Lanczos in the S H inner product form a Gauss rule: the
+    # nodes theta (eigenvalues of T) and weights tau (squared first
+    # components of its eigenvectors) reproduce the moments
+    # v^H S H H^j v / v^H S H v for j < 2 s, and miss the one at j = 2 s
+    p = small_problem(6, seed=1)
+    H = ham.assemble_h(p.A, p.B)
+    SH = ham.assemble_sh(p.A, p.B)
+    v = complex_normal(np.random.default_rng(3), (12,))
+    a, b = lanczos.lanczos_run(p.A, p.B, v, steps)
+    T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+    th, Y = np.linalg.eigh(T)
+    tau = np.abs(Y[0]) ** 2
+    nrm = np.real(np.vdot(v, SH @ v))
+    mom = [np.real(np.vdot(v, SH @ np.linalg.matrix_power(H, j) @ v)) / nrm for j in range(2 * steps + 1)]
+    for j in range(2 * steps):
+        assert abs(np.sum(tau * th ** j) - mom[j]) <= 1e-11 * max(1.0, abs(mom[j]))
+    assert abs(np.sum(tau * th ** (2 * steps)) - mom[2 * steps]) > 1e-8 * abs(mom[2 * steps])
+
+
+def test_lanczos_full_dimension_reproduces_spectrum():
+    # n steps span the whole space: the eigenvalues of T are those of H
+    p = small_problem(6, seed=1)
+    v = complex_normal(np.random.default_rng(4), (12,))
+    a, b = lanczos.lanczos_run(p.A, p.B, v, 12)
+    T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+    lam = np.sort(np.linalg.eigvals(ham.assemble_h(p.A, p.B)).real)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(T)), lam, rtol=1e-10, atol=0)
+
+
 def test_lanczos_estimates_bounds():
-    # parity unpinned heuristic: only bounded
+    # the estimates built on the recurrence are heuristics (parity of the
+    # choices unpinned): only bounded
     p = small_problem(80)
     lam, _ = dense.dense_ph_eig(p.A, p.B)
     mu1, mu_nevex, mu_n = lanczos.spectral_estimates(
