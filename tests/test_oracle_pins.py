@@ -480,6 +480,38 @@ def test_lanczos_full_dimension_reproduces_spectrum():
     assert np.allclose(np.sort(np.linalg.eigvalsh(T)), lam, rtol=1e-10, atol=0)
 
 
+def test_next_degrees_is_the_smallest_sufficient_degree():
+    # per-vector degrees: the smallest d in [deg_min, deg_max] with
+    # r rho^-d <= tol, rho the growth rate of T_d at t = (lambda^2 - c) / e,
+    # taken here from the Chebyshev recurrence itself (T_{d+1} / T_d at
+    # d = 60) on the interval [mu_nevex^2, mu_n^2] of the filter on H^2
+    mu1, mu_nevex, mu_n = 1.0, 1.6, 5.0
+    c = 0.5 * (mu_n ** 2 + mu_nevex ** 2)
+    e = 0.5 * (mu_n ** 2 - mu_nevex ** 2)
+
+    def rho_of(lam):
+        t = abs(lam * lam - c) / e
+        tm, tc = 1.0, t
+        for _ in range(60):
+            tm, tc = tc, 2.0 * t * tc - tm
+        return tc / tm
+
+    lam = np.array([1.0, 1.05, 1.2, 1.4, 1.55, 1.59, 2.0, 3.0, 1.3])
+    res = np.array([1e-2, 1e-4, 1e-6, 1e-3, 1e-1, 1e-2, 1e-2, 1e-3, 1e-12])
+    tol, dmin, dmax = 1e-10, 4, 40
+    got = solver.next_degrees(lam, res, tol, mu1, mu_nevex, mu_n, dmin, dmax)
+    for l, r, d in zip(lam, res, got):
+        if r <= tol:
+            assert d == dmin                        # converged: the smallest degree
+            continue
+        if l * l >= mu_nevex ** 2:
+            assert d == dmax                        # inside the damped interval: no gain rate
+            continue
+        rho = rho_of(l)
+        want = next(dd for dd in range(1, 10 ** 4) if r * rho ** (-dd) <= tol)
+        assert d == min(max(want, dmin), dmax), (l, r, d, want)
+
+
 def test_lanczos_estimates_bounds():
     # the estimates built on the recurrence are heuristics (parity of the
     # choices unpinned): only bounded
