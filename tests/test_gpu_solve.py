@@ -158,8 +158,10 @@ def test_solve_no_convergence_partial(cfg0):
 
 
 def test_solve_config1_fp64_and_mixed():
-    """Full-size m=4000 workload: both precisions against the stored dense
-    oracle eigenvalues (tests/golden, written by make_dense_reference.py)."""
+    """Full-size m=4000 workload: both precisions, and the mixed path with the
+    back-up quotient of Section 6 in every iteration (k up to 520), against
+    the stored dense oracle eigenvalues (tests/golden, written by
+    make_dense_reference.py)."""
     path = os.path.join(GOLDEN, "dense_evals_config1_seed0.txt")
     if not os.path.exists(path):
         pytest.skip("golden file missing")
@@ -169,11 +171,13 @@ def test_solve_config1_fp64_and_mixed():
     A, B = dev_blocks(p)
     W0, Lz = to_dev(p.w0_raw), to_dev(p.lanczos_raw)
     out = {}
-    for prec in (FP64, MIXED):
-        s = PHSolver(A, B, p.nev, p.nex, deg=p.deg, tol=p.tol, precision=prec)
+    for prec, backup in ((FP64, False), (MIXED, False), (MIXED, True)):
+        s = PHSolver(A, B, p.nev, p.nex, deg=p.deg, tol=p.tol, precision=prec, rr_backup=backup)
         ev, V, res, info = s.solve(W0, Lz)
         rel = np.abs(ev - ref[: p.nev]) / ref[: p.nev]
-        print_case("config1", prec=prec, iters=info.iterations, t=round(info.t_total, 3), maxrel=rel.max())
+        print_case("config1", prec=prec, backup=backup, iters=info.iterations, t=round(info.t_total, 3),
+                   maxrel=rel.max())
+        assert info.backup_rr_used == (info.iterations if backup else 0)
         assert np.max(rel) <= 1e-9
         assert np.all(res <= p.tol)
         # sampled host recomputation of residuals (8 pairs)
@@ -181,9 +185,10 @@ def test_solve_config1_fp64_and_mixed():
         Vh = to_host(V[:, idx])
         r = ores.residual_norms(p.A, p.B, Vh, ev[idx])
         assert np.all(r <= 1.5 * p.tol)
-        out[prec] = ev
+        out[(prec, backup)] = ev
         s.close()
-    assert np.max(np.abs(out[FP64] - out[MIXED]) / out[FP64]) <= 1e-9
+    assert np.max(np.abs(out[(FP64, False)] - out[(MIXED, False)]) / out[(FP64, False)]) <= 1e-9
+    assert np.max(np.abs(out[(MIXED, True)] - out[(MIXED, False)]) / out[(MIXED, False)]) <= 1e-9
 
 
 def test_autograd_matches_dense_adjoint_and_fd():
