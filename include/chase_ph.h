@@ -24,8 +24,16 @@
  *   CHASE_PH_ERR_HIP the handle is unusable and must be destroyed.
  *   chase_ph_last_error() returns a handle-owned message for the last error.
  * - One handle per host thread; calls on one handle must not overlap.
- * - No entry point falls back to host computation: every step of the
- *   numerical path runs in the library's own GPU kernels.
+ * - No entry point falls back to host computation: every step on vectors
+ *   of length n and on k x k matrices runs in the library's own GPU
+ *   kernels.  The host keeps O(k) scalars (Ritz values, residuals,
+ *   degrees, locking) and diagonalises the Lanczos tridiagonals (at most
+ *   lanczos_steps x lanczos_steps) for the spectral estimates of
+ *   Section 4.1.
+ * - The back-up quotient is the alternative dual basis named at the end of
+ *   Section 4.4; Section 5.3 ("Non-hermitian Rayleigh-Quotient as
+ *   back-up", carried as removed text in the paper's source) gives its
+ *   quotient and the rule of keeping the real parts.
  */
 #ifndef CHASE_PH_H
 #define CHASE_PH_H
@@ -78,7 +86,7 @@ typedef struct {
   int32_t lanczos_steps;/* per run, even (Section 4.1; 26)                                  */
   int32_t lanczos_vecs; /* independent Lanczos runs (4)                                     */
   int32_t a_conj;       /* 1: the buffer dA holds conj(A) column-major (= A row-major)      */
-  int32_t rr_backup;    /* 0: the non-hermitian back-up quotient of Section 6 only when     */
+  int32_t rr_backup;    /* 0: the non-hermitian back-up quotient of Section 5.3 only when   */
                         /* Alg. 2 resolves fewer than k/2 positive Ritz values (Q^H S Q     */
                         /* singular); 1: the back-up quotient in every iteration            */
 } chase_ph_params;
@@ -181,7 +189,7 @@ chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int
                                     double* hRitz, void* dZpos, int64_t ldz, void* dT,
                                     int64_t ldt);
 
-/* Rayleigh-Ritz with the non-hermitian back-up quotient of Section 6, for
+/* Rayleigh-Ritz with the non-hermitian back-up quotient of Section 5.3, for
  * a block where Alg. 2 fails because Q^H S Q is singular; same arguments
  * and outputs as chase_ph_oblique_rr.  With N = Q^H S Q and D = diag(N)
  * (entries below 1e-8 in modulus replaced by 1, which keeps the dual basis

@@ -22,7 +22,6 @@ qr            CholeskyQR2 with a shifted-CholeskyQR3 fallback (Section 2)
 rayleigh_ritz oblique Rayleigh-Ritz via the inverse Rayleigh quotient (Alg. 2)
 residuals     half back-transform and residual norms (Section 4.5)
 lanczos       S-inner-product Lanczos spectral estimates (Section 4.1)
-              -- parity unpinned (heuristic; affects iteration count only)
 solver        the pseudo-hermitian ChASE outer loop (Alg. 3)
 adjoint       first-order eigenvalue adjoint dL/dA, dL/dB (from Thm 3.2)
 """

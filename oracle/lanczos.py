@@ -1,12 +1,16 @@
 """Spectral estimates mu_1, mu_nevex, mu_n from a few Lanczos steps
 (Section 4.1; Alg. 3, estimation step).
 
-The recurrence (lanczos_run) is pinned: its tridiagonal T is a Gauss rule
-for the moments v^H S H H^j v (j < 2 steps), and a full-dimension run
-reproduces the spectrum of H.  PARITY UNPINNED: the estimates built on it
-(spectral_estimates) are heuristics.  They change how many outer iterations
-the solver needs, never what it converges to; tests only bound them (mu_1
-not far above lambda_1, mu_n >= the largest |lambda|).
+Pins: the recurrence (lanczos_run) is a Gauss rule for the moments
+v^H S H H^j v (j < 2 steps), and a full-dimension run reproduces the
+spectrum of H.  The estimates (spectral_estimates) are pinned on starts
+whose Gauss weights are set through their eigenvector components: a run
+that spans the space must return the smallest |lambda|, the largest, and
+the positive eigenvalue at the positive-axis weight quantile nevex / m;
+on a short run, mu_n must be the largest |Ritz value| plus that Ritz
+pair's residual norm, computed by Rayleigh-Ritz on the Krylov space
+itself.  The estimates change how many outer iterations the solver needs,
+never what it converges to.
 
 Reading taken (the paper defers the variant to Gruning et al. 2011 and only
 states that it uses S-inner products, an even step count and the

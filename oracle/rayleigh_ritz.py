@@ -47,7 +47,7 @@ def oblique_rr(A, B, Q, return_all: bool = False):
     G = 0.5 * (G + G.conj().T)                          # = L^{-1} N L^{-H}  (lines 6-7)
     theta, Y = np.linalg.eigh(G)                         # line 8
     Z = scipy.linalg.solve_triangular(L.conj().T, Y, lower=False)      # line 9: L^{-H} Y
-    # Theta ~ 0 belongs to a direction where Q^H S Q is singular (Section 6):
+    # Theta ~ 0 belongs to a direction where Q^H S Q is singular (Section 4.4):
     # only eigenvalues resolved away from zero, theta > 1e3 u ||G||_F, count
     # as positive (fewer than k/2 of them sends the solver to the back-up).
     pos = theta > 1e3 * np.finfo(float).eps / 2 * np.linalg.norm(G)
@@ -62,14 +62,15 @@ def oblique_rr(A, B, Q, return_all: bool = False):
 
 
 # Threshold below which a diagonal entry of Q^H S Q is replaced in the
-# back-up dual basis (Section 6 allows replacing zero entries; any nonzero
+# back-up dual basis (Section 5.3 allows replacing zero entries; any nonzero
 # value keeps Q_L^H Q = I).  Reading: |d_i| < 1e-8 is taken as zero and
 # replaced by 1.
 BACKUP_DIAG_MIN = 1e-8
 
 
 def backup_quotient(Q, T):
-    """Non-hermitian back-up Rayleigh quotient of Section 6.
+    """Non-hermitian back-up Rayleigh quotient of Section 5.3
+    (the alternative dual basis named at the end of Section 4.4).
 
     With ``N = Q^H S Q`` and ``D = diag(N)`` (entries below BACKUP_DIAG_MIN in
     modulus replaced by 1), the dual basis is
@@ -90,7 +91,7 @@ def backup_quotient(Q, T):
 
 
 def oblique_rr_backup(A, B, Q, return_all: bool = False):
-    """Rayleigh-Ritz with the back-up quotient of Section 6 (for a Q^H S Q
+    """Rayleigh-Ritz with the back-up quotient of Section 5.3 (for a Q^H S Q
     that is singular): general eigenproblem ``G y = lambda y``, real parts
     kept.  The back-up dual basis need not be K-symmetric, so the +/- split
     of Thm 4.5 can fail (a replaced zero of diag(Q^H S Q) gives both values

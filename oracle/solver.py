@@ -61,7 +61,7 @@ def solve(A, B, nev, nex, deg, tol, w0_raw, lanczos_raw, max_iter=25, gamma=1e-3
     """Return ``(lam, V, info)``: the nev smallest positive eigenvalues found
     (ascending), unit right eigenvectors (n x nev) and an info dict.
 
-    rr_backup: 0 uses the back-up quotient of Section 6 only when Q^H S Q is
+    rr_backup: 0 uses the back-up quotient of Section 5.3 only when Q^H S Q is
     singular (fewer than k/2 positive eigenvalues of Alg. 2's quotient);
     1 uses it in every iteration."""
     A = np.asarray(A, dtype=np.complex128)

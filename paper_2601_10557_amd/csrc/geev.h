@@ -1,5 +1,5 @@
 // General (non-hermitian) dense eigenproblem of the back-up Rayleigh
-// quotient of Section 6 (geev.hip).
+// quotient of Section 5.3 (geev.hip).
 #pragma once
 #include "common.h"
 
@@ -20,7 +20,7 @@ struct GeevWs {
 Err nonsym_eig(c128* G, c128* Z, int64_t ld, int k, c128* w, c128* Yt, c128* Y, const GeevWs& ws, hipStream_t s,
                int* qr_status);
 
-// Diagonal threshold of the back-up dual basis (Section 6 allows replacing
+// Diagonal threshold of the back-up dual basis (Section 5.3 allows replacing
 // zero entries of diag(Q^H S Q)): |d_i| < BACKUP_DIAG_MIN is replaced by 1.
 constexpr double BACKUP_DIAG_MIN = 1e-8;
 // d_i = Re N_ii (replaced by 1 below BACKUP_DIAG_MIN in modulus) and

@@ -1,5 +1,5 @@
 // Eigenvalues and right eigenvectors of a small dense complex matrix, for
-// the non-hermitian back-up Rayleigh quotient of Section 6 (whose Ritz
+// the non-hermitian back-up Rayleigh quotient of Section 5.3 (whose Ritz
 // values are complex).  Three phases, after Golub & Van Loan, Matrix
 // Computations (4th ed.), Sections 7.4-7.6:
 //   1. Householder reduction to upper Hessenberg form, G = Z H Z^H (one

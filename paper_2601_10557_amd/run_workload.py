@@ -10,7 +10,7 @@ the solver reports, and ``host_residuals``: ``||H v - lambda v||`` for a few
 returned pairs recomputed on the host from copies of A and B (numpy).  With
 ``--backward`` it also times ``chase_ph_eigval_backward`` for random loss
 weights on the returned pairs; ``--rr-backup`` runs the non-hermitian
-back-up Rayleigh quotient (Section 6) in every iteration.  Per-iteration progress goes to stderr with
+back-up Rayleigh quotient (Section 5.3) in every iteration.  Per-iteration progress goes to stderr with
 ``CHASE_PH_VERBOSE=1``.
 """
 from __future__ import annotations

@@ -234,7 +234,7 @@ class PHSolver:
         return ritz, Z, T
 
     def oblique_rr_backup(self, Q: torch.Tensor):
-        """Back-up quotient of Section 6 on orthonormal Q (n x k): returns
+        """Back-up quotient of Section 5.3 on orthonormal Q (n x k): returns
         (real parts of the k/2 positive Ritz values, Zpos k x k/2, T = H Q)."""
         Q = colmajor(Q)
         k = Q.shape[1]

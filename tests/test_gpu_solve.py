@@ -94,7 +94,7 @@ def test_solve_per_vector_degrees(cfg0):
 
 @pytest.mark.parametrize("prec", [FP64, MIXED])
 def test_solve_backup_rr_every_iteration(cfg0, prec):
-    # the non-hermitian back-up quotient of Section 6 in every iteration
+    # the non-hermitian back-up quotient of Section 5.3 in every iteration
     p, lam = cfg0
     print_case("solve_backup_rr", cfg=0, m=p.m, prec=prec)
     tol0 = p.tol
@@ -159,7 +159,7 @@ def test_solve_no_convergence_partial(cfg0):
 
 def test_solve_config1_fp64_and_mixed():
     """Full-size m=4000 workload: both precisions, and the mixed path with the
-    back-up quotient of Section 6 in every iteration (k up to 520), against
+    back-up quotient of Section 5.3 in every iteration (k up to 520), against
     the stored dense oracle eigenvalues (tests/golden, written by
     make_dense_reference.py)."""
     path = os.path.join(GOLDEN, "dense_evals_config1_seed0.txt")

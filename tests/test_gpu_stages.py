@@ -346,7 +346,7 @@ def solver260(prob):
 
 @pytest.mark.parametrize("kh", [1, 2, 20, 40, 130])
 def test_oblique_rr_backup_matches_oracle(prob, solver, solver80, solver260, kh):
-    # Section 6 back-up quotient on a filtered search block; k = 2 .. 260
+    # Section 5.3 back-up quotient on a filtered search block; k = 2 .. 260
     # (Hessenberg reduction over ragged 64-row groups, QR iteration, back-
     # substitution over up to five 64-thread groups)
     s = solver if kh <= 20 else (solver80 if kh <= 40 else solver260)

@@ -318,7 +318,7 @@ def test_rr_ritz_values_in_field_of_values_interval():
 
 
 def _backup_dual_basis(Q):
-    # Q_L = [S Q - Q (Q^H S Q - D)] D^{-1}, D = diag(Q^H S Q) (Section 6),
+    # Q_L = [S Q - Q (Q^H S Q - D)] D^{-1}, D = diag(Q^H S Q) (Sections 4.4, 5.3),
     # written from the dual-basis equation, not from the quotient
     N = Q.conj().T @ ham.apply_s(Q)
     d = np.real(np.diag(N)).copy()
@@ -327,7 +327,7 @@ def _backup_dual_basis(Q):
 
 
 def test_backup_quotient_is_dual_projection():
-    # the quotient equation of Section 6 equals Q_L^H H Q for the dual basis
+    # the quotient equation of Section 5.3 equals Q_L^H H Q for the dual basis
     # equation, and Q_L^H Q = I
     p = small_problem(30)
     Q = _search_basis(p, 6, seed=7)
@@ -387,6 +387,38 @@ def test_backup_recovers_pairs_when_qsq_singular():
 
 
 # ------------------------------------------------------------- solver
+def test_init_block_is_s_positive():
+    # Section 4.6: the start block must lie in the S-positive manifold; the
+    # lower half of the Gaussian block is scaled by gamma (Alg. 3, first
+    # step), so the coupling ratio ||y|| / ||x|| of every column is gamma
+    # times the raw one and W^H S W is positive definite, while the raw
+    # block is S-indefinite
+    rng = np.random.default_rng(2)
+    m, k, gamma = 50, 12, 1e-3
+    raw = complex_normal(rng, (2 * m, k))
+    W = solver.init_block(raw, gamma)
+    assert np.array_equal(W[:m], raw[:m])
+    ratio = np.linalg.norm(W[m:], axis=0) / np.linalg.norm(W[:m], axis=0)
+    raw_ratio = np.linalg.norm(raw[m:], axis=0) / np.linalg.norm(raw[:m], axis=0)
+    assert np.allclose(ratio, gamma * raw_ratio, rtol=1e-14)
+    assert np.linalg.eigvalsh(W.conj().T @ ham.apply_s(W))[0] > 0
+    ev_raw = np.linalg.eigvalsh(raw.conj().T @ ham.apply_s(raw))
+    assert ev_raw[0] < 0 < ev_raw[-1]
+
+
+def test_back_transform_unit_columns():
+    # Section 4.5 / Alg. 3: the back-transformed Ritz vectors Q Z_+ are the
+    # eigenvector estimates whose residuals are measured, on unit vectors
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(complex_normal(rng, (40, 10)))
+    Z = 3.0 * complex_normal(rng, (10, 5))
+    V = residuals.back_transform(Q, Z)
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0, rtol=0, atol=1e-14)
+    QZ = Q @ Z
+    cos = np.abs(np.einsum("ij,ij->j", V.conj(), QZ)) / np.linalg.norm(QZ, axis=0)
+    assert np.allclose(cos, 1.0, rtol=0, atol=1e-14)
+
+
 def test_solver_matches_dense():
     p = small_problem(60, nev=6, nex=4, deg=10, tol=1e-10)
     lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, p.deg, p.tol, p.w0_raw, p.lanczos_raw)
@@ -431,7 +463,7 @@ def test_solver_per_vector_degrees():
 
 
 def test_solver_backup_rr_every_iteration():
-    # the back-up quotient of Section 6 in every iteration still converges to
+    # the back-up quotient of Section 5.3 in every iteration still converges to
     # the dense eigenvalues (no quadratic convergence, so more iterations)
     p = small_problem(40, nev=4, nex=4)
     rng = np.random.default_rng(0)
@@ -512,9 +544,92 @@ def test_next_degrees_is_the_smallest_sufficient_degree():
         assert d == min(max(want, dmin), dmax), (l, r, d, want)
 
 
+def _all_eigenpairs(p):
+    """Every eigenpair of H from the dense definite solver: the positive
+    half and its K-conj partners (Thm 3.1: H K conj(v) = -lambda K conj(v))."""
+    lam, V = dense.dense_ph_eig(p.A, p.B)
+    return np.concatenate([lam, -lam]), np.concatenate([V, ham.apply_k_conj(V)], axis=1), lam
+
+
+@pytest.mark.parametrize("m,J,seed", [(8, 3, 0), (8, 5, 1), (10, 4, 2)])
+def test_lanczos_estimates_full_dimension_weighted_start(m, J, seed):
+    # A start v0 = sum_i c_i v_i over all 2m eigenvectors carries, in the
+    # S H inner product, the Gauss weight |c_i|^2 lambda_i v_i^H S v_i on
+    # eigenvalue lambda_i (the eigenvectors are S H-orthogonal, eq. 3.5;
+    # lambda_i v_i^H S v_i > 0 for both signs since S H is positive definite).
+    # The c_i are chosen for weight 1 on every eigenvalue except 2 on the
+    # J-th positive one and m on -lambda_1.  A run of n = 2m steps spans the
+    # whole space, so its Ritz values are the spectrum and its weights are
+    # these, and Section 4.1 then fixes all three estimates: mu_1 the
+    # smallest |lambda|, mu_n the largest, and mu_nevex the positive
+    # eigenvalue where the weight accumulated over the positive axis alone
+    # (total m + 1) first reaches nevex / m; with nevex = J that is lambda_J
+    # (J - 1 < J (m + 1) / m <= J + 1).  Weights of the negative axis, from
+    # the wrong row of the eigenvectors of T, or a shifted quantile all
+    # land elsewhere.
+    p = small_problem(m, seed=seed)
+    alll, allv, lam = _all_eigenpairs(p)
+    sn = np.real(np.einsum("ij,ij->j", allv.conj(), ham.apply_s(allv)))
+    w = np.ones(2 * m)
+    w[J - 1] = 2.0
+    w[m] = float(m)                                  # the partner -lambda_1
+    phase = np.exp(2j * np.pi * np.random.default_rng(seed + 7).random(2 * m))
+    v0 = allv @ (np.sqrt(w / (alll * sn)) * phase)
+    mu1, mu_nevex, mu_n = lanczos.spectral_estimates(p.A, p.B, v0[:, None], 2 * m, J)
+    assert abs(mu1 - lam[0]) <= 1e-10 * lam[0]
+    assert abs(mu_nevex - lam[J - 1]) <= 1e-10 * lam[J - 1]
+    assert abs(mu_n - lam[-1]) <= 1e-10 * lam[-1]
+
+
+@pytest.mark.parametrize("m,J,seed", [(8, 3, 0), (10, 4, 1)])
+def test_lanczos_estimates_start_without_lambda1(m, J, seed):
+    # the same construction with no component on lambda_1 (weight 1
+    # elsewhere): 2m - 1 steps span the invariant subspace of the other
+    # eigenvalues, so mu_1 = min |theta| comes from -lambda_1 alone, and the
+    # positive-axis quantile nevex / m of the m - 1 equal weights lands on
+    # lambda_(J+1) (J - 1 < J (m - 1) / m <= J)
+    p = small_problem(m, seed=seed)
+    alll, allv, lam = _all_eigenpairs(p)
+    sn = np.real(np.einsum("ij,ij->j", allv.conj(), ham.apply_s(allv)))
+    w = np.ones(2 * m)
+    w[0] = 0.0
+    phase = np.exp(2j * np.pi * np.random.default_rng(seed + 9).random(2 * m))
+    v0 = allv @ (np.sqrt(w / (alll * sn)) * phase)
+    mu1, mu_nevex, mu_n = lanczos.spectral_estimates(p.A, p.B, v0[:, None], 2 * m - 1, J)
+    assert abs(mu1 - lam[0]) <= 1e-10 * lam[0]
+    assert abs(mu_nevex - lam[J]) <= 1e-10 * lam[J]
+    assert abs(mu_n - lam[-1]) <= 1e-10 * lam[-1]
+
+
+@pytest.mark.parametrize("steps,seed", [(4, 0), (5, 1), (6, 2)])
+def test_lanczos_upper_estimate_is_ritz_value_plus_residual(steps, seed):
+    # mu_n = max |theta| plus the S H-norm of the residual of that Ritz
+    # pair.  Computed here without the recurrence: Rayleigh-Ritz in the S H
+    # inner product on the Krylov space span{v, H v, ..., H^(s-1) v}, with
+    # an S H-orthonormal basis from the Cholesky factor of its Gram matrix.
+    # H is self-adjoint in that inner product, so an eigenvalue of H lies
+    # within the residual of the Ritz value (Krylov-Weinberger bound).
+    p = small_problem(8, seed=seed)
+    H = ham.assemble_h(p.A, p.B)
+    SH = ham.assemble_sh(p.A, p.B)
+    v = complex_normal(np.random.default_rng(seed + 11), (16,))
+    Kr = np.stack([np.linalg.matrix_power(H, j) @ v for j in range(steps)], axis=1)
+    L = np.linalg.cholesky(Kr.conj().T @ SH @ Kr)
+    U = scipy.linalg.solve_triangular(L.conj(), Kr.T, lower=True).T      # U = Kr L^-H
+    Tr = U.conj().T @ SH @ H @ U
+    th, Y = np.linalg.eigh(0.5 * (Tr + Tr.conj().T))
+    i = int(np.argmax(np.abs(th)))
+    x = U @ Y[:, i]
+    r = H @ x - th[i] * x
+    delta = math.sqrt(np.real(np.vdot(r, SH @ r)))
+    _, mu_nevex, mu_n = lanczos.spectral_estimates(p.A, p.B, v[:, None], steps, 2)
+    assert abs(mu_n - (abs(th[i]) + delta)) <= 1e-9 * mu_n
+    alll, _, _ = _all_eigenpairs(p)
+    assert np.min(np.abs(alll - th[i])) <= delta * (1 + 1e-9)
+
+
 def test_lanczos_estimates_bounds():
-    # the estimates built on the recurrence are heuristics (parity of the
-    # choices unpinned): only bounded
+    # on a short run (26 steps, n = 160) the estimates are only bounded
     p = small_problem(80)
     lam, _ = dense.dense_ph_eig(p.A, p.B)
     mu1, mu_nevex, mu_n = lanczos.spectral_estimates(
