@@ -82,7 +82,6 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.chase_ph_mfma_probe.argtypes = [i32, i32, pd]
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if fn.restype is C.c_int or name not in ("chase_ph_default_params", "chase_ph_last_error"):
-            if name not in ("chase_ph_default_params", "chase_ph_last_error"):
-                fn.restype = C.c_int
+        if name not in ("chase_ph_default_params", "chase_ph_last_error"):
+            fn.restype = C.c_int
     return lib

@@ -32,6 +32,7 @@ struct chase_ph_s {
   c64* A32 = nullptr;
   c64* B32 = nullptr;
   int64_t ld32 = 0;
+  bool shadow_ready = false;
   // filter work buffers (n x nevex)
   c128* F1 = nullptr;
   c128* FT = nullptr;
@@ -148,7 +149,11 @@ Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alp
   return zgemm(g, split ? h->ws : nullptr, split ? h->ws_bytes : 0, h->st);
 }
 
-Err ensure_shadow(chase_ph_t h) {
+// c64 copies of A and B and the mixed path's work buffers.  alloc_shadow
+// only allocates; ensure_shadow also converts A and B the first time a
+// stage call needs them; the solver converts them again inside every timed
+// solve (refresh_shadow), so a solve's time includes the conversion.
+Err alloc_shadow(chase_ph_t h) {
   if (h->A32) return ok();
   h->ld32 = (h->m + 63) / 64 * 64;
   CHASE_TRY(dalloc(h, &h->A32, (size_t)h->ld32 * h->m));
@@ -161,7 +166,19 @@ Err ensure_shadow(chase_ph_t h) {
   CHASE_TRY(dalloc(h, &h->S32, (size_t)h->n * h->nevex));
   CHASE_TRY(dalloc(h, &h->R32, (size_t)h->n * h->nevex));
   CHASE_TRY(dalloc(h, &h->dpw, (size_t)h->nevex));
-  return make_shadow(h->A, h->B, h->ld, h->p.a_conj, h->A32, h->B32, h->ld32, h->m, h->st);
+  return ok();
+}
+
+Err refresh_shadow(chase_ph_t h) {
+  CHASE_TRY(alloc_shadow(h));
+  CHASE_TRY(make_shadow(h->A, h->B, h->ld, h->p.a_conj, h->A32, h->B32, h->ld32, h->m, h->st));
+  h->shadow_ready = true;
+  return ok();
+}
+
+Err ensure_shadow(chase_ph_t h) {
+  if (h->shadow_ready) return ok();
+  return refresh_shadow(h);
 }
 
 constexpr size_t PROF_MAX = 65536;
@@ -485,7 +502,7 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
   return ok();
 }
 
-// Back-up Rayleigh quotient of Section 6 on Q and T = H Q; see
+// Back-up Rayleigh quotient of Section 5.3 on Q and T = H Q; see
 // chase_ph_oblique_rr_backup.  Buffers: P and then G in G, Q^H T in Tk,
 // N and then N - D in Nb, D in dres, Schur vectors in Ev, eigenvectors of T
 // in Li (transposed work copy in L3), eigenvectors of G in Ys.
@@ -513,7 +530,7 @@ Err rr_backup(chase_ph_t h, int k, const c128* Q, int64_t ldq, const c128* T, in
 }
 
 // Alg. 2 (inverse Rayleigh quotient); see chase_ph_oblique_rr.
-// backup: -1 never uses the back-up quotient of Section 6 (a singular
+// backup: -1 never uses the back-up quotient of Section 5.3 (a singular
 // Q^H S Q is reported), 0 uses it when Alg. 2 resolves fewer than k/2
 // positive values, 1 always (*used_backup reports which ran).
 // kreal_q: every column of Q is K-real, so T = H Q takes half the products.
@@ -762,7 +779,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       !(mu_n > mu_nevex))
     return fail(CHASE_PH_ERR_NOT_DEFINITE, "Lanczos spectral estimates invalid (SH not positive definite?)");
   const bool mixed = p.precision == CHASE_PH_MIXED;
-  if (mixed) CHASE_TRY(ensure_shadow(h));
+  if (mixed) CHASE_TRY(refresh_shadow(h));
 
   int locked = 0;
   int lq = 0;  // locked pairs whose basis columns are in Xs[:, 0 : 2 lq]
@@ -918,15 +935,17 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       lam_locked.push_back(ritz[i]);
       res_locked.push_back(res[i]);
     }
-    if (verbose) {
-      std::fprintf(stderr, "[chase_ph] it=%d locked=%d kw=%d prec=%s n_fp64=%d nlock=%d ritz[0]=%.12g res[0]=%.3e res[kw-1]=%.3e mu_nevex=%.6g shifted=%d\n",
-                   it, locked, kw, g0 == kw ? "fp64" : (g1 ? "corr" : "fp32"), g0, nlock, ritz[0], res[0], res[kw - 1],
-                   ritz[kw - 1], used);
-    }
-    locked += nlock;
     // largest non-converged positive Ritz value; the interval only narrows (Section 4.1)
     const double lmax = *std::max_element(ritz.begin(), ritz.begin() + kw);
     if (lmax > 0) mu_nevex = std::min(mu_nevex, lmax);
+    if (verbose) {
+      std::fprintf(stderr,
+                   "[chase_ph] it=%d locked=%d kw=%d prec=%s n_fp64=%d nlock=%d ritz[0]=%.12g ritz[kw-1]=%.8g "
+                   "res[0]=%.3e res[nev-1]=%.3e res[kw-1]=%.3e mu_nevex=%.8g shifted=%d\n",
+                   it, locked, kw, g0 == kw ? "fp64" : (g1 ? "corr" : "fp32"), g0, nlock, ritz[0], ritz[kw - 1],
+                   res[0], res[std::min(nev - locked, kw) - 1], res[kw - 1], mu_nevex, used);
+    }
+    locked += nlock;
     inf.iterations = it + 1;
     if (locked >= nev) {
       *converged = true;
@@ -1012,34 +1031,17 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   return ok();
 }
 
+// Eigenvalue adjoint (a9): g and the weights gt live in the handle's
+// workspace; the two m x m outputs come from one launch (adjoint.hip).
 Err backward_impl(chase_ph_t h, int nev, const c128* V, int64_t ldv, const double* g, c128* GA, c128* GB, int64_t ldg) {
-  const int64_t m = h->m;
-  c128 *P = nullptr, *P2 = nullptr, *Pg = nullptr;
-  double* dg = nullptr;
-  const size_t sz = (size_t)m * 2 * nev;
-  CHASE_HIP(hipMalloc(&P, sz * sizeof(c128)));
-  CHASE_HIP(hipMalloc(&P2, sz * sizeof(c128)));
-  CHASE_HIP(hipMalloc(&Pg, sz * sizeof(c128)));
-  CHASE_HIP(hipMalloc(&dg, nev * sizeof(double)));
-  Err e = ok();
-  do {
-    if (hipMemcpyAsync(dg, g, nev * sizeof(double), hipMemcpyHostToDevice, h->st) != hipSuccess) {
-      e = fail(CHASE_PH_ERR_HIP, "backward: upload g");
-      break;
-    }
-    e = adjoint_operands(V, ldv, m, nev, dg, P, P2, Pg, m, h->st);
-    if (e) break;
-    e = gemm(h, 0, 1, m, m, 2 * nev, {1, 0}, Pg, m, P, m, {0, 0}, GA, ldg, -1, false);   // G_A = Pg P^H
-    if (e) break;
-    e = gemm(h, 0, 1, m, m, 2 * nev, {1, 0}, Pg, m, P2, m, {0, 0}, GB, ldg, -1, false);  // G_B = Pg P2^H
-    if (e) break;
-    if (hipStreamSynchronize(h->st) != hipSuccess) e = fail(CHASE_PH_ERR_HIP, "backward: sync");
-  } while (0);
-  (void)hipFree(P);
-  (void)hipFree(P2);
-  (void)hipFree(Pg);
-  (void)hipFree(dg);
-  return e;
+  if ((size_t)2 * nev * sizeof(double) > h->ws_bytes)
+    return fail(CHASE_PH_ERR_ARG, "eigval_backward: nev exceeds the handle's workspace");
+  double* dg = reinterpret_cast<double*>(h->ws);
+  double* dgt = dg + nev;
+  CHASE_HIP(hipMemcpyAsync(dg, g, nev * sizeof(double), hipMemcpyHostToDevice, h->st));
+  CHASE_TRY(adjoint_contract(V, ldv, h->m, nev, dg, dgt, GA, GB, ldg, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  return ok();
 }
 
 Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_t ld, void* stream, chase_ph_t h) {
@@ -1123,7 +1125,7 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   h->dws.gemm_ws_bytes = h->ws_bytes;
   h->hhw.gemm_ws = h->ws;
   h->hhw.gemm_ws_bytes = h->ws_bytes;
-  if (p->precision == CHASE_PH_MIXED) CHASE_TRY(ensure_shadow(h));
+  if (p->precision == CHASE_PH_MIXED) CHASE_TRY(alloc_shadow(h));
   return ok();
 }
 

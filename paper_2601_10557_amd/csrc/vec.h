@@ -34,8 +34,11 @@ Err lanczos_residual(const c128* w, const c128* v, const c128* vp, c128* r, int6
                      const double* alpha, const double* beta_prev, hipStream_t s);
 Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, int64_t ld, int64_t n, int nv,
                     const double* bsq, bool shift_prev, hipStream_t s);
-Err adjoint_operands(const c128* V, int64_t ldv, int64_t m, int nev, const double* dg, c128* P, c128* P2, c128* Pg,
-                     int64_t ldp, hipStream_t s);
+// Eigenvalue adjoint (adjoint.hip): dgt[j] = dg[j] / (x_j^H x_j - y_j^H y_j),
+// G_A = sum_j dgt_j (x_j x_j^H + conj(y_j) y_j^T),
+// G_B = sum_j dgt_j (x_j y_j^H + conj(y_j) x_j^T), both m x m (ldg).
+Err adjoint_contract(const c128* V, int64_t ldv, int64_t m, int nev, const double* dg, double* dgt, c128* GA,
+                     c128* GB, int64_t ldg, hipStream_t s);
 Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s);
 Err add_diag(c128* G, int64_t ld, int k, double v, hipStream_t s);
 Err gather_columns(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t n, int k, const int* dperm,

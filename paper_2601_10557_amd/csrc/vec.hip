@@ -4,8 +4,7 @@
 // recombination before the Rayleigh-Ritz quotient, c128 <-> c64 conversion
 // of the filter block, the fused
 // residual / normalisation of the half back-transform (Section 4.5),
-// S-inner products of the Lanczos estimates (Section 4.1) and the operand
-// build of the eigenvalue adjoint.
+// and the S-inner products of the Lanczos estimates (Section 4.1).
 #include <algorithm>
 
 #include "common.h"
@@ -147,30 +146,6 @@ __global__ void lanczos_next_kernel(c128* vp, c128* v, c128* w, const c128* r, c
 
 // Adjoint operands from V (n x nev) and g: P = [x_i, conj(y_i)],
 // P2 = [y_i, conj(x_i)], Pg = P * diag(gt, gt), gt_i = g_i / (|x_i|^2 - |y_i|^2).
-__global__ __launch_bounds__(256) void adjoint_prep_kernel(const c128* V, int64_t ldv, int64_t m, int nev,
-                                                           const double* g, c128* P, c128* P2, c128* Pg, int64_t ldp) {
-  __shared__ double red[256];
-  const int j = blockIdx.x;
-  const c128* v = V + (int64_t)j * ldv;
-  double s = 0;
-  for (int64_t i = threadIdx.x; i < 2 * m; i += 256) {
-    const double p = v[i].re * v[i].re + v[i].im * v[i].im;
-    s += i < m ? p : -p;
-  }
-  const double d = block_sum(s, red);
-  const double gt = g[j] / d;
-  for (int64_t i = threadIdx.x; i < m; i += 256) {
-    const c128 x = v[i], y = v[m + i];
-    const c128 yb{y.re, -y.im}, xb{x.re, -x.im};
-    P[(int64_t)j * ldp + i] = x;
-    P[(int64_t)(nev + j) * ldp + i] = yb;
-    P2[(int64_t)j * ldp + i] = y;
-    P2[(int64_t)(nev + j) * ldp + i] = xb;
-    Pg[(int64_t)j * ldp + i] = c128{gt * x.re, gt * x.im};
-    Pg[(int64_t)(nev + j) * ldp + i] = c128{gt * yb.re, gt * yb.im};
-  }
-}
-
 __global__ void trace_kernel(const c128* G, int64_t ld, int k, double* out) {
   __shared__ double red[256];
   double s = 0;
@@ -410,13 +385,6 @@ Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, in
                     const double* bsq, bool shift_prev, hipStream_t s) {
   hipLaunchKernelGGL(lanczos_next_kernel, dim3(grid_for(n * nv)), dim3(256), 0, s, vp, v, w, r, z, ld, n, nv, bsq,
                      shift_prev ? 1 : 0);
-  CHASE_LAUNCH_CHECK();
-  return ok();
-}
-
-Err adjoint_operands(const c128* V, int64_t ldv, int64_t m, int nev, const double* dg, c128* P, c128* P2, c128* Pg,
-                     int64_t ldp, hipStream_t s) {
-  hipLaunchKernelGGL(adjoint_prep_kernel, dim3(nev), dim3(256), 0, s, V, ldv, m, nev, dg, P, P2, Pg, ldp);
   CHASE_LAUNCH_CHECK();
   return ok();
 }
