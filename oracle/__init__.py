@@ -16,12 +16,15 @@ It shares no code with the HIP path; the only shared module is ``synth``
 Modules
 -------
 hamiltonian   H from its blocks (eq. 1.1), S, K, apply_h by definition
-dense         dense structure-preserving eigensolver (proof of Thm 3.2)
+dense         dense structure-preserving eigensolver (proof of Thm 3.2); the
+              general eigensolver reference for an indefinite S H
 chebyshev     scaled three-term Chebyshev recurrence on H^2 (eq. 4.1)
 qr            CholeskyQR2 with a shifted-CholeskyQR3 fallback (Section 2)
-rayleigh_ritz oblique Rayleigh-Ritz via the inverse Rayleigh quotient (Alg. 2)
+rayleigh_ritz oblique Rayleigh-Ritz via the inverse Rayleigh quotient (Alg. 2),
+              the back-up quotient and the general quotient of eq. 4.7
 residuals     half back-transform and residual norms (Section 4.5)
-lanczos       S-inner-product Lanczos spectral estimates (Section 4.1)
+lanczos       S-inner-product Lanczos spectral estimates (Section 4.1); Euclidean
+              Lanczos on S H for an indefinite S H
 solver        the pseudo-hermitian ChASE outer loop (Alg. 3)
 adjoint       first-order eigenvalue adjoint dL/dA, dL/dB (from Thm 3.2)
 """

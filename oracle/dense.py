@@ -11,7 +11,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
-from .hamiltonian import assemble_sh
+from .hamiltonian import assemble_h, assemble_sh
 
 
 def dense_ph_eig(A: np.ndarray, B: np.ndarray):
@@ -44,3 +44,31 @@ def smallest_positive(A: np.ndarray, B: np.ndarray, nev: int):
     (the solver's output contract, Alg. 3 Input/Output)."""
     lam, V = dense_ph_eig(A, B)
     return lam[:nev], V[:, :nev]
+
+
+def general_eig(A: np.ndarray, B: np.ndarray):
+    """All n eigenpairs of H from the general (non-hermitian) dense
+    eigensolver (LAPACK zgeev through numpy), with no use of S H: the
+    reference for an indefinite S H (Section 5.3, last paragraph: the
+    non-hermitian quotient does not need S H to be definite).  Returns
+    ``(w, V)``: complex eigenvalues and unit-2-norm eigenvectors."""
+    w, V = np.linalg.eig(assemble_h(A, B))
+    V = V / np.linalg.norm(V, axis=0)[None, :]
+    return w, V
+
+
+def smallest_positive_real(A: np.ndarray, B: np.ndarray, nev: int, imag_tol: float = 1e-9):
+    """The nev smallest positive real eigenvalues of H (ascending) and unit
+    right eigenvectors, for any S H.  Reading (the paper does not treat the
+    indefinite case beyond naming it): an eigenvalue counts as real when
+    |Im lambda| <= imag_tol * max |lambda|; complex eigenvalues are not
+    wanted (their Ritz approximations keep a residual of at least |Im lambda|
+    and are never locked).  Returns ``(lam, V, n_complex)`` with n_complex
+    the number of eigenvalues of H that are not real."""
+    w, V = general_eig(A, B)
+    real = np.abs(w.imag) <= imag_tol * np.max(np.abs(w))
+    pos = real & (w.real > 0)
+    lam = w.real[pos]
+    V = V[:, pos]
+    order = np.argsort(lam)
+    return lam[order][:nev], V[:, order][:, :nev], int(np.sum(~real))

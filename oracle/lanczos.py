@@ -99,3 +99,75 @@ def spectral_estimates(A, B, starts, steps, nevex):
         mu_nevex = float(above[0]) if len(above) else 0.5 * (mu1 + mu_n)
     mu_nevex = min(mu_nevex, 0.99 * mu_n)
     return mu1, mu_nevex, mu_n
+
+
+# ---------------------------------------------------------------------------
+# Indefinite S H.  The S H inner product above is then not an inner product
+# (r^H S H r can be negative) and the recurrence breaks down.  Reading (the
+# paper names the indefinite case for the non-hermitian quotient only): the
+# estimates come from Lanczos on the Hermitian S H in the Euclidean inner
+# product.  Its eigenvalues theta give the singular values |theta| of H
+# (H^H H = (S H)^2, S unitary), so that
+#   mu_n = max |theta| + residual bound  >=  ||H||_2  >=  |lambda| for every eigenvalue,
+#   mu_1 = min |theta|, and
+#   mu_nevex = the |theta| at which the Gauss weight accumulated on the folded
+#              axis reaches nevex / m (the 2 nevex eigenvalues +-lambda_1..nevex
+#              of the n are a fraction nevex / m of the spectrum).
+# For B = 0 the |theta| are exactly the |lambda| (S H = diag(A, conj(A)),
+# H = diag(A, -conj(A))); with coupling they differ, and only the number of
+# outer iterations depends on them.
+
+
+def lanczos_run_euclid(A, B, v0, steps):
+    """Hermitian Lanczos on S H, Euclidean inner product, one product with H
+    (and a sign flip of the lower half) per step; returns (alpha, beta)."""
+    v = np.asarray(v0, dtype=np.complex128)
+    v = v / np.linalg.norm(v)
+    v_prev = np.zeros_like(v)
+    beta_prev = 0.0
+    alpha = np.zeros(steps)
+    beta = np.zeros(steps)
+    m = v.shape[0] // 2
+    for j in range(steps):
+        w = apply_h(A, B, v)
+        w[m:] *= -1.0                                   # S H v
+        a = float(np.real(np.vdot(v, w)))
+        r = w - a * v - beta_prev * v_prev
+        b = float(np.linalg.norm(r))
+        alpha[j], beta[j] = a, b
+        if b == 0.0:
+            return alpha[: j + 1], beta[: j + 1]
+        v_prev, v, beta_prev = v, r / b, b
+    return alpha, beta
+
+
+def spectral_estimates_indefinite(A, B, starts, steps, nevex):
+    """(mu_1, mu_nevex, mu_n) for an indefinite S H from len(starts[0])
+    Euclidean Lanczos runs on S H (see the reading above)."""
+    m = A.shape[0]
+    absth, weights = [], []
+    mu1 = np.inf
+    mu_n = 0.0
+    nruns = starts.shape[1]
+    for i in range(nruns):
+        a, b = lanczos_run_euclid(A, B, starts[:, i], steps)
+        T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+        th, Y = np.linalg.eigh(T)
+        tau = np.abs(Y[0, :]) ** 2
+        mu1 = min(mu1, float(np.min(np.abs(th))))
+        imax = int(np.argmax(np.abs(th)))
+        mu_n = max(mu_n, float(abs(th[imax]) + abs(b[-1] * Y[-1, imax])))
+        absth.append(np.abs(th))
+        weights.append(tau / nruns)
+    th = np.concatenate(absth)
+    tau = np.concatenate(weights)
+    order = np.argsort(th)
+    th, tau = th[order], tau[order]
+    cum = np.cumsum(tau) / np.sum(tau)
+    idx = min(int(np.searchsorted(cum, nevex / m)), len(th) - 1)
+    mu_nevex = float(th[idx])
+    if mu_nevex <= mu1:
+        above = th[th > mu1 * (1.0 + 1e-8)]
+        mu_nevex = float(above[0]) if len(above) else 0.5 * (mu1 + mu_n)
+    mu_nevex = min(mu_nevex, 0.99 * mu_n)
+    return mu1, mu_nevex, mu_n

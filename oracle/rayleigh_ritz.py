@@ -106,16 +106,61 @@ def oblique_rr_backup(A, B, Q, return_all: bool = False):
     with ``return_all`` also the complex eigenvalues and all eigenvectors.
     """
     Q = np.asarray(Q, dtype=np.complex128)
-    k = Q.shape[1]
     T = apply_h(A, B, Q)
     G, _ = backup_quotient(Q, T)
     w, Y = np.linalg.eig(G)
+    lam_pos, Z_pos = select_positive_half(w, Y)
+    if return_all:
+        return lam_pos, Z_pos, T, w, Y
+    return lam_pos, Z_pos, T
+
+
+# Relative size of the smallest diagonal entry of the R factor of Q^H S Q
+# (QR with a non-negative real diagonal) below which Q^H S Q counts as
+# numerically singular in the general quotient (then the back-up quotient
+# runs).
+GENERAL_SINGULAR_REL = 1e3 * np.finfo(float).eps / 2
+
+
+def qsq_singular(N) -> bool:
+    """Q^H S Q numerically singular: min |R_ii| <= GENERAL_SINGULAR_REL max |R_ii|
+    for N = Q_N R (Householder QR)."""
+    r = np.abs(np.diag(np.linalg.qr(N, mode="r")))
+    return bool(r.min() <= GENERAL_SINGULAR_REL * r.max())
+
+
+def select_positive_half(w, Y):
+    """The k/2 eigenvalues with the smallest positive real parts, ascending,
+    then (if fewer than k/2 are positive) the largest non-positive ones,
+    descending; returns (real parts, matching columns of Y)."""
+    k = len(w)
     order = np.argsort(w.real, kind="stable")
     p = int(np.sum(w.real <= 0))
     npos = min(k // 2, k - p)
     sel = np.concatenate([order[p:p + npos], order[p - (k // 2 - npos):p][::-1]])
-    lam_pos = w[sel].real
-    Z_pos = Y[:, sel]
+    return w[sel].real, Y[:, sel]
+
+
+def oblique_rr_general(A, B, Q, return_all: bool = False):
+    """Oblique Rayleigh-Ritz with the dual basis of eq. 4.6 for any S H: the
+    quotient of eq. 4.7, ``G = (Q^H S Q)^{-1} Q^H S H Q``, solved by a
+    general (non-hermitian) dense eigensolver.  Nothing here factors
+    Q^H S H Q, so S H need not be definite (Section 5.3, last paragraph:
+    a non-hermitian quotient extends the method to an indefinite S H); only
+    Q^H S Q must be invertible (``qsq_singular`` is False).  The eigenvalues
+    of G are the Ritz values, its eigenvectors the coefficients of the right
+    Ritz vectors ``Q z``; real parts are kept and the positive half is
+    selected as in ``oblique_rr_backup``.
+
+    Returns ``(lam_pos, Z_pos, T)`` as ``oblique_rr``; with ``return_all``
+    also the complex eigenvalues and all eigenvectors of G."""
+    Q = np.asarray(Q, dtype=np.complex128)
+    T = apply_h(A, B, Q)
+    N = Q.conj().T @ apply_s(Q)                          # Q^H S Q
+    P = Q.conj().T @ apply_s(T)                          # Q^H S H Q
+    G = np.linalg.solve(N, P)                            # eq. 4.7
+    w, Y = np.linalg.eig(G)
+    lam_pos, Z_pos = select_positive_half(w, Y)
     if return_all:
         return lam_pos, Z_pos, T, w, Y
     return lam_pos, Z_pos, T

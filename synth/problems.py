@@ -103,12 +103,45 @@ def _clustered(rng, m):
     return d[rng.permutation(m)]
 
 
+def _bands(bands):
+    """Eigenvalues of A from a list of (count fraction, lo, hi) bands: exact
+    counts round(fraction m) (the last band takes the rest) drawn uniformly
+    in [lo, hi], then a random permutation.  Bands with hi < 0 give A
+    negative eigenvalues, so that S H is indefinite."""
+    def draw(rng, m):
+        parts, used = [], 0
+        for i, (frac, lo, hi) in enumerate(bands):
+            cnt = m - used if i == len(bands) - 1 else int(round(frac * m))
+            parts.append(rng.uniform(lo, hi, size=cnt))
+            used += cnt
+        d = np.concatenate(parts)
+        return d[rng.permutation(m)]
+    return draw
+
+
+# An indefinite S H with a real spectrum: eigenvalues of A in bands of both
+# signs, separated by gaps larger than twice ||B||_2 = 0.05 min |d|, so that
+# no two eigenvalues of H of opposite S-sign meet and leave the real axis.
+# The smallest positive eigenvalues of H come from the negative band
+# [-1.3, -1.0] (eigenvectors mostly in the lower half, v^H S v < 0) and the
+# positive band [1.5, 2.0] (v^H S v > 0).
+INDEFINITE_BANDS = [(0.10, -1.3, -1.0), (0.20, 1.5, 2.0), (0.10, -2.6, -2.2), (0.60, 2.8, 6.0)]
+
+
+def indefinite_problem(m: int, nev: int, nex: int, deg: int = 20, tol: float = 1e-10, seed: int = 0,
+                       coupling: float = 0.05, bands=None) -> "Problem":
+    """A pseudo-hermitian problem whose S H is indefinite (A has eigenvalues
+    of both signs) but whose eigenvalues are real (see INDEFINITE_BANDS)."""
+    return make_problem(m, _bands(bands or INDEFINITE_BANDS), coupling, nev, nex, deg, tol, seed=seed,
+                        name=f"indefinite-m{m}")
+
+
 def make_problem(m: int, d_draw: Callable, coupling: float, nev: int, nex: int,
                  deg: int, tol: float, seed: int = 0, name: str = "custom",
                  deg_min: Optional[int] = None, deg_max: Optional[int] = None,
                  lanczos_vecs: int = 4) -> Problem:
     """Draw one problem.  ``d_draw(rng, m)`` returns the eigenvalues of ``A``;
-    ``coupling`` is c in ``||B||_2 = c * min(d)``."""
+    ``coupling`` is c in ``||B||_2 = c * min |d|``."""
     rng = np.random.default_rng(seed)
     d = np.asarray(d_draw(rng, m), dtype=np.float64)
     q = _haar_unitary(rng, m)
@@ -118,7 +151,7 @@ def make_problem(m: int, d_draw: Callable, coupling: float, nev: int, nex: int,
     g = complex_normal(rng, (m, m))
     b = 0.5 * (g + g.T)
     del g
-    b *= coupling * float(d.min()) / _spectral_norm(b)
+    b *= coupling * float(np.abs(d).min()) / _spectral_norm(b)
     b = 0.5 * (b + b.T)
     nevex = nev + nex
     w0 = complex_normal(rng, (2 * m, nevex))

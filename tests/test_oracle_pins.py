@@ -759,3 +759,215 @@ def test_kreal_qr_rank_deficient_keeps_pm_pairs():
     ev = np.sort(ev.real)
     assert np.sum(ev > 0) == 4
     assert np.max(np.abs(ev + ev[::-1])) < 1e-9 * np.max(np.abs(ev))
+
+
+# ------------------------------------------------ indefinite S H (Section 5.3)
+# The variant for an indefinite S H: dense reference from the general
+# eigensolver, Lanczos on S H in the Euclidean inner product for the
+# estimates, the quotient of eq. 4.7 solved by a general eigensolver.
+def _indefinite_small(m=8, seed=0, coupling=0.05):
+    from synth import indefinite_problem
+    return indefinite_problem(m, 2, 2, seed=seed, coupling=coupling)
+
+
+def test_indefinite_generator_is_indefinite_with_real_spectrum():
+    from synth import indefinite_problem
+    p = indefinite_problem(120, 16, 10)
+    assert np.linalg.eigvalsh(ham.assemble_sh(p.A, p.B))[0] < -0.5      # S H indefinite
+    w = np.linalg.eigvals(ham.assemble_h(p.A, p.B))
+    assert np.max(np.abs(w.imag)) <= 1e-12 * np.max(np.abs(w))
+    lam, V, nc = dense.smallest_positive_real(p.A, p.B, p.nev)
+    sn = np.real(np.einsum("ij,ij->j", V.conj(), ham.apply_s(V)))
+    assert nc == 0 and np.any(sn < 0) and np.any(sn > 0)                 # both S-signs wanted
+    with pytest.raises(np.linalg.LinAlgError):
+        dense.dense_ph_eig(p.A, p.B)                                     # Thm 3.2's reduction needs S H > 0
+
+
+def test_general_eig_b_zero_indefinite():
+    # B = 0: H = diag(A, -conj(A)), so the positive eigenvalues are the
+    # positive d (vectors [x; 0], S-sign +1) and -d for the negative d
+    # (vectors [0; conj(x)], S-sign -1)
+    p = _indefinite_small(12)
+    lam, V, nc = dense.smallest_positive_real(p.A, np.zeros_like(p.B), 12)
+    assert nc == 0
+    assert np.allclose(lam, np.sort(np.abs(p.d)), rtol=1e-12, atol=0)
+    sn = np.real(np.einsum("ij,ij->j", V.conj(), ham.apply_s(V)))
+    d_of = np.sort(np.abs(p.d))
+    sign_ref = np.array([1.0 if np.any(np.isclose(p.d, x)) else -1.0 for x in d_of])
+    assert np.allclose(sn, sign_ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [4, 8])
+def test_general_eig_vs_mpmath_bruteforce_indefinite(m):
+    p = _indefinite_small(m, seed=3, coupling=0.3)
+    lam, _, nc = dense.smallest_positive_real(p.A, p.B, m)
+    mpmath.mp.dps = 50
+    H = ham.assemble_h(p.A, p.B)
+    Hm = mpmath.matrix([[mpmath.mpc(complex(H[i, j])) for j in range(2 * m)] for i in range(2 * m)])
+    ev = mpmath.eig(Hm, left=False, right=False)
+    real_pos = sorted(float(mpmath.re(e)) for e in ev
+                      if abs(mpmath.im(e)) < 1e-30 and mpmath.re(e) > 0)
+    assert nc == sum(1 for e in ev if abs(mpmath.im(e)) >= 1e-30)
+    assert np.allclose(np.array(real_pos[:len(lam)]), lam, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("m,seed", [(4, 2), (6, 1)])
+def test_general_eig_vs_mpmath_with_complex_eigenvalues(m, seed):
+    # strong coupling (||B||_2 = 2 min d) puts eigenvalues of H off the real
+    # axis: only the real positive ones are returned, the others counted
+    p = make_problem(m, lambda rng, mm: rng.uniform(1.0, 2.0, mm), 2.0, 2, 2, 4, 1e-8, seed=seed)
+    lam, V, nc = dense.smallest_positive_real(p.A, p.B, 2 * m)
+    mpmath.mp.dps = 50
+    H = ham.assemble_h(p.A, p.B)
+    Hm = mpmath.matrix([[mpmath.mpc(complex(H[i, j])) for j in range(2 * m)] for i in range(2 * m)])
+    ev = mpmath.eig(Hm, left=False, right=False)
+    cplx = [e for e in ev if abs(mpmath.im(e)) > 1e-20]
+    real_pos = sorted(float(mpmath.re(e)) for e in ev if abs(mpmath.im(e)) <= 1e-20 and mpmath.re(e) > 0)
+    assert len(cplx) > 0 and nc == len(cplx)
+    assert len(lam) == len(real_pos)
+    assert np.allclose(lam, np.array(real_pos), rtol=1e-12, atol=0)
+    assert np.max(np.linalg.norm(H @ V - V * lam[None, :], axis=0)) < 1e-12 * np.max(np.abs(lam))
+
+
+def test_general_eig_matches_structured_dense_in_definite_case():
+    p = small_problem(30, seed=2)
+    lam, _ = dense.smallest_positive(p.A, p.B, 10)
+    lam_g, V, nc = dense.smallest_positive_real(p.A, p.B, 10)
+    assert nc == 0
+    assert np.allclose(lam_g, lam, rtol=1e-12, atol=0)
+    H = ham.assemble_h(p.A, p.B)
+    assert np.max(np.linalg.norm(H @ V - V * lam_g[None, :], axis=0)) < 1e-12 * np.max(np.abs(lam_g))
+
+
+@pytest.mark.parametrize("steps", [3, 5, 6])
+def test_euclid_lanczos_gauss_quadrature_moments(steps):
+    # Hermitian Lanczos on S H: nodes and weights of T reproduce the
+    # moments v^H (S H)^j v / v^H v for j < 2 s and miss j = 2 s
+    p = _indefinite_small(6, seed=1)
+    SH = ham.assemble_sh(p.A, p.B)
+    v = complex_normal(np.random.default_rng(3), (12,))
+    a, b = lanczos.lanczos_run_euclid(p.A, p.B, v, steps)
+    T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+    th, Y = np.linalg.eigh(T)
+    tau = np.abs(Y[0]) ** 2
+    mom = [np.real(np.vdot(v, np.linalg.matrix_power(SH, j) @ v)) / np.real(np.vdot(v, v))
+           for j in range(2 * steps + 1)]
+    for j in range(2 * steps):
+        assert abs(np.sum(tau * th ** j) - mom[j]) <= 1e-11 * max(1.0, abs(mom[j]))
+    assert abs(np.sum(tau * th ** (2 * steps)) - mom[2 * steps]) > 1e-8 * abs(mom[2 * steps])
+
+
+@pytest.mark.parametrize("m,nevex,seed", [(8, 3, 0), (8, 2, 1), (10, 4, 2)])
+def test_indefinite_estimates_full_dimension_weighted_start(m, nevex, seed):
+    # Start v0 = sum_i c_i u_i over the 2m unit eigenvectors u_i of the
+    # Hermitian S H: its Gauss weights are |c_i|^2.  Weight 1 on every
+    # eigenvalue except 2 on the one of rank 2 nevex in |theta|.  A run of
+    # n steps spans the space, so mu_1 = min |theta|, mu_n = max |theta|
+    # (= ||H||_2), and the weight accumulated over |theta| (total n + 1)
+    # first reaches nevex / m = 2 nevex / n at rank 2 nevex
+    # ((2 nevex - 1)/(n + 1) < 2 nevex / n <= (2 nevex + 1)/(n + 1)).
+    p = _indefinite_small(m, seed=seed, coupling=0.3)
+    th, U = np.linalg.eigh(ham.assemble_sh(p.A, p.B))
+    assert th[0] < 0
+    rank = np.argsort(np.abs(th))
+    w = np.ones(2 * m)
+    w[rank[2 * nevex - 1]] = 2.0
+    phase = np.exp(2j * np.pi * np.random.default_rng(seed + 5).random(2 * m))
+    v0 = U @ (np.sqrt(w) * phase)
+    mu1, mu_nevex, mu_n = lanczos.spectral_estimates_indefinite(p.A, p.B, v0[:, None], 2 * m, nevex)
+    a = np.sort(np.abs(th))
+    assert abs(mu1 - a[0]) <= 1e-10 * a[-1]
+    assert abs(mu_nevex - a[2 * nevex - 1]) <= 1e-10 * a[-1]
+    assert abs(mu_n - a[-1]) <= 1e-10 * a[-1]
+    assert abs(a[-1] - np.linalg.norm(ham.assemble_h(p.A, p.B), 2)) <= 1e-12 * a[-1]
+
+
+def test_indefinite_estimates_bound_the_spectrum():
+    from synth import indefinite_problem
+    p = indefinite_problem(80, 8, 6)
+    starts = solver.init_block(p.lanczos_raw, 1e-3)
+    mu1, mu_nevex, mu_n = lanczos.spectral_estimates_indefinite(p.A, p.B, starts, 26, p.nevex)
+    w = np.linalg.eigvals(ham.assemble_h(p.A, p.B))
+    assert mu_n >= np.max(np.abs(w))
+    assert 0 < mu1 < mu_nevex < mu_n
+
+
+def test_general_rr_matches_alg2_in_definite_case():
+    # independent routes to the same Ritz values: Cholesky + Hermitian
+    # eigensolver of the inverse quotient (Alg. 2) and LU + general
+    # eigensolver of eq. 4.7
+    p = small_problem(40, seed=4)
+    X = complex_normal(np.random.default_rng(5), (80, 6))
+    Q, _ = np.linalg.qr(np.concatenate([X, ham.apply_k_conj(X)], axis=1))
+    lam1, Z1, _ = rayleigh_ritz.oblique_rr(p.A, p.B, Q)
+    lam2, Z2, _ = rayleigh_ritz.oblique_rr_general(p.A, p.B, Q)
+    assert np.allclose(lam2, lam1, rtol=1e-11, atol=0)
+    for j in range(6):
+        v1, v2 = Q @ Z1[:, j], Q @ Z2[:, j]
+        assert abs(abs(np.vdot(v1, v2)) - np.linalg.norm(v1) * np.linalg.norm(v2)) < 1e-9 * np.linalg.norm(v1) * np.linalg.norm(v2)
+
+
+def _kinv_basis(X):
+    Q, _ = np.linalg.qr(np.concatenate([X, ham.apply_k_conj(X)], axis=1))
+    return Q
+
+
+def test_general_rr_indefinite_exact_invariant_subspace():
+    from synth import indefinite_problem
+    p = indefinite_problem(40, 6, 2)
+    lam, V, _ = dense.smallest_positive_real(p.A, p.B, 6)
+    Q = _kinv_basis(V)
+    lam_r, _, _, w, _ = rayleigh_ritz.oblique_rr_general(p.A, p.B, Q, return_all=True)
+    assert np.allclose(lam_r, lam, rtol=1e-11, atol=0)
+    assert np.allclose(np.sort(w.real), np.sort(np.concatenate([lam, -lam])), rtol=1e-11, atol=0)
+
+
+def test_general_rr_indefinite_petrov_galerkin_and_pm_pairs():
+    # dual basis S Q (Q^H S Q)^{-1} (eq. 4.6): every Ritz pair leaves a
+    # residual S-orthogonal to range(Q); on a K-invariant Q the Ritz values
+    # come in +/- pairs (Thm 4.5)
+    from synth import indefinite_problem
+    p = indefinite_problem(40, 6, 2, coupling=0.3)
+    X = complex_normal(np.random.default_rng(6), (80, 5))
+    Q = _kinv_basis(X)
+    lam, Z, T, w, Y = rayleigh_ritz.oblique_rr_general(p.A, p.B, Q, return_all=True)
+    for j in range(10):
+        v = Q @ Y[:, j]
+        r = ham.apply_h(p.A, p.B, v[:, None])[:, 0] - w[j] * v
+        assert np.linalg.norm(Q.conj().T @ ham.apply_s(r[:, None])) <= 1e-10 * np.linalg.norm(v) * abs(w[j])
+    ws = np.sort_complex(w)
+    assert np.allclose(np.sort_complex(-w), ws, atol=1e-10 * np.max(np.abs(w)))
+
+
+def test_qsq_singular_detects_zero_block():
+    A, B, Q, _ = decoupled_singular_case()
+    assert rayleigh_ritz.qsq_singular(Q.conj().T @ ham.apply_s(Q))
+    Qr = _kinv_basis(complex_normal(np.random.default_rng(1), (20, 3)))
+    assert not rayleigh_ritz.qsq_singular(Qr.conj().T @ ham.apply_s(Qr))
+
+
+@pytest.mark.parametrize("m,nev,nex,seed", [(120, 16, 10, 0), (200, 30, 14, 2)])
+def test_solver_indefinite_matches_general_dense(m, nev, nex, seed):
+    from synth import indefinite_problem
+    p = indefinite_problem(m, nev, nex, tol=1e-10, seed=seed)
+    lam_ref, _, _ = dense.smallest_positive_real(p.A, p.B, nev)
+    lam, V, info = solver.solve(p.A, p.B, nev, nex, p.deg, p.tol, p.w0_raw, p.lanczos_raw,
+                                max_iter=30, definite=False)
+    assert info["converged"]
+    assert np.allclose(lam, lam_ref, rtol=1e-10, atol=0)
+    assert np.all(residuals.residual_norms(p.A, p.B, V, lam) <= p.tol)
+    sn = np.real(np.einsum("ij,ij->j", V.conj(), ham.apply_s(V)))
+    assert np.any(sn < 0) and np.any(sn > 0)
+
+
+def test_solver_indefinite_skips_spurious_pairs():
+    # With the back-up quotient in every iteration, this problem produces a
+    # spurious Ritz value (residual of the order of |lambda~|) ahead of the
+    # wanted pairs; it must not hold a place in the locking prefix.
+    from synth import indefinite_problem
+    p = indefinite_problem(120, 16, 10, tol=1e-10, seed=0)
+    lam_ref, _, _ = dense.smallest_positive_real(p.A, p.B, p.nev)
+    lam, V, info = solver.solve(p.A, p.B, p.nev, p.nex, p.deg, p.tol, p.w0_raw, p.lanczos_raw,
+                                max_iter=30, definite=False, rr_backup=1)
+    assert info["converged"] and info["iterations"] <= 10
+    assert np.allclose(lam, lam_ref, rtol=1e-10, atol=0)
