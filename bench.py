@@ -13,9 +13,12 @@ path.  ``value`` is the filter throughput of the mixed solves (filter flops
 time).  The JSON line also carries both time-to-solution figures, their
 ratio, the eigenvalue agreement, the roofline of the dominant kernel (the
 c64 block-structured GEMM that applies H, timed launch by launch with HIP
-events inside the timed steps) and the CPU oracle timed on a bounded sample.
+events inside the timed steps) and the CPU oracle timed on bounded samples:
+its filter on 8 columns, and its dense time to solution (the plain
+definition the solver reaches) timed on an m = 2000 draw of the same
+generator and scaled by n^3 (``--cpu-full`` times it on the workload).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--cpu-full]
 """
 from __future__ import annotations
 
@@ -60,12 +63,27 @@ def measured_traffic():
     return d
 
 
-def cpu_baseline(p, seconds_target=12.0):
-    """The oracle's Chebyshev filter on a bounded sample of the workload:
-    degree-d filter on k sample columns of the same H, on the host cores,
-    repeated to about seconds_target seconds."""
+def cpu_model():
+    """CPU model name of the host that drives the GPU (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def blas_threads():
     from threadpoolctl import threadpool_info
-    from oracle import chebyshev, dense  # noqa: F401  (oracle: baseline leg only)
+    return int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+
+
+def cpu_filter_sample(p, seconds_target=12.0):
+    """The oracle's Chebyshev filter on a bounded sample of the workload:
+    degree-1 filter on 8 sample columns of the same H, repeated to about
+    seconds_target seconds.  Returns (TFLOP/s, seconds per call, reps)."""
+    from oracle import chebyshev  # oracle: baseline leg only
     from oracle.solver import init_block
     k, deg = 8, 1
     W = init_block(p.w0_raw[:, :k], 1e-3)
@@ -73,19 +91,53 @@ def cpu_baseline(p, seconds_target=12.0):
     t = time.perf_counter()
     chebyshev.chebyshev_filter(p.A, p.B, W, deg, mu1, mu_nevex, mu_n)
     dt = time.perf_counter() - t
-    # scale the sample up to ~seconds_target if it was very short
-    reps = max(1, int(seconds_target / max(dt, 1e-3)) - 1)
-    reps = min(reps, 40)
+    reps = min(max(1, int(seconds_target / max(dt, 1e-3)) - 1), 40)
     t = time.perf_counter()
     for _ in range(reps):
         chebyshev.chebyshev_filter(p.A, p.B, W, deg, mu1, mu_nevex, mu_n)
-    dt = (time.perf_counter() - t) / reps if reps else dt
-    flops = 16.0 * p.n * p.n * k * deg
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle chebyshev_filter, degree {deg} in H^2 on {k} of {p.nevex} columns of the "
-                      f"m={p.m} workload ({reps} timed repetitions, {dt:.2f} s each)",
-            "seconds_per_call": dt}
+    dt = (time.perf_counter() - t) / reps
+    return 16.0 * p.n * p.n * k * deg / dt / 1e12, dt, reps, k
+
+
+def cpu_dense_time(config, m, seed=0):
+    """Seconds of the dense oracle (all positive eigenpairs of H, the plain
+    definition the solver converges to) on an m-row draw of the workload's
+    generator (same spectrum and coupling)."""
+    from synth import config_problem
+    from oracle import dense  # oracle: baseline leg only
+    q = config_problem(config, seed=seed, m=m, nev=min(200, m // 4), nex=min(60, m // 8))
+    t = time.perf_counter()
+    dense.dense_ph_eig(q.A, q.B)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(p, config, full=False, dense_m=2000):
+    """The oracle on the host cores, beside the GPU figures of the same run.
+
+    * value: the oracle's Chebyshev filter (TFLOP/s) on 8 of the nevex
+      columns of the workload (degree 1, repeated to ~12 s).
+    * time_to_solution_s: the dense oracle's time on the workload.  By
+      default it is timed on a dense_m-row draw of the same generator
+      (about 20 s on 16 cores) and scaled by (m / dense_m)^3, the cost
+      order of the Cholesky, congruence and Hermitian eigensolve; with
+      full=True the dense oracle runs on the workload itself."""
+    tf, dt, reps, k = cpu_filter_sample(p)
+    out = {"value": tf, "unit": "TFLOP/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": f"oracle chebyshev_filter, degree 1 in H^2 on {k} of {p.nevex} columns of the "
+                     f"m={p.m} workload ({reps} timed repetitions, {dt:.2f} s each)",
+           "cpu_model": cpu_model(), "os_cpus": os.cpu_count()}
+    if full:
+        t = cpu_dense_time(config, p.m)
+        out["time_to_solution_s"] = {"dense_oracle": round(t, 2), "measured_at_m": p.m, "extrapolated": False,
+                                     "what": "oracle.dense.dense_ph_eig on the workload itself"}
+    else:
+        t = cpu_dense_time(config, dense_m)
+        scale = (p.m / dense_m) ** 3
+        out["time_to_solution_s"] = {"dense_oracle": round(t * scale, 2), "measured_at_m": dense_m,
+                                     "measured_s": round(t, 2), "extrapolated": True,
+                                     "what": f"oracle.dense.dense_ph_eig on an m={dense_m} draw of the same "
+                                             f"generator, scaled by (m/{dense_m})^3"}
+    return out
 
 
 def main():
@@ -95,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the dense oracle on the workload itself instead of a scaled draw")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a device copy of this many MiB before the timed region (counter calibration)")
     args = ap.parse_args()
@@ -201,8 +255,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        cpu = cpu_baseline(p)
-        cpu.pop("seconds_per_call", None)
+        cpu = cpu_baseline(p, args.config, full=args.cpu_full)
+        ratio = cpu["time_to_solution_s"]["dense_oracle"] / tts_m
+        cpu["time_to_solution_s"]["over_gpu_mixed"] = round(ratio, 1)
 
     value = filt_flops_m / filt_time_m / 1e12
     out = {
@@ -238,7 +293,7 @@ def main():
         "eig_err_vs_dense_oracle": err_vs_dense,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},
+        "host": {"cpu": cpu_model(), "os_cpus": os.cpu_count()},
     }
     print(json.dumps(out), flush=True)
 

@@ -695,13 +695,8 @@ Err launch_dma(const ApplyHArgs<float>& a, const Plan& p, void* ws, hipStream_t 
   return ok();
 }
 
-// CHASE_PH_PLAN_LOG=1 prints the plan of every launch to stderr (tuning aid).
-void plan_log(const char* prec, int64_t m, int k, const Plan& p) {
-  static const bool on = std::getenv("CHASE_PH_PLAN_LOG") != nullptr;
-  if (on) std::fprintf(stderr, "[chase_ph plan] %s m=%lld k=%d cfg=%d splits=%d\n", prec, (long long)m, k, p.cfg, p.splits);
-}
-
-// CHASE_PH_APPLY_PLAN="cfg,splits" forces a tile shape and K split (tuning aid).
+// CHASE_PH_APPLY_PLAN="cfg,splits" forces a tile shape and K split, so that
+// every tile shape and split can be checked for parity on one problem.
 template <int NCFG>
 void plan_override(Plan& p, int64_t m, int64_t n2, const int (&bm)[NCFG], const int (&bn)[NCFG],
                    const int (&bk)[NCFG], size_t elem, size_t ws_bytes) {
@@ -743,7 +738,6 @@ static Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes,
   Plan p = make_plan<9>(a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, 0.01, sizeof(c64), wsb, dma_ok ? 9 : 7);
   plan_override<9>(p, a.m, 2 * (int64_t)a.k, bm, bn, bk, sizeof(c64), wsb);
   if (p.cfg >= 7 && !dma_ok) p.cfg = p.cfg == 8 ? 1 : 0;
-  plan_log("c64", a.m, a.k, p);
   switch (p.cfg) {
     case 0:
       return vb2 ? launch_cfg<TF32, 256, 64, 16, 4, 1, 2>(a, p, ws, s)
@@ -775,7 +769,6 @@ static Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes
   const int64_t n2 = (a.kreal ? 1 : 2) * (int64_t)a.k;
   Plan p = make_plan<4>(a.m, n2, bm, bn, bk, eff, occ, 0.02, sizeof(c128), wsb);
   plan_override<4>(p, a.m, n2, bm, bn, bk, sizeof(c128), wsb);
-  plan_log("c128", a.m, a.k, p);
   switch (p.cfg) {
     case 0: return launch_cfg<TF64, 128, 64, 16, 2, 2, 1>(a, p, ws, s);
     case 1: return launch_cfg<TF64, 256, 32, 16, 4, 1, 1>(a, p, ws, s);
@@ -800,13 +793,9 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
   // c64: split when the last r = k mod 32 columns (2r of the 2k) fit in at
   // most three 16-column fragments of the narrow tile (measured inside the
   // filter on m = 4000, r = 17 and 20 gain 3-5% over the whole launch, r = 22
-  // and 26 lose 7-20%); c128: r <= 16.  Tuning aids: CHASE_PH_SPLIT_MAX=r
-  // overrides the bound, CHASE_PH_NO_SPLIT=1 launches every call whole.
-  const char* nosplit = std::getenv("CHASE_PH_NO_SPLIT");
-  const char* smax = std::getenv("CHASE_PH_SPLIT_MAX");
-  const int rmax = smax ? std::atoi(smax) : (sizeof(R) == 4 ? 20 : 16);
-  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < 2 * gran || a.kreal ||
-      (nosplit && nosplit[0] == '1'))
+  // and 26 lose 7-20%); c128: r <= 16.
+  constexpr int rmax = sizeof(R) == 4 ? 20 : 16;
+  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < 2 * gran || a.kreal)
     return one(a, ws, ws_bytes, s);
   using C = typename ApplyHArgs<R>::C;
   ApplyHArgs<R> am = a, ar = a;
