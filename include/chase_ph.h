@@ -16,7 +16,9 @@
  * - Pointers named d* are device pointers; h* are host pointers.
  * - Device buffers passed in are borrowed: the caller owns them.  A and B
  *   given to chase_ph_create must stay valid and unmodified until
- *   chase_ph_destroy.  All workspace is owned by the handle.
+ *   chase_ph_destroy.  All workspace is owned by the handle (the one
+ *   handle-free entry point, chase_ph_eigval_backward_noalloc, uses a fixed
+ *   device array of the library instead).
  * - Every call is ordered on the HIP stream given at create time.  Calls
  *   that return host values synchronise that stream before returning.
  * - Errors are reported by status code only; the library never aborts.
@@ -122,6 +124,9 @@ chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const 
 /* Free all handle-owned memory.  Accepts NULL. */
 chase_ph_status chase_ph_destroy(chase_ph_t h);
 
+/* Message of the last error on handle h; with h = NULL, that of the last
+ * failed handle-free call (chase_ph_eigval_backward_noalloc) on this host
+ * thread. */
 const char* chase_ph_last_error(chase_ph_t h);
 
 /* Y = H X for an n x k block (Section 1, eq. 1.1; the product behind every
@@ -241,6 +246,28 @@ chase_ph_status chase_ph_solve(chase_ph_t h, const void* dW0, int64_t ldw0, cons
 chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* dV,
                                          int64_t ldv, const double* hG, void* dGA,
                                          void* dGB, int64_t ldg);
+
+/* Largest nev accepted by chase_ph_eigval_backward_noalloc. */
+#define CHASE_PH_NOALLOC_MAX_NEV 16384
+
+/* The eigenvalue adjoint of chase_ph_eigval_backward without a handle and
+ * without any device allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same contraction, conventions and outputs, for H of
+ * block size m (dV: 2m x nev c128, ldv >= 2m; dGA, dGB: m x m c128,
+ * ldg >= m, overwritten; hG: host, nev).  Runs on the current device,
+ * ordered on hip_stream (NULL: the null stream; it must belong to the
+ * current device), and synchronises that stream before returning.
+ * The nev weights and the scaled weights gt live in a fixed array of
+ * 2 * CHASE_PH_NOALLOC_MAX_NEV doubles (256 KiB) that the library holds on
+ * every device it runs on until the process ends; nothing needs clearing
+ * between calls.  Calls that overlap on one device race on that array.
+ * Returns CHASE_PH_ERR_ARG for bad arguments or nev > CHASE_PH_NOALLOC_MAX_NEV,
+ * CHASE_PH_ERR_HIP if a HIP call or launch fails; chase_ph_last_error(NULL)
+ * then gives the message of the last failed call on this host thread. */
+chase_ph_status chase_ph_eigval_backward_noalloc(int64_t m, int32_t nev, const void* dV,
+                                                 int64_t ldv, const double* hG, void* dGA,
+                                                 void* dGB, int64_t ldg, void* hip_stream);
 
 /* Timing of the most recent chase_ph_apply_h / chase_ph_filter launch
  * sequence in milliseconds (HIP events on the handle's stream) and the

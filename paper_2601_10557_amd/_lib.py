@@ -49,7 +49,10 @@ EXPORTS = [
     "chase_ph_apply_h", "chase_ph_filter", "chase_ph_qr", "chase_ph_oblique_rr", "chase_ph_oblique_rr_backup",
     "chase_ph_residuals", "chase_ph_solve", "chase_ph_eigval_backward", "chase_ph_last_timing",
     "chase_ph_profile", "chase_ph_profile_read", "chase_ph_filter_refined", "chase_ph_mfma_probe",
+    "chase_ph_eigval_backward_noalloc",
 ]
+
+NOALLOC_MAX_NEV = 16384   # CHASE_PH_NOALLOC_MAX_NEV
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:
@@ -76,6 +79,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.chase_ph_residuals.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp, i64, pd, vp, i64, pd]
     lib.chase_ph_solve.argtypes = [vp, vp, i64, vp, i64, pd, vp, i64, pd, C.POINTER(Info)]
     lib.chase_ph_eigval_backward.argtypes = [vp, i32, vp, i64, pd, vp, vp, i64]
+    lib.chase_ph_eigval_backward_noalloc.argtypes = [i64, i32, vp, i64, pd, vp, vp, i64, vp]
     lib.chase_ph_last_timing.argtypes = [vp, pd, pi]
     lib.chase_ph_profile.argtypes = [vp, i32]
     lib.chase_ph_profile_read.argtypes = [vp, i32, pd, pd, pd, pi]

@@ -10,8 +10,18 @@
 // V, and, by the symmetry of both outputs, only tiles with I >= J are
 // computed: the tile (J, I) is written from the same registers
 // (conjugate transpose for G_A, transpose for G_B).
+#include <mutex>
+
 #include "common.h"
 #include "vec.h"
+
+// Fixed device memory of the allocation-free adjoint entry point
+// (chase_ph_eigval_backward_noalloc): the host weights g (first
+// CHASE_PH_NOALLOC_MAX_NEV doubles) and the scaled weights gt (the next
+// CHASE_PH_NOALLOC_MAX_NEV).  Each device holds its own copy at its own
+// address, resolved once per device with hipGetSymbolAddress; host code
+// never passes the array's name itself to a kernel or a copy.
+static __device__ __align__(256) double scratch[2 * CHASE_PH_NOALLOC_MAX_NEV];
 
 namespace chase {
 namespace {
@@ -191,4 +201,64 @@ Err adjoint_contract(const c128* V, int64_t ldv, int64_t m, int nev, const doubl
   return ok();
 }
 
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[kMaxDevices] = {};
+thread_local std::string noalloc_err;
+
+// Device address of this device's copy of the scratch array (resolved on the
+// first call on each device, with that device current).
+Err scratch_on_current_device(double** out) {
+  int dev = 0;
+  CHASE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CHASE_PH_ERR_ARG, "eigval_backward_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    CHASE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CHASE_PH_ERR_HIP, "eigval_backward_noalloc: no device address for the scratch array");
+    scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_ptr[dev];
+  return ok();
+}
+
+Err backward_noalloc(int64_t m, int nev, const c128* V, int64_t ldv, const double* hG, c128* GA, c128* GB,
+                     int64_t ldg, hipStream_t s) {
+  double* ws = nullptr;
+  CHASE_TRY(scratch_on_current_device(&ws));
+  double* dg = ws;
+  double* dgt = ws + CHASE_PH_NOALLOC_MAX_NEV;
+  CHASE_HIP(hipMemcpyAsync(dg, hG, (size_t)nev * sizeof(double), hipMemcpyHostToDevice, s));
+  CHASE_TRY(adjoint_contract(V, ldv, m, nev, dg, dgt, GA, GB, ldg, s));
+  CHASE_HIP(hipStreamSynchronize(s));
+  return ok();
+}
+
+}  // namespace
+
+const char* noalloc_last_error() { return noalloc_err.c_str(); }
+
 }  // namespace chase
+
+extern "C" chase_ph_status chase_ph_eigval_backward_noalloc(int64_t m, int32_t nev, const void* dV, int64_t ldv,
+                                                            const double* hG, void* dGA, void* dGB, int64_t ldg,
+                                                            void* hip_stream) {
+  using namespace chase;
+  Err e;
+  if (m <= 0 || nev <= 0 || !dV || !hG || !dGA || !dGB || ldv < 2 * m || ldg < m)
+    e = fail(CHASE_PH_ERR_ARG, "eigval_backward_noalloc: bad arguments");
+  else if (nev > CHASE_PH_NOALLOC_MAX_NEV)
+    e = fail(CHASE_PH_ERR_ARG, "eigval_backward_noalloc: nev = " + std::to_string(nev) +
+                                   " exceeds the fixed scratch of " + std::to_string(CHASE_PH_NOALLOC_MAX_NEV) +
+                                   " pairs");
+  else
+    e = backward_noalloc(m, nev, (const c128*)dV, ldv, hG, (c128*)dGA, (c128*)dGB, ldg, (hipStream_t)hip_stream);
+  if (e) {
+    noalloc_err = e.msg;
+    return e.st;
+  }
+  return CHASE_PH_OK;
+}

@@ -1186,7 +1186,7 @@ chase_ph_status chase_ph_destroy(chase_ph_t h) {
   return CHASE_PH_OK;
 }
 
-const char* chase_ph_last_error(chase_ph_t h) { return h ? h->err.c_str() : "null handle"; }
+const char* chase_ph_last_error(chase_ph_t h) { return h ? h->err.c_str() : chase::noalloc_last_error(); }
 
 #define CHECK_HANDLE(h)                                   \
   do {                                                    \

@@ -39,6 +39,9 @@ Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, in
 // G_B = sum_j dgt_j (x_j y_j^H + conj(y_j) x_j^T), both m x m (ldg).
 Err adjoint_contract(const c128* V, int64_t ldv, int64_t m, int nev, const double* dg, double* dgt, c128* GA,
                      c128* GB, int64_t ldg, hipStream_t s);
+// Message of the last failed chase_ph_eigval_backward_noalloc call on this
+// host thread (adjoint.hip).
+const char* noalloc_last_error();
 Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s);
 Err add_diag(c128* G, int64_t ld, int k, double v, hipStream_t s);
 Err gather_columns(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t n, int k, const int* dperm,

@@ -69,6 +69,24 @@ def mfma_probe(kind: int, iters: int = 10000) -> float:
     return out.value
 
 
+def eigval_backward_noalloc(V: torch.Tensor, g, GA: torch.Tensor, GB: torch.Tensor, stream=None) -> None:
+    """Eigenvalue adjoint into caller-allocated ``GA``, ``GB`` (m x m
+    column-major complex128) with no handle and no device allocation
+    (chase_ph_eigval_backward_noalloc); ``V`` is the 2m x nev block of unit
+    right eigenvectors on the current device, ``g`` the nev host weights."""
+    V = colmajor(V)
+    m, nev = V.shape[0] // 2, V.shape[1]
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    assert g.shape == (nev,) and GA.shape == (m, m) and GB.shape == (m, m)
+    assert _ld(GA) == _ld(GB), "GA and GB must share one leading dimension"
+    s = (stream or torch.cuda.current_stream(V.device)).cuda_stream
+    st = lib().chase_ph_eigval_backward_noalloc(
+        m, nev, _ptr(V), _ld(V), g.ctypes.data_as(C.POINTER(C.c_double)), _ptr(GA), _ptr(GB),
+        _ld(GA), C.c_void_p(s))
+    if st != _lib.OK:
+        raise ChasePHError(st, lib().chase_ph_last_error(None).decode())
+
+
 def default_params() -> _lib.Params:
     p = _lib.Params()
     lib().chase_ph_default_params(C.byref(p))
