@@ -15,7 +15,7 @@ ratio, the eigenvalue agreement, the roofline of the dominant kernel (the
 c64 block-structured GEMM that applies H, timed launch by launch with HIP
 events inside the timed steps) and the CPU oracle timed on bounded samples:
 its filter on 8 columns, and its dense time to solution (the plain
-definition the solver reaches) timed on an m = 2000 draw of the same
+definition the solver reaches) timed on an m = 3000 draw of the same
 generator and scaled by n^3 (``--cpu-full`` times it on the workload).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--cpu-full]
@@ -111,14 +111,14 @@ def cpu_dense_time(config, m, seed=0):
     return time.perf_counter() - t
 
 
-def cpu_baseline(p, config, full=False, dense_m=2000):
+def cpu_baseline(p, config, full=False, dense_m=3000):
     """The oracle on the host cores, beside the GPU figures of the same run.
 
     * value: the oracle's Chebyshev filter (TFLOP/s) on 8 of the nevex
       columns of the workload (degree 1, repeated to ~12 s).
     * time_to_solution_s: the dense oracle's time on the workload.  By
       default it is timed on a dense_m-row draw of the same generator
-      (about 20 s on 16 cores) and scaled by (m / dense_m)^3, the cost
+      (about 16 s on 16 cores) and scaled by (m / dense_m)^3, the cost
       order of the Cholesky, congruence and Hermitian eigensolve; with
       full=True the dense oracle runs on the workload itself."""
     tf, dt, reps, k = cpu_filter_sample(p)

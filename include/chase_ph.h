@@ -91,6 +91,12 @@ typedef struct {
   int32_t rr_backup;    /* 0: the non-hermitian back-up quotient of Section 5.3 only when   */
                         /* Alg. 2 resolves fewer than k/2 positive Ritz values (Q^H S Q     */
                         /* singular); 1: the back-up quotient in every iteration            */
+  int32_t definite;     /* 1 (default): S H positive definite, Alg. 2 and S H-inner-product */
+                        /* Lanczos.  0: S H may be indefinite (Section 5.3, last paragraph):*/
+                        /* Lanczos on S H in the Euclidean inner product, the quotient of   */
+                        /* eq. 4.7 by a general eigensolver (chase_ph_oblique_rr_general),  */
+                        /* the back-up quotient when Q^H S Q is singular; wanted are the    */
+                        /* nev smallest positive real eigenvalues                           */
 } chase_ph_params;
 
 typedef struct {
@@ -107,10 +113,11 @@ typedef struct {
   int32_t resid_history_len; /* capacity of resid_history in doubles (0 if NULL)           */
   int32_t householder_qr_used; /* times the Householder QR fallback was taken              */
   int32_t backup_rr_used;  /* iterations whose Rayleigh-Ritz used the back-up quotient      */
+  int32_t general_rr_used; /* iterations whose Rayleigh-Ritz used the general quotient      */
 } chase_ph_info;
 
 /* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos
- * steps x 4 runs, FP64, tol 1e-10, opt_deg 0. */
+ * steps x 4 runs, FP64, tol 1e-10, opt_deg 0, definite 1. */
 void chase_ph_default_params(chase_ph_params* p);
 
 /* Create a solver handle for H built from the m x m blocks at dA, dB
@@ -210,6 +217,20 @@ chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int
 chase_ph_status chase_ph_oblique_rr_backup(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq,
                                            double* hRitz, void* dZpos, int64_t ldz, void* dT,
                                            int64_t ldt);
+
+/* Rayleigh-Ritz for any S H, definite or not (Section 5.3, last paragraph:
+ * a non-hermitian quotient does not need S H to be definite), with the dual
+ * basis Q_L = S Q (Q^H S Q)^{-1} of eq. 4.6; same arguments and outputs as
+ * chase_ph_oblique_rr.  The quotient of eq. 4.7,
+ *   T = H Q;  P = Q^H S T;  Q^H S Q = Q_N R (Householder QR);
+ *   G = R^{-1} Q_N^H P;  G Y = Y W (general eigenproblem),
+ * never factors Q^H S H Q.  Real parts of the Ritz values are kept and the
+ * positive half is selected as in chase_ph_oblique_rr_backup.
+ * CHASE_PH_ERR_SINGULAR_QSQ if Q^H S Q is numerically singular
+ * (min |R_ii| <= 1e3 u max |R_ii|) or the QR iteration does not converge. */
+chase_ph_status chase_ph_oblique_rr_general(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq,
+                                            double* hRitz, void* dZpos, int64_t ldz, void* dT,
+                                            int64_t ldt);
 
 /* Half back-transform and residuals (Section 4.5): for the first kk
  * columns of dZpos, V = Q Z (normalised to unit 2-norm, written to dV,

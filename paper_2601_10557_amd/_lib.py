@@ -28,6 +28,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int32), ("tol", C.c_double), ("precision", C.c_int32),
         ("switch_tol", C.c_double), ("gamma", C.c_double), ("lanczos_steps", C.c_int32),
         ("lanczos_vecs", C.c_int32), ("a_conj", C.c_int32), ("rr_backup", C.c_int32),
+        ("definite", C.c_int32),
     ]
 
 
@@ -40,7 +41,7 @@ class Info(C.Structure):
         ("t_total", C.c_double), ("filter_flops", C.c_double), ("rr_flops", C.c_double),
         ("filter_flops_fp32", C.c_double), ("resid_history", C.POINTER(C.c_double)),
         ("resid_history_len", C.c_int32), ("householder_qr_used", C.c_int32),
-        ("backup_rr_used", C.c_int32),
+        ("backup_rr_used", C.c_int32), ("general_rr_used", C.c_int32),
     ]
 
 
@@ -49,7 +50,7 @@ EXPORTS = [
     "chase_ph_apply_h", "chase_ph_filter", "chase_ph_qr", "chase_ph_oblique_rr", "chase_ph_oblique_rr_backup",
     "chase_ph_residuals", "chase_ph_solve", "chase_ph_eigval_backward", "chase_ph_last_timing",
     "chase_ph_profile", "chase_ph_profile_read", "chase_ph_filter_refined", "chase_ph_mfma_probe",
-    "chase_ph_eigval_backward_noalloc",
+    "chase_ph_eigval_backward_noalloc", "chase_ph_oblique_rr_general",
 ]
 
 NOALLOC_MAX_NEV = 16384   # CHASE_PH_NOALLOC_MAX_NEV
@@ -76,6 +77,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.chase_ph_qr.argtypes = [vp, i32, vp, i64, vp, i64, pi]
     lib.chase_ph_oblique_rr.argtypes = [vp, i32, vp, i64, pd, vp, i64, vp, i64]
     lib.chase_ph_oblique_rr_backup.argtypes = [vp, i32, vp, i64, pd, vp, i64, vp, i64]
+    lib.chase_ph_oblique_rr_general.argtypes = [vp, i32, vp, i64, pd, vp, i64, vp, i64]
     lib.chase_ph_residuals.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp, i64, pd, vp, i64, pd]
     lib.chase_ph_solve.argtypes = [vp, vp, i64, vp, i64, pd, vp, i64, pd, C.POINTER(Info)]
     lib.chase_ph_eigval_backward.argtypes = [vp, i32, vp, i64, pd, vp, vp, i64]

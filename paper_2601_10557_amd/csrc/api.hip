@@ -98,6 +98,9 @@ struct chase_ph_s {
 namespace {
 
 constexpr double U_ROUND = 1.1102230246251565e-16;
+// Indefinite S H: a Ritz pair with residual above this fraction of
+// |lambda~| is spurious and holds no place in the locking prefix.
+constexpr double SPURIOUS_REL = 0.1;
 
 chase_ph_status finish(chase_ph_t h, const Err& e) {
   if (e) {
@@ -529,10 +532,60 @@ Err rr_backup(chase_ph_t h, int k, const c128* Q, int64_t ldq, const c128* T, in
   return ok();
 }
 
+// Oblique Rayleigh-Ritz with the dual basis of eq. 4.6 for any S H: the
+// quotient of eq. 4.7, G = (Q^H S Q)^{-1} Q^H S H Q, by a general
+// eigensolver (nothing factors Q^H S H Q, so S H may be indefinite; Section
+// 5.3, last paragraph).  Q^H S Q = Q_N R (Householder QR), G = R^{-1} Q_N^H P
+// with R^{-1} = ((R^H)^{-1})^H from the lower triangular inverse.  *singular
+// is set (and nothing else done) when min |R_ii| <= 1e3 u max |R_ii|.
+// T = H Q is given (n x k, ldt).
+Err rr_general(chase_ph_t h, int k, const c128* Q, int64_t ldq, const c128* T, int64_t ldt, double* ritz, c128* Zpos,
+               int64_t ldz, bool* singular) {
+  const int kp = pad64(k);
+  const int64_t m = h->m, n = h->n;
+  *singular = false;
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m));   // P = Q^H S H Q
+  CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, Q, ldq, {0, 0}, h->Nb, kp, m));  // N = Q^H S Q
+  CHASE_TRY(householder_qr(h->Nb, kp, k, k, h->L3, kp, h->hhw, h->st));            // N = Q_N R
+  std::vector<c128> rdiag(k);
+  CHASE_HIP(hipMemcpy2DAsync(rdiag.data(), sizeof(c128), h->L3, (kp + 1) * sizeof(c128), sizeof(c128), k,
+                             hipMemcpyDeviceToHost, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  double rmin = 1e300, rmax = 0;
+  for (const c128& z : rdiag) {
+    const double a = std::hypot(z.re, z.im);
+    rmin = std::min(rmin, a);
+    rmax = std::max(rmax, a);
+  }
+  if (!(rmin > 1e3 * U_ROUND * rmax)) {
+    *singular = true;
+    return ok();
+  }
+  CHASE_TRY(gemm(h, 1, 0, k, k, k, {1, 0}, h->Nb, kp, h->G, kp, {0, 0}, h->Tk, kp));  // C = Q_N^H P
+  CHASE_TRY(fill_padded(h->L1, kp, k, 0.0, 1.0, true, h->st));
+  CHASE_TRY(conj_transpose(h->L3, kp, h->L1, kp, k, h->st));                        // R^H (lower)
+  CHASE_TRY(tri_inverse_lower(h->L1, h->Li, kp, h->dws, h->st));                    // (R^H)^{-1}
+  CHASE_TRY(gemm(h, 1, 0, k, k, k, {1, 0}, h->Li, kp, h->Tk, kp, {0, 0}, h->G, kp, -1, false));  // G = R^{-1} C
+  int qs = 0;
+  CHASE_TRY(nonsym_eig(h->G, h->Ev, kp, k, h->Wev, h->L3, h->Li, h->gw, h->st, &qs));
+  if (qs != 0)
+    return fail(CHASE_PH_ERR_SINGULAR_QSQ, "general Rayleigh quotient: QR iteration did not converge for k = " +
+                                               std::to_string(k));
+  CHASE_TRY(gemm(h, 0, 0, k, k, k, {1, 0}, h->Ev, kp, h->Li, kp, {0, 0}, h->Ys, kp, -1, false));  // Z Y
+  CHASE_TRY(select_by_real_part(h->Wev, k, h->Ys, kp, h->dperm, h->dlam, Zpos, ldz, h->st));
+  if (ritz) {
+    CHASE_TRY(d2h_small(ritz, h->dlam, sizeof(double) * (k / 2), h->dws, h->st));
+  }
+  return ok();
+}
+
 // Alg. 2 (inverse Rayleigh quotient); see chase_ph_oblique_rr.
 // backup: -1 never uses the back-up quotient of Section 5.3 (a singular
 // Q^H S Q is reported), 0 uses it when Alg. 2 resolves fewer than k/2
-// positive values, 1 always (*used_backup reports which ran).
+// positive values, 1 always (*used_backup reports which ran); 2 runs the
+// general quotient of eq. 4.7 instead of Alg. 2 (indefinite S H) and the
+// back-up quotient when Q^H S Q is singular; 3 the general quotient only
+// (a singular Q^H S Q is reported).
 // kreal_q: every column of Q is K-real, so T = H Q takes half the products.
 // In a K-real basis the quotient G below is i times a real antisymmetric
 // matrix, whose zero diagonal slows the Jacobi sweeps down; the columns 2j
@@ -550,6 +603,14 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
   }
   if (used_backup) *used_backup = backup == 1;
   if (backup == 1) return rr_backup(h, k, Q, ldq, T, ldt, ritz, Zpos, ldz);
+  if (backup == 2 || backup == 3) {
+    bool singular = false;
+    CHASE_TRY(rr_general(h, k, Q, ldq, T, ldt, ritz, Zpos, ldz, &singular));
+    if (!singular) return ok();
+    if (backup == 3) return fail(CHASE_PH_ERR_SINGULAR_QSQ, "general Rayleigh quotient: Q^H S Q numerically singular");
+    if (used_backup) *used_backup = true;
+    return rr_backup(h, k, Q, ldq, T, ldt, ritz, Zpos, ldz);
+  }
   CHASE_TRY(fill_padded(h->G, kp, k, 0.0, 1.0, true, h->st));
   CHASE_TRY(gemm(h, 1, 0, k, k, n, {1, 0}, Q, ldq, T, ldt, {0, 0}, h->G, kp, m, true,
                  GEMM_LOWER_ONLY));  // M = Q^H S T (Hermitian; the Cholesky reads the lower triangle)
@@ -648,26 +709,44 @@ void tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, std
   }
 }
 
-// Spectral estimates mu_1, mu_nevex, mu_n (Section 4.1) from Lanczos runs in
-// the S H inner product, one product with H per step; start vectors are the
-// gamma-scaled caller draws.
+// Spectral estimates mu_1, mu_nevex, mu_n (Section 4.1) from Lanczos runs,
+// one product with H per step; start vectors are the gamma-scaled caller
+// draws.  Definite S H: Lanczos on H in the S H inner product,
+//   w = H v, alpha = w^H S w, r = w - alpha v - beta v_prev, z = H r,
+//   beta^2 = r^H S z, v <- r / beta, w <- z / beta;
+// mu_nevex is the quantile nevex / m of the density on the positive axis.
+// Indefinite S H (the S H inner product is then indefinite): Hermitian
+// Lanczos on S H in the Euclidean inner product, the same recurrence with
+// w = S H v, alpha = v^H w, z = S H r and beta^2 = r^H r; the |theta| are
+// the singular values of H, mu_nevex is their quantile nevex / m on the
+// folded axis.
 Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, double* mu_nevex, double* mu_n) {
   const int nv = h->p.lanczos_vecs, steps = h->p.lanczos_steps;
   const int64_t n = h->n, m = h->m;
+  const bool definite = h->p.definite != 0;
   double* alpha = h->dab;
   double* bsq = h->dab + (size_t)steps * nv;
   double* b0 = h->dab + (size_t)2 * steps * nv;
+  // Y = (S) H X for the indefinite recurrence's sign flip
+  auto op = [&](const c128* X, c128* Y) -> Err {
+    CHASE_TRY(apply64(h, nv, X, n, Y, n));
+    if (!definite) CHASE_TRY(scale_lower_half(Y, n, Y, n, m, nv, -1.0, h->st));
+    return ok();
+  };
+  auto dots = [&](const c128* X, const c128* Y, double* out) -> Err {
+    return definite ? s_dots(X, n, Y, n, m, nv, out, h->st) : plain_dots(X, n, Y, n, m, nv, out, h->st);
+  };
   CHASE_TRY(scale_lower_half(dLz, ldlz, h->lv, n, m, nv, h->p.gamma, h->st));
   CHASE_HIP(hipMemsetAsync(h->lvp, 0, sizeof(c128) * n * nv, h->st));
-  CHASE_TRY(apply64(h, nv, h->lv, n, h->lw, n));
-  CHASE_TRY(s_dots(h->lv, n, h->lw, n, m, nv, b0, h->st));
+  CHASE_TRY(op(h->lv, h->lw));
+  CHASE_TRY(dots(h->lv, definite ? h->lw : h->lv, b0));
   CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lv, h->lw, n, n, nv, b0, false, h->st));
   for (int j = 0; j < steps; ++j) {
-    CHASE_TRY(s_dots(h->lw, n, h->lw, n, m, nv, alpha + (size_t)j * nv, h->st));
+    CHASE_TRY(dots(definite ? h->lw : h->lv, h->lw, alpha + (size_t)j * nv));
     CHASE_TRY(lanczos_residual(h->lw, h->lv, h->lvp, h->lr, n, n, nv, alpha + (size_t)j * nv,
                                j ? bsq + (size_t)(j - 1) * nv : nullptr, h->st));
-    CHASE_TRY(apply64(h, nv, h->lr, n, h->lz, n));
-    CHASE_TRY(s_dots(h->lr, n, h->lz, n, m, nv, bsq + (size_t)j * nv, h->st));
+    CHASE_TRY(op(h->lr, h->lz));
+    CHASE_TRY(dots(h->lr, definite ? h->lz : h->lr, bsq + (size_t)j * nv));
     if (j + 1 < steps) CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lr, h->lz, n, n, nv, bsq + (size_t)j * nv, true, h->st));
   }
   std::vector<double> ha((size_t)steps * nv), hb((size_t)steps * nv);
@@ -690,8 +769,10 @@ Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, doubl
       if (std::fabs(th[i]) > std::fabs(th[imax])) imax = i;
     }
     mn = std::max(mn, std::fabs(th[imax]) + std::fabs(b[steps - 1] * l[imax]));
-    for (int i = 0; i < steps; ++i)
-      if (th[i] > 0) pos.push_back({th[i], f[i] * f[i] / nv});
+    for (int i = 0; i < steps; ++i) {
+      if (definite && th[i] > 0) pos.push_back({th[i], f[i] * f[i] / nv});
+      if (!definite) pos.push_back({std::fabs(th[i]), f[i] * f[i] / nv});
+    }
   }
   std::sort(pos.begin(), pos.end());
   double tot = 0;
@@ -779,6 +860,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       !(mu_n > mu_nevex))
     return fail(CHASE_PH_ERR_NOT_DEFINITE, "Lanczos spectral estimates invalid (SH not positive definite?)");
   const bool mixed = p.precision == CHASE_PH_MIXED;
+  const bool definite = p.definite != 0;
   if (mixed) CHASE_TRY(refresh_shadow(h));
 
   int locked = 0;
@@ -910,8 +992,10 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     const int kq = 2 * kw;
     CHASE_TRY(tm.start());
     bool used_backup = false;
-    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n, true, p.rr_backup ? 1 : 0, &used_backup));
+    const int rr_mode = p.rr_backup ? 1 : (definite ? 0 : 2);
+    CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n, true, rr_mode, &used_backup));
     inf.backup_rr_used += used_backup;
+    inf.general_rr_used += rr_mode == 2 && !used_backup;
     CHASE_TRY(tm.stop(&inf.t_rr));
     // half back-transform and residuals (Section 4.5)
     CHASE_TRY(tm.start());
@@ -925,15 +1009,35 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     }
     // locking: contiguous prefix of the wanted pairs with residual <= tol
     // (and a positive Ritz value: the back-up quotient may complete the
-    // positive half with non-positive values, which come last)
+    // positive half with non-positive values, which come last).  With an
+    // indefinite S H the Ritz values obey no min-max ordering and a
+    // spurious one (residual above SPURIOUS_REL |lambda~|) may sit ahead of
+    // converged pairs: such pairs hold no place in the prefix.
+    std::vector<int> cand, sel, rest;
+    for (int i = 0; i < kw; ++i)
+      if (definite || res[i] <= SPURIOUS_REL * std::fabs(ritz[i])) cand.push_back(i);
     int nlock = 0;
-    while (nlock < nev - locked && res[nlock] <= p.tol && ritz[nlock] > 0) ++nlock;
-    if (nlock > 0)
+    while (nlock < std::min(nev - locked, (int)cand.size()) && res[cand[nlock]] <= p.tol && ritz[cand[nlock]] > 0)
+      ++nlock;
+    sel.assign(cand.begin(), cand.begin() + nlock);
+    for (int i = 0, t = 0; i < kw; ++i) {
+      if (t < nlock && sel[t] == i) {
+        ++t;
+        continue;
+      }
+      rest.push_back(i);
+    }
+    const bool prefix = nlock == 0 || sel[nlock - 1] == nlock - 1;
+    if (nlock > 0 && prefix)
       CHASE_HIP(hipMemcpy2DAsync(h->Ylock + (int64_t)locked * n, n * sizeof(c128), h->Vt, n * sizeof(c128),
                                  n * sizeof(c128), nlock, hipMemcpyDeviceToDevice, h->st));
+    if (nlock > 0 && !prefix) {
+      CHASE_TRY(h2d(h, h->dperm, sel.data(), sizeof(int) * nlock));
+      CHASE_TRY(gather_columns(h->Vt, n, h->Ylock + (int64_t)locked * n, n, n, nlock, h->dperm, h->st));
+    }
     for (int i = 0; i < nlock; ++i) {
-      lam_locked.push_back(ritz[i]);
-      res_locked.push_back(res[i]);
+      lam_locked.push_back(ritz[sel[i]]);
+      res_locked.push_back(res[sel[i]]);
     }
     // largest non-converged positive Ritz value; the interval only narrows (Section 4.1)
     const double lmax = *std::max_element(ritz.begin(), ritz.begin() + kw);
@@ -956,7 +1060,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     std::vector<char> nmode(kn);
     std::vector<double> npr(kn);
     for (int j = 0; j < kn; ++j) {
-      const int i = nlock + j;
+      const int i = rest[j];
       const double r = res[i];
       char md = mode[i];
       if (mixed && md == 2 && !(p.switch_tol > 0 && r > p.switch_tol)) md = 1;
@@ -973,7 +1077,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
       const double c = 0.5 * (mu_n * mu_n + mu_nevex * mu_nevex);
       const double e = 0.5 * (mu_n * mu_n - mu_nevex * mu_nevex);
       for (int j = 0; j < kn; ++j) {
-        const double l = ritz[nlock + j], r = res[nlock + j];
+        const double l = ritz[rest[j]], r = res[rest[j]];
         const double t = std::fabs((l * l - c) / e);
         int d;
         if (t <= 1.0 + 1e-12 || r <= p.tol) {
@@ -995,9 +1099,9 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     g0 = 0;
     g1 = 0;
     for (int j = 0; j < kn; ++j) {
-      src[j] = nlock + perm[j];
+      src[j] = rest[perm[j]];
       degs[j] = nd[perm[j]];
-      lamcol[j] = ritz[nlock + perm[j]];
+      lamcol[j] = ritz[rest[perm[j]]];
       g0 += nmode[j] == 0;
       g1 += nmode[j] == 1;
     }
@@ -1019,13 +1123,23 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   inf.t_total = ms * 1e-3;
   inf.locked = locked;
   const int nout = std::min(locked, nev);
+  // ascending output (pairs locked out of order only in the indefinite case)
+  std::vector<int> order(nout);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam_locked[a] < lam_locked[b]; });
+  bool sorted = true;
   for (int i = 0; i < nout; ++i) {
-    evals[i] = lam_locked[i];
-    if (resid_out) resid_out[i] = res_locked[i];
+    evals[i] = lam_locked[order[i]];
+    if (resid_out) resid_out[i] = res_locked[order[i]];
+    sorted = sorted && order[i] == i;
   }
-  if (nout > 0)
+  if (nout > 0 && sorted)
     CHASE_HIP(hipMemcpy2DAsync(V, ldv * sizeof(c128), h->Ylock, n * sizeof(c128), n * sizeof(c128), nout,
                                hipMemcpyDeviceToDevice, h->st));
+  if (nout > 0 && !sorted) {
+    CHASE_TRY(h2d(h, h->dperm, order.data(), sizeof(int) * nout));
+    CHASE_TRY(gather_columns(h->Ylock, n, V, ldv, n, nout, h->dperm, h->st));
+  }
   CHASE_HIP(hipStreamSynchronize(h->st));
   if (info) *info = inf;
   return ok();
@@ -1148,6 +1262,7 @@ void chase_ph_default_params(chase_ph_params* p) {
   p->lanczos_steps = 26;
   p->lanczos_vecs = 4;
   p->a_conj = 0;
+  p->definite = 1;
 }
 
 chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const void* dB, int64_t ld, void* hip_stream,
@@ -1157,7 +1272,8 @@ chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const 
   if (!p || !dA || !dB || p->m <= 0 || ld < p->m || p->nev <= 0 || p->nex < 0 || p->nev + p->nex > p->m ||
       p->deg < 1 || p->max_iter < 1 || !(p->tol > 0) || p->lanczos_steps < 2 || p->lanczos_steps % 2 != 0 ||
       p->lanczos_vecs < 1 || (p->precision != CHASE_PH_FP64 && p->precision != CHASE_PH_MIXED) ||
-      (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)) || (p->rr_backup != 0 && p->rr_backup != 1))
+      (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)) || (p->rr_backup != 0 && p->rr_backup != 1) ||
+      (p->definite != 0 && p->definite != 1))
     return CHASE_PH_ERR_ARG;
   chase_ph_t h = new (std::nothrow) chase_ph_s;
   if (!h) return CHASE_PH_ERR_ALLOC;
@@ -1278,6 +1394,14 @@ chase_ph_status chase_ph_oblique_rr_backup(chase_ph_t h, int32_t k, const void* 
   if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
     return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr_backup: bad arguments"));
   return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt, false, 1));
+}
+
+chase_ph_status chase_ph_oblique_rr_general(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq, double* hRitz,
+                                            void* dZpos, int64_t ldz, void* dT, int64_t ldt) {
+  CHECK_HANDLE(h);
+  if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
+    return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr_general: bad arguments"));
+  return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt, false, 3));
 }
 
 chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const void* dQ, int64_t ldq, const void* dT,

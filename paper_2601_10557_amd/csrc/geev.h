@@ -20,6 +20,9 @@ struct GeevWs {
 Err nonsym_eig(c128* G, c128* Z, int64_t ld, int k, c128* w, c128* Yt, c128* Y, const GeevWs& ws, hipStream_t s,
                int* qr_status);
 
+// dst (k x k, ldd) = src^H (k x k, lds); dst must not alias src.
+Err conj_transpose(const c128* src, int64_t lds, c128* dst, int64_t ldd, int k, hipStream_t s);
+
 // Diagonal threshold of the back-up dual basis (Section 5.3 allows replacing
 // zero entries of diag(Q^H S Q)): |d_i| < BACKUP_DIAG_MIN is replaced by 1.
 constexpr double BACKUP_DIAG_MIN = 1e-8;

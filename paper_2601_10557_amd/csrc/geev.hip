@@ -388,6 +388,24 @@ __global__ void scale_rows_inv_kernel(c128* G, int64_t ld, int k, const double* 
 
 }  // namespace
 
+__global__ void conj_transpose_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int k) {
+  const int64_t total = (int64_t)k * k;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / k, i = t % k;  // dst(i, j) = conj(src(j, i))
+    const c128 z = src[i * lds + j];
+    dst[j * ldd + i] = c128{z.re, -z.im};
+  }
+}
+
+Err conj_transpose(const c128* src, int64_t lds, c128* dst, int64_t ldd, int k, hipStream_t s) {
+  if (k <= 0) return ok();
+  const int64_t total = (int64_t)k * k;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(conj_transpose_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, k);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
 Err backup_diag(c128* N, int64_t ld, int k, double dmin, double* d, hipStream_t s) {
   if (k <= 0) return ok();
   hipLaunchKernelGGL(backup_diag_kernel, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, N, ld, k, dmin, d);

@@ -29,6 +29,8 @@ Err scale_c64(const c64* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, 
 // W[:, j] = pw[j] W[:, j] + ce D[:, j]  (pw device, k values)
 Err combine_correction(c128* W, int64_t ldw, const c64* D, int64_t ldd, const double* dpw, double ce, int64_t n, int k,
                        hipStream_t s);
+// out[j] = Re(x_j^H y_j) over the 2m rows (Euclidean).
+Err plain_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s);
 Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s);
 Err lanczos_residual(const c128* w, const c128* v, const c128* vp, c128* r, int64_t ld, int64_t n, int nv,
                      const double* alpha, const double* beta_prev, hipStream_t s);

@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void resid_kernel(c128* V, int64_t ldv, const 
   if (threadIdx.x == 0) resid[j] = sqrt(rr2) * inv;
 }
 
-// out[j] = Re(x_j^H S y_j)
+// out[j] = Re(x_j^H diag(I, lsgn I) y_j): lsgn = -1 gives x^H S y, +1 the
+// Euclidean product
 __global__ __launch_bounds__(256) void sdot_kernel(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m,
-                                                   double* out) {
+                                                   double lsgn, double* out) {
   __shared__ double red[256];
   const int j = blockIdx.x;
   const c128* x = X + (int64_t)j * ldx;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void sdot_kernel(const c128* X, int64_t ldx, c
   double s = 0;
   for (int64_t i = threadIdx.x; i < 2 * m; i += 256) {
     const double p = x[i].re * y[i].re + x[i].im * y[i].im;
-    s += i < m ? p : -p;
+    s += i < m ? p : lsgn * p;
   }
   const double r = block_sum(s, red);
   if (threadIdx.x == 0) out[j] = r;
@@ -368,7 +369,13 @@ Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const doub
 }
 
 Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, m, out);
+  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, m, -1.0, out);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err plain_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, m, 1.0, out);
   CHASE_LAUNCH_CHECK();
   return ok();
 }

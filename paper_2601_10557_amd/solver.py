@@ -114,6 +114,7 @@ class SolveInfo:
     resid_history: Optional[np.ndarray] = None
     householder_qr_used: int = 0
     backup_rr_used: int = 0
+    general_rr_used: int = 0
 
 
 class PHSolver:
@@ -123,7 +124,7 @@ class PHSolver:
                  tol: float = 1e-10, max_iter: int = 25, precision: int = _lib.FP64,
                  opt_deg: bool = False, deg_min: int = 8, deg_max: int = 20,
                  switch_tol: float = 0.0, gamma: float = 1e-3, lanczos_steps: int = 26,
-                 lanczos_vecs: int = 4, rr_backup: bool = False):
+                 lanczos_vecs: int = 4, rr_backup: bool = False, definite: bool = True):
         if A.dtype != torch.complex128 or B.dtype != torch.complex128:
             raise TypeError("A and B must be complex128")
         if not A.is_cuda or not B.is_cuda:
@@ -144,6 +145,7 @@ class PHSolver:
         p.lanczos_steps, p.lanczos_vecs = lanczos_steps, lanczos_vecs
         p.a_conj = 1          # C-contiguous Hermitian A read column-major is conj(A)
         p.rr_backup = int(rr_backup)
+        p.definite = int(definite)
         self.params = p
         self.device = A.device
         self.stream = torch.cuda.current_stream(self.device)
@@ -260,6 +262,20 @@ class PHSolver:
         Z = empty_cm(k, k // 2, torch.complex128, Q.device)
         T = empty_cm(self.n, k, torch.complex128, Q.device)
         self._check(lib().chase_ph_oblique_rr_backup(
+            self._h, k, _ptr(Q), _ld(Q), ritz.ctypes.data_as(C.POINTER(C.c_double)),
+            _ptr(Z), _ld(Z), _ptr(T), _ld(T)))
+        return ritz, Z, T
+
+    def oblique_rr_general(self, Q: torch.Tensor):
+        """Quotient of eq. 4.7 by a general eigensolver, for any S H, on
+        orthonormal Q (n x k): returns (real parts of the k/2 positive Ritz
+        values, Zpos k x k/2, T = H Q)."""
+        Q = colmajor(Q)
+        k = Q.shape[1]
+        ritz = np.zeros(k // 2)
+        Z = empty_cm(k, k // 2, torch.complex128, Q.device)
+        T = empty_cm(self.n, k, torch.complex128, Q.device)
+        self._check(lib().chase_ph_oblique_rr_general(
             self._h, k, _ptr(Q), _ld(Q), ritz.ctypes.data_as(C.POINTER(C.c_double)),
             _ptr(Z), _ld(Z), _ptr(T), _ld(T)))
         return ritz, Z, T
