@@ -27,5 +27,7 @@ lanczos       S-inner-product Lanczos spectral estimates (Section 4.1); Euclidea
               Lanczos on S H for an indefinite S H
 solver        the pseudo-hermitian ChASE outer loop (Alg. 3)
 adjoint       first-order eigenvalue adjoint dL/dA, dL/dB (from Thm 3.2)
+tda           Hermitian ChASE on the resonant block (Alg. 1, B = 0) and the
+              automatic choice of nex
 """
-from . import hamiltonian, dense, chebyshev, qr, rayleigh_ritz, residuals, lanczos, solver, adjoint  # noqa: F401
+from . import hamiltonian, dense, chebyshev, qr, rayleigh_ritz, residuals, lanczos, solver, adjoint, tda  # noqa: F401

@@ -971,3 +971,104 @@ def test_solver_indefinite_skips_spurious_pairs():
                                 max_iter=30, definite=False, rr_backup=1)
     assert info["converged"] and info["iterations"] <= 10
     assert np.allclose(lam, lam_ref, rtol=1e-10, atol=0)
+
+
+# ------------------------------------------------ Hermitian ChASE (Alg. 1)
+def _tda_problem(m=60, seed=0, nev=6, nex=4):
+    return small_problem(m, seed=seed, nev=nev, nex=nex)
+
+
+@pytest.mark.parametrize("deg", [1, 2, 7])
+def test_tda_filter_closed_form_on_eigenvectors(deg):
+    # p_d(A) x_i = T_d(t(omega_i)) / T_d(t(mu_1)) x_i, t(w) = (w - c) / e,
+    # T_d by cos / cosh (the scaled recurrence equals this ratio exactly)
+    from oracle import tda
+    p = _tda_problem()
+    om, X = np.linalg.eigh(p.A)
+    mu1, mu_nevex, mu_m = 0.97 * om[0], om[9], 1.01 * om[-1]
+    c, e, _ = tda.filter_params(mu1, mu_nevex, mu_m)
+
+    def T(d, t):
+        return math.cos(d * math.acos(t)) if abs(t) <= 1 else (np.sign(t) ** d) * math.cosh(d * math.acosh(abs(t)))
+
+    out = tda.chebyshev_filter(p.A, X, deg, mu1, mu_nevex, mu_m)
+    scale = np.array([T(deg, (w - c) / e) / T(deg, (mu1 - c) / e) for w in om])
+    assert np.max(np.abs(out - X * scale[None, :])) <= 1e-11 * max(1.0, np.max(np.abs(scale)))
+
+
+@pytest.mark.parametrize("steps", [3, 6])
+def test_tda_lanczos_gauss_quadrature_moments(steps):
+    from oracle import tda
+    p = _tda_problem(12)
+    v = complex_normal(np.random.default_rng(5), (12,))
+    a, b = tda.lanczos_run(p.A, v, steps)
+    T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+    th, Y = np.linalg.eigh(T)
+    tau = np.abs(Y[0]) ** 2
+    mom = [np.real(np.vdot(v, np.linalg.matrix_power(p.A, j) @ v)) / np.real(np.vdot(v, v)) for j in range(2 * steps + 1)]
+    for j in range(2 * steps):
+        assert abs(np.sum(tau * th ** j) - mom[j]) <= 1e-11 * max(1.0, abs(mom[j]))
+    assert abs(np.sum(tau * th ** (2 * steps)) - mom[2 * steps]) > 1e-8 * abs(mom[2 * steps])
+
+
+@pytest.mark.parametrize("m,J,seed", [(10, 3, 0), (12, 5, 1)])
+def test_tda_estimates_full_dimension_weighted_start(m, J, seed):
+    # weight 1 on every eigenvector of A but 2 on the J-th: a run of m steps
+    # gives mu_1 = omega_1, mu_m = omega_m and the left-end quantile
+    # nevex / m with nevex = J at omega_J ((J - 1)/(m + 1) < J/m <= (J + 1)/(m + 1))
+    from oracle import tda
+    p = _tda_problem(m, seed=seed)
+    om, X = np.linalg.eigh(p.A)
+    w = np.ones(m)
+    w[J - 1] = 2.0
+    phase = np.exp(2j * np.pi * np.random.default_rng(seed + 3).random(m))
+    v0 = X @ (np.sqrt(w) * phase)
+    mu1, mu_nevex, mu_m = tda.spectral_estimates(p.A, v0[:, None], m, J)
+    assert abs(mu1 - om[0]) <= 1e-10 * om[-1]
+    assert abs(mu_nevex - om[J - 1]) <= 1e-10 * om[-1]
+    assert abs(mu_m - om[-1]) <= 1e-10 * om[-1]
+
+
+def test_tda_rayleigh_ritz_exact_and_interlacing():
+    from oracle import tda
+    p = _tda_problem()
+    om, X = np.linalg.eigh(p.A)
+    Q, _ = np.linalg.qr(X[:, :5] @ np.linalg.qr(complex_normal(np.random.default_rng(1), (5, 5)))[0])
+    om_r, V = tda.rayleigh_ritz(p.A, Q)
+    assert np.allclose(om_r, om[:5], rtol=1e-12, atol=0)
+    Q, _ = np.linalg.qr(complex_normal(np.random.default_rng(2), (60, 8)))
+    om_r, _ = tda.rayleigh_ritz(p.A, Q)
+    assert np.all(om_r >= om[:8] - 1e-12) and np.all(om_r <= om[-8:] + 1e-12)   # Cauchy interlacing
+
+
+@pytest.mark.parametrize("m,nev,nex,seed", [(120, 10, 6, 0), (200, 16, 8, 1)])
+def test_tda_solve_matches_the_spectrum_of_a(m, nev, nex, seed):
+    # the generator builds A = Q diag(d) Q^H: the nev smallest d are the answer
+    from oracle import tda
+    p = make_problem(m, lambda rng, mm: rng.uniform(1.0, 5.0, mm), 0.4, nev, nex, 20, 1e-10, seed=seed)
+    om, X, info = tda.solve(p.A, nev, nex, 20, 1e-10, p.w0_raw[:m], p.lanczos_raw[:m])
+    assert info["converged"]
+    assert np.allclose(om, np.sort(p.d)[:nev], rtol=1e-10, atol=0)
+    assert np.max(np.linalg.norm(p.A @ X - X * om[None, :], axis=0)) <= 1e-10
+    assert np.allclose(X.conj().T @ X, np.eye(nev), atol=1e-10)
+
+
+def test_auto_nex_minimises_the_estimated_filter_work():
+    # uniform density on [1, 5] with 1000 equal weights: the quantiles are
+    # known, and the factor of each candidate is 1 / cosh(deg arccosh |t|)
+    from oracle import tda
+    m, nev, deg, tol = 1000, 20, 12, 1e-9
+    th = np.linspace(1.0, 5.0, m)
+    w = np.ones(m)
+    cands = [2, 5, 10, 20, 40, 80]
+    nex, table = tda.auto_nex(th, w, 1.0, 5.0, m, nev, deg, tol, cands)
+    costs = []
+    for (nx, factor, its, cost) in table:
+        om_nev = th[nev - 1]
+        om_nevex = th[nev + nx - 1]
+        c, e = 0.5 * (5.0 + om_nevex), 0.5 * (5.0 - om_nevex)
+        ref = 1.0 / math.cosh(deg * math.acosh(abs((om_nev - c) / e)))
+        assert abs(factor - ref) <= 1e-12 * ref
+        assert its == math.ceil(math.log(tol / 4.0) / math.log(ref))
+        costs.append(its * (nev + nx))
+    assert nex == cands[int(np.argmin(costs))]
