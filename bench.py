@@ -8,9 +8,11 @@ host and uploaded before the timed region.
 One step = one pass of the whole hot path: a full solve (Lanczos, Chebyshev
 filter, CholeskyQR2, oblique Rayleigh-Ritz, residuals, locking) with the
 FP32-filter / FP64-refine policy, followed by the same solve on the FP64
-path.  ``value`` is the filter throughput of the mixed solves (filter flops
-16 n^2 per active column per degree, divided by the stream-timed filter
-time).  The JSON line also carries both time-to-solution figures, their
+path.  ``value`` is the filter throughput of the mixed solves: filter flops
+divided by the stream-timed filter time, with 8 n^2 real flops per active
+column per degree (two products with H, each one real GEMM of 4 n^2 per
+column on the real structure of H; ``filter_tflops.complex_model`` gives the
+same time on the 16 n^2 of a complex-GEMM formulation).  The JSON line also carries both time-to-solution figures, their
 ratio, the eigenvalue agreement, the roofline of the dominant kernel (the
 c64 block-structured GEMM that applies H, timed launch by launch with HIP
 events inside the timed steps) and the CPU oracle timed on bounded samples:
@@ -239,9 +241,9 @@ def main():
                           "write_bytes_per_launch": tr["write_bytes_per_launch"],
                           "source": "profiles/apply_h_c64_traffic_mixed_vs_fp64_m4000.json"}
     roofline = {
-        "kernel": "apply_h_dma_kernel / apply_h_kernel (c64): one H X call with the fused Chebyshev "
-                  "epilogue (one launch, or a main launch plus a side-stream launch for the last k mod 32 "
-                  "columns)",
+        "kernel": "hx_kernel (c64 real GEMM on D = [A+B, i(A-B)]) with its operand pack and the fused "
+                  "Chebyshev epilogue: one H X call (one launch, or a main launch plus a side-stream launch "
+                  "for the last k mod 32 columns); 4 n^2 k real flops per call",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_detail": traffic_detail,
         "measured_mfma_peak": round(probe32, 1), "frac_of_measured": round(achieved / probe32, 4) if probe32 > 0 else None,
@@ -282,7 +284,11 @@ def main():
                                "fp64_min_max": [round(min(r.t_total for r in runs_d), 4),
                                                 round(max(r.t_total for r in runs_d), 4)],
                                "statistic": f"median of {args.steps} timed solves each"},
-        "filter_tflops": {"mixed": round(value, 3), "fp64_path": round(filt_flops_d / filt_time_d / 1e12, 3)},
+        "filter_tflops": {"mixed": round(value, 3), "fp64_path": round(filt_flops_d / filt_time_d / 1e12, 3),
+                          "flops_per_column_per_degree": "8 n^2 (real GEMM on the real structure of H)",
+                          "complex_model": {"mixed": round(2 * value, 3),
+                                            "fp64_path": round(2 * filt_flops_d / filt_time_d / 1e12, 3),
+                                            "flops_per_column_per_degree": "16 n^2 (complex GEMM)"}},
         "iterations": {"mixed": runs_m[-1].iterations, "fp64": runs_d[-1].iterations,
                        "mixed_switch_iter": runs_m[-1].switch_iter},
         "phase_s_mixed": {k: round(getattr(runs_m[-1], k), 4) for k in

@@ -106,8 +106,10 @@ typedef struct {
   int32_t switch_iter;     /* MIXED: first iteration with an FP64 filter (-1: never)        */
   double mu1, mu_nevex0, mu_n; /* Lanczos spectral estimates                                */
   double t_lanczos, t_filter, t_qr, t_rr, t_resid, t_total; /* seconds (stream-timed)       */
-  double filter_flops;     /* 16 n^2 per active column per degree                           */
-  double rr_flops;         /* 4 n^2 k (H Q on K-real columns) + 12 n k^2 + CholeskyQR2 16 n k^2 */
+  double filter_flops;     /* 8 n^2 real flops per active column per degree: each product  */
+                           /* with H is one real GEMM of 4 n^2 per column (a complex GEMM   */
+                           /* [A B][X, K conj(X)] would take 8 n^2)                        */
+  double rr_flops;         /* 2 n^2 k (H Q on K-real columns) + 12 n k^2 + CholeskyQR2 16 n k^2 */
   double filter_flops_fp32;/* part of filter_flops done in c64                              */
   double* resid_history;   /* optional host array (caller-owned) of max_iter * nevex        */
   int32_t resid_history_len; /* capacity of resid_history in doubles (0 if NULL)           */
@@ -137,14 +139,17 @@ chase_ph_status chase_ph_destroy(chase_ph_t h);
 const char* chase_ph_last_error(chase_ph_t h);
 
 /* Y = H X for an n x k block (Section 1, eq. 1.1; the product behind every
- * GEMM of Alg. 2 and eq. 4.1).  prec: CHASE_PH_FP64 -> dX, dY are c128 and
- * the c128 A, B are used; CHASE_PH_FP32 -> dX, dY are c64 and the c64
- * copies of A, B are used (created on first use); CHASE_PH_FP64_KREAL ->
- * as CHASE_PH_FP64 for a block whose columns are K-real (x = [a; conj(a)],
- * K conj(x) = x), for which H x = [t; -conj(t)] with t = [A B] x: half the
- * products (the bottom half of dX is not read; the solver's Rayleigh-Ritz
- * basis is of this kind).  dX and dY must not overlap.  0 <= k;
- * ldx, ldy >= n. */
+ * GEMM of Alg. 2 and eq. 4.1).  H is real-linear on K-real vectors
+ * (Thm 3.1): H [a; conj(a)] = [t; -conj(t)] with t = (A + B) Re(a) +
+ * i (A - B) Im(a).  Each column is split into its two K-real parts and the
+ * product runs as one real GEMM of 4 n^2 k flops against D = [A + B,
+ * i (A - B)] (column-interleaved, built by the library from A and B), half
+ * the flops of a complex GEMM.  prec: CHASE_PH_FP64 -> dX, dY are c128 (D
+ * in c128); CHASE_PH_FP32 -> dX, dY are c64 (D in c64, built on first
+ * use); CHASE_PH_FP64_KREAL -> as CHASE_PH_FP64 for a block whose columns
+ * are K-real (x = [a; conj(a)], K conj(x) = x): 2 n^2 k flops (the bottom
+ * half of dX is not read; the solver's Rayleigh-Ritz basis is of this
+ * kind).  dX and dY must not overlap.  0 <= k; ldx, ldy >= n. */
 chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_t ldx,
                                  void* dY, int64_t ldy, int32_t prec);
 

@@ -28,11 +28,20 @@ struct chase_ph_s {
   SideStream side;  // second stream for column-split H X launches
   int64_t m = 0, n = 0;
   int nevex = 0, kmax = 0, kp = 0;
-  // c64 copies of A and B (mixed / FP32 filter)
-  c64* A32 = nullptr;
-  c64* B32 = nullptr;
-  int64_t ld32 = 0;
+  // D = [A + B, i (A - B)] column-interleaved (m x 2m, ldd): the real
+  // operand of every H X product, in c128 (D64) and, for the mixed / FP32
+  // filter, in c64 (D32)
+  c128* D64 = nullptr;
+  c64* D32 = nullptr;
+  int64_t ldd = 0;
+  bool d64_ready = false;
   bool shadow_ready = false;
+  // packed real coordinates of the H X operand (k-pair layout: yrows row
+  // pairs of ldyr reals, in doubles; the c64 path uses it as floats)
+  double* Yr = nullptr;
+  int64_t ldyr = 0;
+  int kcap = 0;    // columns the packed buffer holds (calls with more run in chunks)
+  int64_t yrows = 0;
   // filter work buffers (n x nevex)
   c128* F1 = nullptr;
   c128* FT = nullptr;
@@ -152,15 +161,15 @@ Err gemm(chase_ph_t h, int ta, int tb, int64_t M, int64_t N, int64_t K, c128 alp
   return zgemm(g, split ? h->ws : nullptr, split ? h->ws_bytes : 0, h->st);
 }
 
-// c64 copies of A and B and the mixed path's work buffers.  alloc_shadow
-// only allocates; ensure_shadow also converts A and B the first time a
-// stage call needs them; the solver converts them again inside every timed
-// solve (refresh_shadow), so a solve's time includes the conversion.
+// D in c64 and the mixed path's work buffers.  alloc_shadow only
+// allocates; ensure_shadow also builds D32 the first time a stage call
+// needs it; the solver builds it again inside every timed solve
+// (refresh_shadow), so a solve's time includes the conversion.  D64 is
+// allocated at create and built the same way (refresh_d64, on first use and
+// inside every solve).
 Err alloc_shadow(chase_ph_t h) {
-  if (h->A32) return ok();
-  h->ld32 = (h->m + 63) / 64 * 64;
-  CHASE_TRY(dalloc(h, &h->A32, (size_t)h->ld32 * h->m));
-  CHASE_TRY(dalloc(h, &h->B32, (size_t)h->ld32 * h->m));
+  if (h->D32) return ok();
+  CHASE_TRY(dalloc(h, &h->D32, (size_t)h->ldd * 2 * h->m));
   CHASE_TRY(dalloc(h, &h->W32, (size_t)h->n * h->nevex));
   CHASE_TRY(dalloc(h, &h->F1_32, (size_t)h->n * h->nevex));
   CHASE_TRY(dalloc(h, &h->FT_32, (size_t)h->n * h->nevex));
@@ -174,7 +183,7 @@ Err alloc_shadow(chase_ph_t h) {
 
 Err refresh_shadow(chase_ph_t h) {
   CHASE_TRY(alloc_shadow(h));
-  CHASE_TRY(make_shadow(h->A, h->B, h->ld, h->p.a_conj, h->A32, h->B32, h->ld32, h->m, h->st));
+  CHASE_TRY(make_d<c64>(h->A, h->B, h->ld, h->p.a_conj, h->D32, h->ldd, h->m, h->st));
   h->shadow_ready = true;
   return ok();
 }
@@ -183,6 +192,13 @@ Err ensure_shadow(chase_ph_t h) {
   if (h->shadow_ready) return ok();
   return refresh_shadow(h);
 }
+
+Err refresh_d64(chase_ph_t h) {
+  CHASE_TRY(make_d<c128>(h->A, h->B, h->ld, h->p.a_conj, h->D64, h->ldd, h->m, h->st));
+  h->d64_ready = true;
+  return ok();
+}
+
 
 constexpr size_t PROF_MAX = 65536;
 
@@ -201,14 +217,17 @@ Err prof_begin(chase_ph_t h) {
   return ok();
 }
 
-// kreal: the call ran on K-real columns (half the products: 4 n^2 k flops).
+// Real flops of one H X product on k columns in the real formulation:
+// 4 n^2 k (2 n^2 k on K-real columns).
+inline double hx_flops(double n, int k, bool kreal) { return (kreal ? 2.0 : 4.0) * n * n * k; }
+
 Err prof_end(chase_ph_t h, int prec, int k, size_t elem, bool has_p, bool has_q, bool kreal = false) {
   if (!h->prof || h->launches.size() >= PROF_MAX) return ok();
   const size_t i = 2 * h->launches.size();
   CHASE_HIP(hipEventRecord(h->evpool[i + 1], h->st));
   const double n = (double)h->n, m = (double)h->m;
   const double bytes = (2.0 * m * m + (2.0 + (has_p ? 1 : 0) + (has_q ? 1 : 0)) * n * k) * elem;
-  h->launches.push_back({prec, k, (kreal ? 4.0 : 8.0) * n * n * k, bytes});
+  h->launches.push_back({prec, k, hx_flops(n, k, kreal), bytes});
   return ok();
 }
 
@@ -217,7 +236,9 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
             const c128* P = nullptr, int64_t ldp = 0, double beta = 0, const c128* Q = nullptr, int64_t ldq = 0,
             double gamma = 0, int kreal = 0) {
   ApplyHArgs<double> a{};
-  a.A = h->A; a.B = h->B; a.lda = h->ld; a.a_conj = h->p.a_conj; a.m = h->m; a.k = k;
+  a.D = h->D64; a.ldd = h->ldd; a.m = h->m; a.k = k;
+  a.yr = h->Yr; a.ldyr = h->ldyr; a.yrows = h->yrows; a.kcap = h->kcap;
+  if (k > 0 && !h->d64_ready) CHASE_TRY(refresh_d64(h));
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
   a.alpha = alpha; a.beta = beta; a.gamma = gamma; a.kreal = kreal;
   if (k <= 0) return ok();
@@ -230,7 +251,10 @@ Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy,
             const c64* P = nullptr, int64_t ldp = 0, float beta = 0, const c64* Q = nullptr, int64_t ldq = 0,
             float gamma = 0, const c64* S = nullptr, int64_t lds = 0, const float* dcol = nullptr) {
   ApplyHArgs<float> a{};
-  a.A = h->A32; a.B = h->B32; a.lda = h->ld32; a.a_conj = 0; a.m = h->m; a.k = k;
+  a.D = h->D32; a.ldd = h->ldd; a.m = h->m; a.k = k;
+  a.yr = reinterpret_cast<float*>(h->Yr); a.ldyr = h->ldyr; a.yrows = h->yrows; a.kcap = h->kcap;
+  if (k > 0 && !h->shadow_ready) CHASE_TRY(refresh_shadow(h));
+  a.D = h->D32;
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
   a.S = S; a.lds = lds; a.dcol = dcol;
@@ -257,7 +281,7 @@ Err filter_impl(chase_ph_t h, int k, C* W, int64_t ldw, const std::vector<int>& 
   auto app = [&](int kc, const C* X, int64_t ldx, C* Y, int64_t ldy, double al, const C* P, int64_t ldp, double be,
                  const C* Q, int64_t ldq, double ga) -> Err {
     ++*launches;
-    *flops += 8.0 * (double)n * (double)n * kc;
+    *flops += hx_flops((double)n, kc, false);
     if constexpr (sizeof(R) == 4)
       return apply32(h, kc, X, ldx, Y, ldy, (float)al, P, ldp, (float)be, Q, ldq, (float)ga);
     else
@@ -341,7 +365,7 @@ Err filter_correction(chase_ph_t h, int k, c128* W, int64_t ldw, const c128* R, 
   CHASE_TRY(h2d(h, h->dcoef, coef.data(), coef.size() * sizeof(float)));
   CHASE_TRY(h2d(h, h->dpw, pw.data(), k * sizeof(double)));
   CHASE_TRY(convert_to_c64(R, ldr, h->R32, n, n, k, h->st));
-  auto count = [&](int kc) { *flops += 8.0 * (double)n * (double)n * kc; };
+  auto count = [&](int kc) { *flops += hx_flops((double)n, kc, false); };
   // s = H r + lambda r
   CHASE_TRY(apply32(h, k, h->R32, n, h->S32, n, 1.0f, nullptr, 0, 0.0f, nullptr, 0, 0.0f, h->R32, n,
                     h->dcoef + (size_t)rows * k));
@@ -418,24 +442,26 @@ Err filter_any(chase_ph_t h, int k, void* dW, int64_t ldw, const std::vector<int
 // One Cholesky-QR pass: Xout = Xin L^{-H} with L L^H = Xin^H Xin + shift I.
 // real: Xin is real (held in c128), and so are the Gram matrix, L and Xout.
 Err cholqr_pass(chase_ph_t h, int k, int kp, const c128* Xin, int64_t ldin, c128* Xout, int64_t ldout, c128* Lbuf,
-                double shift, bool* failed, bool real = false) {
+                double shift, bool* failed, bool real = false, int64_t rows = 0) {
   const int rf = real ? GEMM_REAL : 0;
+  const int64_t nr = rows > 0 ? rows : h->n;
   CHASE_TRY(fill_padded(Lbuf, kp, k, 0.0, 1.0, true, h->st));
   // Gram matrix: the Cholesky reads its lower triangle only
-  CHASE_TRY(gemm(h, 1, 0, k, k, h->n, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp, -1, true,
+  CHASE_TRY(gemm(h, 1, 0, k, k, nr, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp, -1, true,
                  GEMM_LOWER_ONLY | rf));
   if (shift != 0.0) CHASE_TRY(add_diag(Lbuf, kp, k, shift, h->st));
   CHASE_TRY(cholesky_lower(Lbuf, kp, h->dws, h->st, failed));
   if (*failed) return ok();
   CHASE_TRY(tri_inverse_lower(Lbuf, h->Li, kp, h->dws, h->st));
-  return gemm(h, 0, 1, h->n, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout, -1, true, GEMM_B_UPPER | rf);
+  return gemm(h, 0, 1, nr, k, k, {1, 0}, Xin, ldin, h->Li, kp, {0, 0}, Xout, ldout, -1, true, GEMM_B_UPPER | rf);
 }
 
 // Householder QR of X in place; with npre = 2, X is the output of two
 // Cholesky-QR passes with factors L1, L2 and R also takes L2^H L1^H.
-Err householder_fallback(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int npre) {
+Err householder_fallback(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int npre,
+                         int64_t rows = 0) {
   const int kp = pad64(k);
-  CHASE_TRY(householder_qr(X, ldx, h->n, k, R ? h->G : nullptr, kp, h->hhw, h->st));
+  CHASE_TRY(householder_qr(X, ldx, rows > 0 ? rows : h->n, k, R ? h->G : nullptr, kp, h->hhw, h->st));
   if (!R) return ok();
   if (npre == 0) {
     CHASE_HIP(hipMemcpy2DAsync(R, ldr * sizeof(c128), h->G, kp * sizeof(c128), k * sizeof(c128), k,
@@ -453,20 +479,21 @@ Err householder_fallback(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int
 // passes of the shifted variant, on their output (same leading spans).
 // With householder = false the breakdown is only reported (*used_shift = 2,
 // X unspecified): the solver then orthonormalises the K-real form instead.
+// rows: rows of X (0: n).
 Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift,
-            bool householder = true, bool real = false) {
+            bool householder = true, bool real = false, int64_t rows = 0) {
   if (used_shift) *used_shift = 0;
   if (k == 0) return ok();
   const int kp = pad64(k);
-  const int64_t n = h->n;
+  const int64_t n = rows > 0 ? rows : h->n;
   bool failed = false;
-  CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, 0.0, &failed, real));
+  CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, 0.0, &failed, real, n));
   int nf = 2;
   if (!failed) {
-    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real));
+    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real, n));
     if (failed) {
       if (used_shift) *used_shift = 2;
-      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0) : ok();
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0, n) : ok();
     }
   } else {
     if (used_shift) *used_shift = 1;
@@ -478,16 +505,16 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
     double fro2 = 0;
     CHASE_TRY(d2h_small(&fro2, h->dws.dscalar, sizeof(double), h->dws, h->st));
     const double shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * U_ROUND * fro2;
-    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed, real));
-    if (!failed) CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real));
+    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, shift, &failed, real, n));
+    if (!failed) CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real, n));
     if (failed) {
       if (used_shift) *used_shift = 2;
-      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0) : ok();
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0, n) : ok();
     }
-    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L3, 0.0, &failed, real));
+    CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L3, 0.0, &failed, real, n));
     if (failed) {
       if (used_shift) *used_shift = 2;
-      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 2) : ok();
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 2, n) : ok();
     }
     CHASE_HIP(hipMemcpy2DAsync(X, ldx * sizeof(c128), h->Xt, n * sizeof(c128), n * sizeof(c128), k,
                                hipMemcpyDeviceToDevice, h->st));
@@ -846,6 +873,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   CHASE_HIP(hipEventCreate(&t1));
   CHASE_HIP(hipEventRecord(t0, h->st));
 
+  CHASE_TRY(refresh_d64(h));  // the real operand D of every c128 H X product, inside the timed solve
   CHASE_TRY(scale_lower_half(W0, ldw0, h->Wk, n, m, nevex, p.gamma, h->st));  // Alg. 3, line 1 / Section 4.6
   double mu1, mu_nevex, mu_n;
   CHASE_TRY(tm.start());
@@ -1002,7 +1030,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     CHASE_TRY(resid_impl(h, kq, kw, Q, n, h->Tq, n, h->Zp, h->kmax, nullptr, h->Vt, n, res.data(),
                          mixed ? h->Rv : nullptr));
     CHASE_TRY(tm.stop(&inf.t_resid));
-    inf.rr_flops += 4.0 * n * n * kq + 12.0 * n * (double)kq * kq + qr_flops;
+    inf.rr_flops += hx_flops((double)n, kq, true) + 12.0 * n * (double)kq * kq + qr_flops;
     if (inf.resid_history && hist_pos + kw <= inf.resid_history_len) {
       std::copy(res.begin(), res.begin() + kw, inf.resid_history + hist_pos);
       hist_pos += kw;
@@ -1176,6 +1204,12 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   CHASE_HIP(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
   CHASE_HIP(hipEventCreate(&h->e0));
   CHASE_HIP(hipEventCreate(&h->e1));
+  h->ldd = (h->m + 63) / 64 * 64;
+  CHASE_TRY(dalloc(h, &h->D64, (size_t)h->ldd * 2 * h->m));
+  h->kcap = std::max(h->kmax, 512);
+  h->ldyr = 4 * (int64_t)h->kcap + 8;
+  h->yrows = (h->m + 31) / 32 * 32;
+  CHASE_TRY(dalloc(h, &h->Yr, (size_t)h->ldyr * h->yrows));
   CHASE_TRY(dalloc(h, &h->F1, (size_t)n * h->nevex));
   CHASE_TRY(dalloc(h, &h->FT, (size_t)n * h->nevex));
   CHASE_TRY(dalloc(h, &h->Xs, (size_t)n * h->kmax));

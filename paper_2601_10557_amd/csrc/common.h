@@ -70,21 +70,20 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ----------------------------------------------------------------------------
 // Block-structured operator H X from the blocks A, B (apply_h.hip).
 //
-// Computes, for the active columns of an n x k block X,
-//   R = [A B] * [X, K conj(X)]          (m x 2k GEMM, K-dim 2m)
-//   (H X)_top = R[:, :k],  (H X)_bot = -conj(R[:, k:])
-// and writes  Y = alpha (H X) + beta P + gamma Q + diag(dcol) S
+// Computes, for the active columns of an n x k block X, H X as one real
+// GEMM of M = D read as a real 2m x 2m matrix, D = [A + B, i (A - B)]
+// column-interleaved (make_d), with the real coordinates of the K-real parts
+// of X (packed into yr first), and writes
+//   Y = alpha (H X) + beta P + gamma Q + diag(dcol) S
 // (P, Q, S optional; alpha, beta, gamma real scalars, dcol a device array of
-// per-column real scalars).  Y may alias Q (element-wise read-before-write
-// in the same thread).
+// per-column real scalars).  Y may alias P or Q (element-wise
+// read-before-write in the same thread), not X.
 // ----------------------------------------------------------------------------
 template <typename R>
 struct ApplyHArgs {
   using C = typename Cplx<R>::T;
-  const C* A;       // m x m, column-major, lda
-  const C* B;       // m x m, column-major, lda
-  int64_t lda;
-  int a_conj;       // buffer A holds conj(A)
+  const C* D;       // m x 2m, column-major, ldd (multiple of 8, >= m)
+  int64_t ldd;
   int64_t m;
   int k;            // active columns
   const C* X;       // n x k, ldx (already offset to the first active column)
@@ -99,11 +98,28 @@ struct ApplyHArgs {
   const C* S;       // may be null
   int64_t lds;
   const R* dcol;    // k per-column scalars for S (device)
-  // 1: every column of X is K-real (x = [a; conj(a)]), so K conj(X) = X and
-  // H x = [t; -conj(t)] with t = [A B] x: the product runs on the k columns
-  // of X only and the epilogue writes both halves (c128 path, no P/Q/S)
+  // 1: every column of X is K-real (x = [a; conj(a)]), so H x = [t; -conj(t)]
+  // with t from the real coordinates of a: the product runs on k real columns
+  // (c128 path, no P/Q/S)
   int kreal = 0;
+  // 1: Hermitian product A X on the resonant block alone (TDA; D built with
+  // B = 0, so M is the real form of A): X is m x k, Y = alpha A X + ... is
+  // m x k; the product runs on k real columns
+  int tda = 0;
+  // packed real operand in k-pair layout: yrows (>= m rounded up to 32) row
+  // pairs of ldyr (>= 4 kcap + 4, multiple of 8) reals; calls with more than
+  // kcap columns run in chunks
+  R* yr = nullptr;
+  int64_t ldyr = 0;
+  int64_t yrows = 0;
+  int kcap = 0;
 };
+
+// D = [A + B, i (A - B)] column-interleaved (m x 2m, ldd; rows m .. ldd zero)
+// from the c128 blocks (ld); A is conj of its buffer when a_conj; B may be
+// null (B = 0: D = [A, i A], the real form of A).
+template <typename C>
+Err make_d(const c128* A, const c128* B, int64_t ld, int a_conj, C* D, int64_t ldd, int64_t m, hipStream_t s);
 
 // ws: device workspace for split-K partial products (ws_bytes may be 0:
 // then the K range is never split).

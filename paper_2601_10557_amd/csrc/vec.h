@@ -19,8 +19,6 @@ Err pair_mix(c128* X, int64_t ldx, int64_t n, int npair, hipStream_t s);
 Err kreal_unpack(c128* X, int64_t ldx, int64_t m, int k, hipStream_t s);
 Err convert_to_c64(const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s);
 Err convert_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int cols, hipStream_t s);
-Err make_shadow(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32, int64_t m,
-                hipStream_t s);
 Err scale_lower_half(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g,
                      hipStream_t s);
 Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const double* dlam, int64_t n, int kk,
@@ -29,6 +27,9 @@ Err scale_c64(const c64* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, 
 // W[:, j] = pw[j] W[:, j] + ce D[:, j]  (pw device, k values)
 Err combine_correction(c128* W, int64_t ldw, const c64* D, int64_t ldd, const double* dpw, double ce, int64_t n, int k,
                        hipStream_t s);
+// out[j] = Re(x_j^H y_j) over `rows` rows.
+Err row_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t rows, int k, double* out,
+             hipStream_t s);
 // out[j] = Re(x_j^H y_j) over the 2m rows (Euclidean).
 Err plain_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s);
 Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s);

@@ -33,19 +33,6 @@ __global__ void to_c128_kernel(const c64* src, int64_t lds, c128* dst, int64_t l
   }
 }
 
-// conj(A) and B (c128, ld) -> c64 copies with leading dimension ld32
-__global__ void shadow_kernel(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32,
-                              int64_t m) {
-  const int64_t total = m * m;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = t / m, i = t % m;
-    const c128 a = A[j * ld + i];
-    const c128 b = B[j * ld + i];
-    A32[j * ld32 + i] = c64{(float)a.re, (float)(a_conj ? -a.im : a.im)};
-    B32[j * ld32 + i] = c64{(float)b.re, (float)b.im};
-  }
-}
-
 __global__ void scale_lower_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g) {
   const int64_t n = 2 * m;
   const int64_t total = n * cols;
@@ -101,18 +88,19 @@ __global__ __launch_bounds__(256) void resid_kernel(c128* V, int64_t ldv, const 
   if (threadIdx.x == 0) resid[j] = sqrt(rr2) * inv;
 }
 
-// out[j] = Re(x_j^H diag(I, lsgn I) y_j): lsgn = -1 gives x^H S y, +1 the
-// Euclidean product
-__global__ __launch_bounds__(256) void sdot_kernel(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m,
-                                                   double lsgn, double* out) {
+// out[j] = Re(x_j^H y_j) over `rows` rows, rows from msplit on weighted by
+// lsgn: lsgn = -1, msplit = m gives x^H S y on 2m rows, +1 the Euclidean
+// product
+__global__ __launch_bounds__(256) void sdot_kernel(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t rows,
+                                                   int64_t msplit, double lsgn, double* out) {
   __shared__ double red[256];
   const int j = blockIdx.x;
   const c128* x = X + (int64_t)j * ldx;
   const c128* y = Y + (int64_t)j * ldy;
   double s = 0;
-  for (int64_t i = threadIdx.x; i < 2 * m; i += 256) {
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
     const double p = x[i].re * y[i].re + x[i].im * y[i].im;
-    s += i < m ? p : lsgn * p;
+    s += i < msplit ? p : lsgn * p;
   }
   const double r = block_sum(s, red);
   if (threadIdx.x == 0) out[j] = r;
@@ -345,13 +333,6 @@ Err convert_to_c128(const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t
   return ok();
 }
 
-Err make_shadow(const c128* A, const c128* B, int64_t ld, int a_conj, c64* A32, c64* B32, int64_t ld32, int64_t m,
-                hipStream_t s) {
-  hipLaunchKernelGGL(shadow_kernel, dim3(grid_for(m * m)), dim3(256), 0, s, A, B, ld, a_conj, A32, B32, ld32, m);
-  CHASE_LAUNCH_CHECK();
-  return ok();
-}
-
 Err scale_lower_half(const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t m, int cols, double g,
                      hipStream_t s) {
   if (cols == 0) return ok();
@@ -369,13 +350,20 @@ Err residual_norms(c128* V, int64_t ldv, const c128* TZ, int64_t ldt, const doub
 }
 
 Err s_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, m, -1.0, out);
+  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, 2 * m, m, -1.0, out);
   CHASE_LAUNCH_CHECK();
   return ok();
 }
 
 Err plain_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t m, int k, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, m, 1.0, out);
+  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, 2 * m, 2 * m, 1.0, out);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err row_dots(const c128* X, int64_t ldx, const c128* Y, int64_t ldy, int64_t rows, int k, double* out,
+             hipStream_t s) {
+  hipLaunchKernelGGL(sdot_kernel, dim3(k), dim3(256), 0, s, X, ldx, Y, ldy, rows, rows, 1.0, out);
   CHASE_LAUNCH_CHECK();
   return ok();
 }

@@ -63,9 +63,10 @@ def test_apply_h_fp32(prob, solver, k):
     assert np.max(np.abs(Y - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
-# every c64 tile shape of H X (32x32 and 16x16 MFMA tiles), with and without
-# the split-K reduction; "cfg,splits" forces the plan of each launch
-@pytest.mark.parametrize("plan", ["0,1", "0,4", "1,1", "1,5", "2,1", "2,2", "2,7", "3,1", "3,3", "4,2", "5,4", "6,1", "6,5", "7,1", "7,3", "7,6", "8,1", "8,2", "8,5"])
+# every c64 tile shape of the real H X GEMM (0: 256 x 128, 1: 256 x 64 on
+# the 32x32x2 MFMA, 2: 256 x 32 on the 16x16x4 MFMA), with and without the
+# split-K reduction; "cfg,splits" forces the plan of each launch
+@pytest.mark.parametrize("plan", ["0,1", "0,4", "0,9", "1,1", "1,5", "2,1", "2,3", "2,8"])
 @pytest.mark.parametrize("k", [37, 61])
 def test_apply_h_fp32_every_tile_plan(prob, solver, plan, k, monkeypatch):
     print_case("apply_h_fp32_plan", m=prob.m, k=k, plan=plan)
@@ -92,7 +93,9 @@ def test_apply_h_fp64_kreal(prob, solver80, k):
     assert np.max(np.abs(Y - Yg)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("plan", ["0,1", "0,3", "1,2", "2,1", "2,4", "3,1", "3,5"])
+# every c128 tile shape (0: 128 x 128, 1: 128 x 64, 2: 128 x 32, all on
+# the f64 16x16x4 MFMA)
+@pytest.mark.parametrize("plan", ["0,1", "0,3", "1,1", "1,4", "2,1", "2,6"])
 @pytest.mark.parametrize("k", [37, 61])
 def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
     print_case("apply_h_fp64_plan", m=prob.m, k=k, plan=plan)
@@ -117,6 +120,16 @@ def test_apply_h_column_split(prob, solver, k):
     Y32 = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
     ref32 = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
     assert np.max(np.abs(Y32 - ref32)) <= 1e-5 * np.max(np.abs(ref32))
+
+
+def test_apply_h_more_columns_than_the_packed_buffer(prob, solver):
+    # the packed operand holds 512 columns: k = 530 runs as 512 + 18
+    print_case("apply_h_chunks", m=prob.m, k=530)
+    rng = np.random.default_rng(530)
+    X = complex_normal(rng, (prob.n, 530))
+    Y = to_host(solver.apply_h(to_dev(X)))
+    ref = ham.apply_h(prob.A, prob.B, X)
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 def _mus(prob):
