@@ -97,6 +97,20 @@ typedef struct {
                         /* eq. 4.7 by a general eigensolver (chase_ph_oblique_rr_general),  */
                         /* the back-up quotient when Q^H S Q is singular; wanted are the    */
                         /* nev smallest positive real eigenvalues                           */
+  int32_t tda;          /* 1: Hermitian ChASE on A alone (Alg. 1; the B = 0 block of         */
+                        /* Section 1.1): the nev smallest eigenvalues of A, m-row vectors.  */
+                        /* dB is not read (may be NULL); FP64 only, fixed degree deg (in A, */
+                        /* not H^2); the stage calls other than chase_ph_apply_h (which     */
+                        /* then computes A X) return CHASE_PH_ERR_ARG on such a handle      */
+  int32_t nex_auto;     /* tda only.  1: choose the number of extra vectors at solve time   */
+                        /* (the automatic nex named as future work in Section 6.1) among    */
+                        /* ceil(j nex / 8), j = 1..8, minimising the estimated iterations   */
+                        /* x (nev + candidate) from the Lanczos density of A: each          */
+                        /* candidate's nev-th and (nev + candidate)-th eigenvalues are       */
+                        /* density quantiles, the per-iteration factor of the nev-th pair   */
+                        /* is 1 / |T_deg(t)| on the damped interval, and the iterations are */
+                        /* those that take a residual of mu_m - mu_1 down to tol (p->nex is */
+                        /* the largest candidate and sizes the workspace)                   */
 } chase_ph_params;
 
 typedef struct {
@@ -116,6 +130,7 @@ typedef struct {
   int32_t householder_qr_used; /* times the Householder QR fallback was taken              */
   int32_t backup_rr_used;  /* iterations whose Rayleigh-Ritz used the back-up quotient      */
   int32_t general_rr_used; /* iterations whose Rayleigh-Ritz used the general quotient      */
+  int32_t nex_used;        /* extra search vectors of the solve (p->nex unless nex_auto)     */
 } chase_ph_info;
 
 /* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos
@@ -124,9 +139,11 @@ void chase_ph_default_params(chase_ph_params* p);
 
 /* Create a solver handle for H built from the m x m blocks at dA, dB
  * (device, c128, column-major, leading dimension ld >= m).  dA must be
- * Hermitian, dB complex symmetric.  hip_stream may be NULL (default
- * stream).  Allocates all workspace for nevex = nev + nex columns, plus
- * the c64 copies of A and B when precision is MIXED.  Section 1, eq. 1.1. */
+ * Hermitian, dB complex symmetric (dB may be NULL when p->tda = 1).
+ * hip_stream may be NULL (default stream).  Allocates all workspace for
+ * nevex = nev + nex columns and the real operand D = [A + B, i (A - B)]
+ * of the H X products in c128 and, when precision is MIXED, in c64.
+ * Section 1, eq. 1.1. */
 chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const void* dB,
                                 int64_t ld, void* hip_stream, chase_ph_t* out);
 
@@ -149,7 +166,9 @@ const char* chase_ph_last_error(chase_ph_t h);
  * use); CHASE_PH_FP64_KREAL -> as CHASE_PH_FP64 for a block whose columns
  * are K-real (x = [a; conj(a)], K conj(x) = x): 2 n^2 k flops (the bottom
  * half of dX is not read; the solver's Rayleigh-Ritz basis is of this
- * kind).  dX and dY must not overlap.  0 <= k; ldx, ldy >= n. */
+ * kind).  dX and dY must not overlap.  0 <= k; ldx, ldy >= n.
+ * On a TDA handle (p->tda = 1): Y = A X for an m x k block (ldx, ldy >= m;
+ * FP64 or FP32), the same kernel on D = [A, i A]: 8 m^2 k flops. */
 chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_t ldx,
                                  void* dY, int64_t ldy, int32_t prec);
 
@@ -256,7 +275,16 @@ chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const vo
  * nev, ascending), dV (device c128 n x nev, ldv >= n, unit columns),
  * hResid (host, nev, may be NULL), info (may be NULL).  Returns
  * CHASE_PH_ERR_NO_CONVERGENCE with info->locked valid pairs if max_iter is
- * reached first. */
+ * reached first.
+ * On a TDA handle (p->tda = 1) the same call runs Alg. 1 on the Hermitian A:
+ * Lanczos on A (unscaled starts, dLz m x lanczos_vecs, ldlz >= m), then
+ * filter W <- p_deg(A) W (the scaled Chebyshev recurrence of eq. 2.1 on
+ * [mu_nevex, mu_m], normalised at mu_1), Cholesky QR of [Y, W] (Y the
+ * locked vectors), Rayleigh-Ritz G = Q^H A Q (eq. 2.2; block Jacobi),
+ * residuals ||A w - omega w||_2 of unit Ritz vectors and locking of the
+ * leading converged pairs.  dW0 (m x (nev + nex), ldw0 >= m; the first
+ * nev + info->nex_used columns are used), dV (m x nev, ldv >= m); hEvals
+ * are the nev smallest eigenvalues of A, ascending. */
 chase_ph_status chase_ph_solve(chase_ph_t h, const void* dW0, int64_t ldw0, const void* dLz,
                                int64_t ldlz, double* hEvals, void* dV, int64_t ldv,
                                double* hResid, chase_ph_info* info);

@@ -10,5 +10,5 @@ in ``libchase_ph.so`` (HIP for gfx950, C ABI in ``include/chase_ph.h``);
 this package only marshals arguments.
 """
 from ._lib import FP32, FP64, MIXED  # noqa: F401
-from .solver import ChasePHError, PHSolver, colmajor, empty_cm, lib  # noqa: F401
+from .solver import ChasePHError, PHSolver, TDASolver, colmajor, empty_cm, lib  # noqa: F401
 from .autograd import EigvalsPH, eigsh_ph  # noqa: F401

@@ -28,7 +28,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int32), ("tol", C.c_double), ("precision", C.c_int32),
         ("switch_tol", C.c_double), ("gamma", C.c_double), ("lanczos_steps", C.c_int32),
         ("lanczos_vecs", C.c_int32), ("a_conj", C.c_int32), ("rr_backup", C.c_int32),
-        ("definite", C.c_int32),
+        ("definite", C.c_int32), ("tda", C.c_int32), ("nex_auto", C.c_int32),
     ]
 
 
@@ -41,7 +41,7 @@ class Info(C.Structure):
         ("t_total", C.c_double), ("filter_flops", C.c_double), ("rr_flops", C.c_double),
         ("filter_flops_fp32", C.c_double), ("resid_history", C.POINTER(C.c_double)),
         ("resid_history_len", C.c_int32), ("householder_qr_used", C.c_int32),
-        ("backup_rr_used", C.c_int32), ("general_rr_used", C.c_int32),
+        ("backup_rr_used", C.c_int32), ("general_rr_used", C.c_int32), ("nex_used", C.c_int32),
     ]
 
 

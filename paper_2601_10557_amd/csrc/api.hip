@@ -183,7 +183,7 @@ Err alloc_shadow(chase_ph_t h) {
 
 Err refresh_shadow(chase_ph_t h) {
   CHASE_TRY(alloc_shadow(h));
-  CHASE_TRY(make_d<c64>(h->A, h->B, h->ld, h->p.a_conj, h->D32, h->ldd, h->m, h->st));
+  CHASE_TRY(make_d<c64>(h->A, h->p.tda ? nullptr : h->B, h->ld, h->p.a_conj, h->D32, h->ldd, h->m, h->st));
   h->shadow_ready = true;
   return ok();
 }
@@ -194,7 +194,7 @@ Err ensure_shadow(chase_ph_t h) {
 }
 
 Err refresh_d64(chase_ph_t h) {
-  CHASE_TRY(make_d<c128>(h->A, h->B, h->ld, h->p.a_conj, h->D64, h->ldd, h->m, h->st));
+  CHASE_TRY(make_d<c128>(h->A, h->p.tda ? nullptr : h->B, h->ld, h->p.a_conj, h->D64, h->ldd, h->m, h->st));
   h->d64_ready = true;
   return ok();
 }
@@ -226,7 +226,8 @@ Err prof_end(chase_ph_t h, int prec, int k, size_t elem, bool has_p, bool has_q,
   const size_t i = 2 * h->launches.size();
   CHASE_HIP(hipEventRecord(h->evpool[i + 1], h->st));
   const double n = (double)h->n, m = (double)h->m;
-  const double bytes = (2.0 * m * m + (2.0 + (has_p ? 1 : 0) + (has_q ? 1 : 0)) * n * k) * elem;
+  const double rows = h->p.tda ? m : n;  // vectors of m rows on a TDA handle
+  const double bytes = (2.0 * m * m + (2.0 + (has_p ? 1 : 0) + (has_q ? 1 : 0)) * rows * k) * elem;
   h->launches.push_back({prec, k, hx_flops(n, k, kreal), bytes});
   return ok();
 }
@@ -240,11 +241,11 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
   a.yr = h->Yr; a.ldyr = h->ldyr; a.yrows = h->yrows; a.kcap = h->kcap;
   if (k > 0 && !h->d64_ready) CHASE_TRY(refresh_d64(h));
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
-  a.alpha = alpha; a.beta = beta; a.gamma = gamma; a.kreal = kreal;
+  a.alpha = alpha; a.beta = beta; a.gamma = gamma; a.kreal = kreal; a.tda = h->p.tda;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
   CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st, &h->side));
-  return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr, kreal != 0);
+  return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr, kreal != 0 || h->p.tda);
 }
 
 Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy, float alpha = 1,
@@ -257,11 +258,11 @@ Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy,
   a.D = h->D32;
   a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.P = P; a.ldp = ldp; a.Q = Q; a.ldq = ldq;
   a.alpha = alpha; a.beta = beta; a.gamma = gamma;
-  a.S = S; a.lds = lds; a.dcol = dcol;
+  a.S = S; a.lds = lds; a.dcol = dcol; a.tda = h->p.tda;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
   CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st, &h->side));
-  return prof_end(h, CHASE_PH_FP32, k, sizeof(c64), P != nullptr, Q != nullptr);
+  return prof_end(h, CHASE_PH_FP32, k, sizeof(c64), P != nullptr, Q != nullptr, h->p.tda != 0);
 }
 
 // Scaled Chebyshev recurrence on H^2 (eq. 4.1, Zhou-Saad scaling); see
@@ -747,13 +748,45 @@ void tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, std
 // w = S H v, alpha = v^H w, z = S H r and beta^2 = r^H r; the |theta| are
 // the singular values of H, mu_nevex is their quantile nevex / m on the
 // folded axis.
+// The Lanczos recurrence, one product per step, on nv = lanczos_vecs runs
+// at once over `rows`-row vectors whose starts are in lv (ld rows):
+//   w = op(v), alpha = <w, w> or <v, w>, r = w - alpha v - beta v_prev,
+//   z = op(r), beta^2 = <r, z> or <r, r>, v <- r / beta, w <- z / beta
+// (first forms with sh_inner, the S H inner product where op = H; second
+// forms for a Hermitian op in the Euclidean product).  Returns alpha and
+// beta^2 of every run and step on the host ([j * nv + r]).
+template <typename Op, typename Dots>
+Err lanczos_recurrence(chase_ph_t h, int64_t rows, bool sh_inner, Op op, Dots dots, std::vector<double>& ha,
+                       std::vector<double>& hb) {
+  const int nv = h->p.lanczos_vecs, steps = h->p.lanczos_steps;
+  double* alpha = h->dab;
+  double* bsq = h->dab + (size_t)steps * nv;
+  double* b0 = h->dab + (size_t)2 * steps * nv;
+  CHASE_HIP(hipMemsetAsync(h->lvp, 0, sizeof(c128) * rows * nv, h->st));
+  CHASE_TRY(op(h->lv, h->lw));
+  CHASE_TRY(dots(h->lv, sh_inner ? h->lw : h->lv, b0));
+  CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lv, h->lw, rows, rows, nv, b0, false, h->st));
+  for (int j = 0; j < steps; ++j) {
+    CHASE_TRY(dots(sh_inner ? h->lw : h->lv, h->lw, alpha + (size_t)j * nv));
+    CHASE_TRY(lanczos_residual(h->lw, h->lv, h->lvp, h->lr, rows, rows, nv, alpha + (size_t)j * nv,
+                               j ? bsq + (size_t)(j - 1) * nv : nullptr, h->st));
+    CHASE_TRY(op(h->lr, h->lz));
+    CHASE_TRY(dots(h->lr, sh_inner ? h->lz : h->lr, bsq + (size_t)j * nv));
+    if (j + 1 < steps)
+      CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lr, h->lz, rows, rows, nv, bsq + (size_t)j * nv, true, h->st));
+  }
+  ha.assign((size_t)steps * nv, 0.0);
+  hb.assign((size_t)steps * nv, 0.0);
+  CHASE_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * ha.size(), hipMemcpyDeviceToHost, h->st));
+  CHASE_HIP(hipMemcpyAsync(hb.data(), bsq, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, h->st));
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  return ok();
+}
+
 Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, double* mu_nevex, double* mu_n) {
   const int nv = h->p.lanczos_vecs, steps = h->p.lanczos_steps;
   const int64_t n = h->n, m = h->m;
   const bool definite = h->p.definite != 0;
-  double* alpha = h->dab;
-  double* bsq = h->dab + (size_t)steps * nv;
-  double* b0 = h->dab + (size_t)2 * steps * nv;
   // Y = (S) H X for the indefinite recurrence's sign flip
   auto op = [&](const c128* X, c128* Y) -> Err {
     CHASE_TRY(apply64(h, nv, X, n, Y, n));
@@ -764,22 +797,8 @@ Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, doubl
     return definite ? s_dots(X, n, Y, n, m, nv, out, h->st) : plain_dots(X, n, Y, n, m, nv, out, h->st);
   };
   CHASE_TRY(scale_lower_half(dLz, ldlz, h->lv, n, m, nv, h->p.gamma, h->st));
-  CHASE_HIP(hipMemsetAsync(h->lvp, 0, sizeof(c128) * n * nv, h->st));
-  CHASE_TRY(op(h->lv, h->lw));
-  CHASE_TRY(dots(h->lv, definite ? h->lw : h->lv, b0));
-  CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lv, h->lw, n, n, nv, b0, false, h->st));
-  for (int j = 0; j < steps; ++j) {
-    CHASE_TRY(dots(definite ? h->lw : h->lv, h->lw, alpha + (size_t)j * nv));
-    CHASE_TRY(lanczos_residual(h->lw, h->lv, h->lvp, h->lr, n, n, nv, alpha + (size_t)j * nv,
-                               j ? bsq + (size_t)(j - 1) * nv : nullptr, h->st));
-    CHASE_TRY(op(h->lr, h->lz));
-    CHASE_TRY(dots(h->lr, definite ? h->lz : h->lr, bsq + (size_t)j * nv));
-    if (j + 1 < steps) CHASE_TRY(lanczos_advance(h->lvp, h->lv, h->lw, h->lr, h->lz, n, n, nv, bsq + (size_t)j * nv, true, h->st));
-  }
-  std::vector<double> ha((size_t)steps * nv), hb((size_t)steps * nv);
-  CHASE_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * ha.size(), hipMemcpyDeviceToHost, h->st));
-  CHASE_HIP(hipMemcpyAsync(hb.data(), bsq, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, h->st));
-  CHASE_HIP(hipStreamSynchronize(h->st));
+  std::vector<double> ha, hb;
+  CHASE_TRY(lanczos_recurrence(h, n, definite, op, dots, ha, hb));
   double m1 = 1e300, mn = 0;
   std::vector<std::pair<double, double>> pos;  // (theta, weight)
   for (int r = 0; r < nv; ++r) {
@@ -825,6 +844,147 @@ Err lanczos_impl(chase_ph_t h, const c128* dLz, int64_t ldlz, double* mu1, doubl
   *mu1 = m1;
   *mu_nevex = mnev;
   *mu_n = mn;
+  return ok();
+}
+
+// ---------------------------------------------------------------- TDA
+// Hermitian ChASE on A alone (Alg. 1; B = 0 in Section 1.1).  The H X
+// kernels run on D = [A, i A] and give A X on m-row columns.
+
+// Lanczos density of A: Ritz values of every run with Gauss weights
+// |first eigenvector component|^2 / runs, ascending, plus the upper bound
+// mu_m = max over runs of (largest Ritz value + |beta_last z_last|).
+struct TdaDensity {
+  std::vector<std::pair<double, double>> tw;  // (theta, weight), ascending theta
+  double mu1 = 0, mu_m = 0;
+};
+
+Err tda_lanczos(chase_ph_t h, const c128* dLz, int64_t ldlz, TdaDensity* d) {
+  const int nv = h->p.lanczos_vecs, steps = h->p.lanczos_steps;
+  const int64_t m = h->m;
+  auto op = [&](const c128* X, c128* Y) -> Err { return apply64(h, nv, X, m, Y, m); };
+  auto dots = [&](const c128* X, const c128* Y, double* out) -> Err {
+    return row_dots(X, m, Y, m, m, nv, out, h->st);
+  };
+  CHASE_HIP(hipMemcpy2DAsync(h->lv, m * sizeof(c128), dLz, ldlz * sizeof(c128), m * sizeof(c128), nv,
+                             hipMemcpyDeviceToDevice, h->st));
+  std::vector<double> ha, hb;
+  CHASE_TRY(lanczos_recurrence(h, m, false, op, dots, ha, hb));
+  d->tw.clear();
+  d->mu_m = -1e300;
+  for (int r = 0; r < nv; ++r) {
+    std::vector<double> a(steps), b(steps);
+    for (int j = 0; j < steps; ++j) {
+      a[j] = ha[(size_t)j * nv + r];
+      b[j] = std::sqrt(std::max(hb[(size_t)j * nv + r], 0.0));
+    }
+    std::vector<double> th, f, l;
+    tridiag_eig(a, b, th, f, l);
+    int imax = 0;
+    for (int i = 1; i < steps; ++i)
+      if (th[i] > th[imax]) imax = i;
+    d->mu_m = std::max(d->mu_m, th[imax] + std::fabs(b[steps - 1] * l[imax]));
+    for (int i = 0; i < steps; ++i) d->tw.push_back({th[i], f[i] * f[i] / nv});
+  }
+  std::sort(d->tw.begin(), d->tw.end());
+  d->mu1 = d->tw.front().first;
+  return ok();
+}
+
+// Smallest Ritz value at which the weight accumulated from the left end
+// reaches frac of the total.
+double tda_quantile(const TdaDensity& d, double frac) {
+  double tot = 0;
+  for (const auto& p : d.tw) tot += p.second;
+  double cum = 0;
+  for (const auto& p : d.tw) {
+    cum += p.second;
+    if (cum / tot >= frac) return p.first;
+  }
+  return d.tw.back().first;
+}
+
+// mu_nevex of Alg. 1: the density quantile nevex / m, moved off mu_1 and
+// kept 1% of the interval below mu_m.
+double tda_mu_nevex(const TdaDensity& d, int nevex, int64_t m) {
+  double q = tda_quantile(d, (double)nevex / (double)m);
+  if (q <= d.mu1) {
+    q = 0.5 * (d.mu1 + d.mu_m);
+    const double lim = d.mu1 + 1e-8 * std::max(1.0, std::fabs(d.mu1));
+    for (const auto& p : d.tw)
+      if (p.first > lim) {
+        q = p.first;
+        break;
+      }
+  }
+  return std::min(q, d.mu_m - 0.01 * (d.mu_m - d.mu1));
+}
+
+// Automatic nex: per candidate, omega_nev and omega_nevex are density
+// quantiles; the filter on [omega_nevex, mu_m] reduces the nev-th pair by
+// 1 / |T_deg(t)|, t = |omega_nev - c| / e, per iteration; the iterations
+// to take a residual of mu_m - mu_1 to tol times (nev + nex) is the filter
+// work, minimised over the candidates (the first of equal costs).
+int tda_auto_nex(const TdaDensity& d, int64_t m, int nev, int deg, double tol, const std::vector<int>& cands) {
+  int best = -1;
+  double best_cost = 0;
+  for (int nex : cands) {
+    const double om_nev = tda_quantile(d, (double)nev / (double)m);
+    const double om_nevex = tda_quantile(d, (double)(nev + nex) / (double)m);
+    if (om_nevex <= om_nev || om_nevex >= d.mu_m) continue;
+    const double c = 0.5 * (d.mu_m + om_nevex), e = 0.5 * (d.mu_m - om_nevex);
+    const double t = std::fabs((om_nev - c) / e);
+    const double rho = t + std::sqrt(t * t - 1.0);
+    const double factor = 2.0 / (std::pow(rho, deg) + std::pow(rho, -deg));
+    const double its = std::ceil(std::log(tol / (d.mu_m - d.mu1)) / std::log(factor));
+    const double cost = its * (nev + nex);
+    if (best < 0 || cost < best_cost) {
+      best = nex;
+      best_cost = cost;
+    }
+  }
+  return best < 0 ? cands.back() : best;
+}
+
+// Candidates of the automatic nex: ceil(j nex_max / 8), j = 1..8, distinct.
+std::vector<int> tda_nex_candidates(int nex_max) {
+  std::vector<int> c;
+  for (int j = 1; j <= 8; ++j) {
+    const int v = (int)ceil_div((int64_t)j * nex_max, 8);
+    if (v >= 1 && (c.empty() || v != c.back())) c.push_back(v);
+  }
+  return c;
+}
+
+// In place W <- p_deg(A) W (m x k, ldw): the scaled Chebyshev recurrence of
+// eq. 2.1 on [mu_nevex, mu_m], normalised at mu_1,
+//   W_1 = (sigma_1 / e)(A - c) W_0,
+//   W_{s+1} = (2 sigma_{s+1} / e)(A - c) W_s - sigma_s sigma_{s+1} W_{s-1},
+// one H X call (TDA mode) per degree with the update fused; W_s alternates
+// between W and F1 (ld m).
+Err filter_tda(chase_ph_t h, int k, c128* W, int64_t ldw, int deg, double mu1, double mu_nevex, double mu_m,
+               double* flops) {
+  if (k == 0) return ok();
+  const int64_t m = h->m;
+  const double c = 0.5 * (mu_m + mu_nevex), e = 0.5 * (mu_m - mu_nevex);
+  const double s1 = e / (mu1 - c);
+  c128* cur = h->F1;
+  int64_t ldc = m;
+  c128* prev = W;
+  int64_t ldp = ldw;
+  CHASE_TRY(apply64(h, k, W, ldw, h->F1, m, s1 / e, W, ldw, -s1 * c / e));
+  double sigma = s1;
+  for (int s = 1; s < deg; ++s) {
+    const double sn = 1.0 / (2.0 / s1 - sigma);
+    CHASE_TRY(apply64(h, k, cur, ldc, prev, ldp, 2.0 * sn / e, cur, ldc, -2.0 * sn * c / e, prev, ldp, -sigma * sn));
+    std::swap(cur, prev);
+    std::swap(ldc, ldp);
+    sigma = sn;
+  }
+  if (cur != W)
+    CHASE_HIP(hipMemcpy2DAsync(W, ldw * sizeof(c128), cur, ldc * sizeof(c128), m * sizeof(c128), k,
+                               hipMemcpyDeviceToDevice, h->st));
+  *flops += deg * hx_flops((double)h->n, k, true);
   return ok();
 }
 
@@ -1173,6 +1333,152 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
   return ok();
 }
 
+// Alg. 1 on the Hermitian A: Lanczos estimates, then per outer iteration
+// filter, Cholesky QR of [Y, W], Rayleigh-Ritz G = Q^H A Q (eq. 2.2) by
+// block Jacobi and an ascending sort, residuals of the unit Ritz vectors
+// and locking of the leading converged pairs.  All blocks have m rows
+// (leading dimension m in the handle's buffers).
+Err solve_tda_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64_t ldlz, double* evals, c128* V,
+                   int64_t ldv, double* resid_out, chase_ph_info* info, bool* converged) {
+  const chase_ph_params& p = h->p;
+  const int64_t m = h->m;
+  const int nev = p.nev;
+  chase_ph_info inf{};
+  if (info) {
+    inf.resid_history = info->resid_history;
+    inf.resid_history_len = info->resid_history_len;
+  }
+  inf.switch_iter = -1;
+  Timer tm(h);
+  hipEvent_t t0, t1;
+  CHASE_HIP(hipEventCreate(&t0));
+  CHASE_HIP(hipEventCreate(&t1));
+  CHASE_HIP(hipEventRecord(t0, h->st));
+  CHASE_TRY(refresh_d64(h));  // D = [A, i A], inside the timed solve
+
+  CHASE_TRY(tm.start());
+  TdaDensity dens;
+  CHASE_TRY(tda_lanczos(h, Lz, ldlz, &dens));
+  int nex = p.nex;
+  if (p.nex_auto) nex = tda_auto_nex(dens, m, nev, p.deg, p.tol, tda_nex_candidates(p.nex));
+  const int nevex = nev + nex;
+  const double mu1 = dens.mu1, mu_m = dens.mu_m;
+  double mu_nevex = tda_mu_nevex(dens, nevex, m);
+  CHASE_TRY(tm.stop(&inf.t_lanczos));
+  inf.mu1 = mu1;
+  inf.mu_nevex0 = mu_nevex;
+  inf.mu_n = mu_m;
+  inf.nex_used = nex;
+  if (!std::isfinite(mu1) || !std::isfinite(mu_m) || !(mu_nevex > mu1) || !(mu_m > mu_nevex))
+    return fail(CHASE_PH_ERR_ARG, "TDA: Lanczos spectral estimates degenerate (is A a multiple of I?)");
+  const bool verbose = std::getenv("CHASE_PH_VERBOSE") != nullptr;
+  if (verbose)
+    std::fprintf(stderr, "[chase_ph] tda lanczos mu1=%.6g mu_nevex=%.6g mu_m=%.6g nex=%d\n", mu1, mu_nevex, mu_m, nex);
+
+  CHASE_HIP(hipMemcpy2DAsync(h->Wk, m * sizeof(c128), W0, ldw0 * sizeof(c128), m * sizeof(c128), nevex,
+                             hipMemcpyDeviceToDevice, h->st));
+  int locked = 0, hist_pos = 0;
+  std::vector<double> lam_locked, res_locked, ritz(nevex), res(nevex);
+  std::vector<int> order(nevex);
+  *converged = false;
+  for (int it = 0; it < p.max_iter; ++it) {
+    const int kw = nevex - locked;
+    const int kt = pad64(kw);
+    // filter (eq. 2.1)
+    CHASE_TRY(tm.start());
+    CHASE_TRY(filter_tda(h, kw, h->Wk, m, p.deg, mu1, mu_nevex, mu_m, &inf.filter_flops));
+    CHASE_TRY(tm.stop(&inf.t_filter));
+    // orthonormalise [Y, W]; Q = the columns after the locked ones
+    CHASE_TRY(tm.start());
+    if (locked > 0)
+      CHASE_HIP(hipMemcpy2DAsync(h->Xs, m * sizeof(c128), h->Ylock, m * sizeof(c128), m * sizeof(c128), locked,
+                                 hipMemcpyDeviceToDevice, h->st));
+    CHASE_HIP(hipMemcpy2DAsync(h->Xs + (int64_t)locked * m, m * sizeof(c128), h->Wk, m * sizeof(c128),
+                               m * sizeof(c128), kw, hipMemcpyDeviceToDevice, h->st));
+    int used = 0;
+    CHASE_TRY(qr_impl(h, nevex, h->Xs, m, nullptr, 0, &used, true, false, m));
+    inf.shifted_qr_used += used == 1;
+    inf.householder_qr_used += used == 2;
+    CHASE_TRY(tm.stop(&inf.t_qr));
+    const c128* Q = h->Xs + (int64_t)locked * m;
+    // Rayleigh-Ritz: G = Q^H (A Q), G Z = Z Omega, ascending
+    CHASE_TRY(tm.start());
+    CHASE_TRY(apply64(h, kw, Q, m, h->Tq, m));
+    CHASE_TRY(fill_padded(h->G, kt, kw, 0.0, 0.0, true, h->st));
+    CHASE_TRY(gemm(h, 1, 0, kw, kw, m, {1, 0}, Q, m, h->Tq, m, {0, 0}, h->G, kt));
+    int sweeps = 0;
+    CHASE_TRY(jacobi_eigh(h->G, h->Ev, kt, h->dws, h->st, 40, &sweeps));
+    CHASE_TRY(diag_real(h->G, kt, kw, h->dlam, h->st));
+    std::vector<double> om(kw);
+    CHASE_TRY(d2h_small(om.data(), h->dlam, sizeof(double) * kw, h->dws, h->st));
+    std::iota(order.begin(), order.begin() + kw, 0);
+    std::stable_sort(order.begin(), order.begin() + kw, [&](int a, int b) { return om[a] < om[b]; });
+    for (int j = 0; j < kw; ++j) ritz[j] = om[order[j]];
+    CHASE_TRY(h2d(h, h->dperm, order.data(), sizeof(int) * kw));
+    CHASE_TRY(gather_columns(h->Ev, kt, h->Ys, kt, kw, kw, h->dperm, h->st));
+    CHASE_TRY(tm.stop(&inf.t_rr));
+    inf.rr_flops += hx_flops((double)h->n, kw, true) + 8.0 * m * (double)kw * kw + 16.0 * m * (double)nevex * nevex;
+    // residuals ||A w - omega w|| of the unit Ritz vectors w = Q z
+    CHASE_TRY(tm.start());
+    CHASE_TRY(gemm(h, 0, 0, m, kw, kw, {1, 0}, Q, m, h->Ys, kt, {0, 0}, h->Vt, m, -1, false));
+    CHASE_TRY(gemm(h, 0, 0, m, kw, kw, {1, 0}, h->Tq, m, h->Ys, kt, {0, 0}, h->TZ, m, -1, false));
+    CHASE_TRY(h2d(h, h->dlam, ritz.data(), sizeof(double) * kw));
+    CHASE_TRY(residual_norms(h->Vt, m, h->TZ, m, h->dlam, m, kw, h->dres, nullptr, 0, h->st));
+    CHASE_TRY(d2h_small(res.data(), h->dres, sizeof(double) * kw, h->dws, h->st));
+    CHASE_TRY(tm.stop(&inf.t_resid));
+    if (inf.resid_history && hist_pos + kw <= inf.resid_history_len) {
+      std::copy(res.begin(), res.begin() + kw, inf.resid_history + hist_pos);
+      hist_pos += kw;
+    }
+    // lock the leading converged pairs among the first nev - locked
+    int nl = 0;
+    while (nl < nev - locked && res[nl] <= p.tol) ++nl;
+    if (verbose)
+      std::fprintf(stderr, "[chase_ph] tda it %d: k=%d locked %d+%d omega_1=%.6g max resid %.3g\n", it, kw, locked,
+                   nl, ritz[0], *std::max_element(res.begin(), res.begin() + kw));
+    if (nl > 0)
+      CHASE_HIP(hipMemcpy2DAsync(h->Ylock + (int64_t)locked * m, m * sizeof(c128), h->Vt, m * sizeof(c128),
+                                 m * sizeof(c128), nl, hipMemcpyDeviceToDevice, h->st));
+    for (int j = 0; j < nl; ++j) {
+      lam_locked.push_back(ritz[j]);
+      res_locked.push_back(res[j]);
+    }
+    if (kw - nl > 0)
+      CHASE_HIP(hipMemcpy2DAsync(h->Wk, m * sizeof(c128), h->Vt + (int64_t)nl * m, m * sizeof(c128),
+                                 m * sizeof(c128), kw - nl, hipMemcpyDeviceToDevice, h->st));
+    mu_nevex = std::min(mu_nevex, ritz[kw - 1]);
+    locked += nl;
+    inf.iterations = it + 1;
+    if (locked >= nev) {
+      *converged = true;
+      break;
+    }
+  }
+  CHASE_HIP(hipEventRecord(t1, h->st));
+  CHASE_HIP(hipEventSynchronize(t1));
+  float ms = 0;
+  CHASE_HIP(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  inf.t_total = ms * 1e-3;
+  inf.locked = locked;
+  const int nout = std::min(locked, nev);
+  std::vector<int> out(nout);
+  std::iota(out.begin(), out.end(), 0);
+  std::stable_sort(out.begin(), out.end(), [&](int a, int b) { return lam_locked[a] < lam_locked[b]; });
+  for (int i = 0; i < nout; ++i) {
+    evals[i] = lam_locked[out[i]];
+    if (resid_out) resid_out[i] = res_locked[out[i]];
+  }
+  if (nout > 0) {
+    CHASE_TRY(h2d(h, h->dperm, out.data(), sizeof(int) * nout));
+    CHASE_TRY(gather_columns(h->Ylock, m, V, ldv, m, nout, h->dperm, h->st));
+  }
+  CHASE_HIP(hipStreamSynchronize(h->st));
+  if (info) *info = inf;
+  return ok();
+}
+
 // Eigenvalue adjoint (a9): g and the weights gt live in the handle's
 // workspace; the two m x m outputs come from one launch (adjoint.hip).
 Err backward_impl(chase_ph_t h, int nev, const c128* V, int64_t ldv, const double* g, c128* GA, c128* GB, int64_t ldg) {
@@ -1303,7 +1609,11 @@ chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const 
                                 chase_ph_t* out) {
   if (!out) return CHASE_PH_ERR_ARG;
   *out = nullptr;
-  if (!p || !dA || !dB || p->m <= 0 || ld < p->m || p->nev <= 0 || p->nex < 0 || p->nev + p->nex > p->m ||
+  if (!p || (p->tda != 0 && p->tda != 1) || (p->nex_auto != 0 && p->nex_auto != 1)) return CHASE_PH_ERR_ARG;
+  // TDA (Alg. 1): FP64 filter of fixed degree, B not read; nex_auto needs it
+  if ((p->tda && (p->precision != CHASE_PH_FP64 || p->opt_deg)) || (p->nex_auto && (!p->tda || p->nex < 1)))
+    return CHASE_PH_ERR_ARG;
+  if (!dA || (!dB && !p->tda) || p->m <= 0 || ld < p->m || p->nev <= 0 || p->nex < 0 || p->nev + p->nex > p->m ||
       p->deg < 1 || p->max_iter < 1 || !(p->tol > 0) || p->lanczos_steps < 2 || p->lanczos_steps % 2 != 0 ||
       p->lanczos_vecs < 1 || (p->precision != CHASE_PH_FP64 && p->precision != CHASE_PH_MIXED) ||
       (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)) || (p->rr_backup != 0 && p->rr_backup != 1) ||
@@ -1347,11 +1657,20 @@ const char* chase_ph_last_error(chase_ph_t h) { return h ? h->err.c_str() : chas
     }                                                     \
   } while (0)
 
+// Stage calls of the pseudo-hermitian solver, not defined on a TDA handle.
+#define CHECK_PH_HANDLE(h)                                                            \
+  do {                                                                                \
+    CHECK_HANDLE(h);                                                                  \
+    if ((h)->p.tda) return finish(h, fail(CHASE_PH_ERR_ARG, "stage call not defined on a TDA handle")); \
+  } while (0)
+
 chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_t ldx, void* dY, int64_t ldy,
                                  int32_t prec) {
   CHECK_HANDLE(h);
-  if (k < 0 || (k > 0 && (!dX || !dY)) || ldx < h->n || ldy < h->n ||
-      (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32 && prec != CHASE_PH_FP64_KREAL))
+  const int64_t rows = h->p.tda ? h->m : h->n;
+  if (k < 0 || (k > 0 && (!dX || !dY)) || ldx < rows || ldy < rows ||
+      (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32 && prec != CHASE_PH_FP64_KREAL) ||
+      (h->p.tda && prec == CHASE_PH_FP64_KREAL))
     return finish(h, fail(CHASE_PH_ERR_ARG, "apply_h: bad arguments"));
   if (k == 0) return CHASE_PH_OK;
   Err e = ok();
@@ -1375,7 +1694,7 @@ chase_ph_status chase_ph_apply_h(chase_ph_t h, int32_t k, const void* dX, int64_
 
 chase_ph_status chase_ph_filter(chase_ph_t h, int32_t k, void* dW, int64_t ldw, const int32_t* degs, double mu1,
                                 double mu_nevex, double mu_n, int32_t prec) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   std::vector<int> d;
   Err e = check_filter_args(h, k, ldw, degs, mu1, mu_nevex, mu_n, d);
   if (!e && (prec != CHASE_PH_FP64 && prec != CHASE_PH_FP32)) e = fail(CHASE_PH_ERR_ARG, "filter: bad precision");
@@ -1387,7 +1706,7 @@ chase_ph_status chase_ph_filter(chase_ph_t h, int32_t k, void* dW, int64_t ldw, 
 chase_ph_status chase_ph_filter_refined(chase_ph_t h, int32_t k, void* dW, int64_t ldw, const void* dR, int64_t ldr,
                                         const double* hLam, const int32_t* degs, double mu1, double mu_nevex,
                                         double mu_n) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   std::vector<int> d;
   Err e = check_filter_args(h, k, ldw, degs, mu1, mu_nevex, mu_n, d);
   if (!e && k > 0 && (!dW || !dR || !hLam || ldr < h->n)) e = fail(CHASE_PH_ERR_ARG, "filter_refined: bad arguments");
@@ -1402,7 +1721,7 @@ chase_ph_status chase_ph_filter_refined(chase_ph_t h, int32_t k, void* dW, int64
 }
 
 chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void* dR, int64_t ldr, int32_t* used_shift) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   if (k < 0 || k > h->kmax || (k > 0 && !dX) || ldx < h->n || (dR && ldr < k))
     return finish(h, fail(CHASE_PH_ERR_ARG, "qr: bad arguments"));
   int us = 0;
@@ -1416,7 +1735,7 @@ chase_ph_status chase_ph_qr(chase_ph_t h, int32_t k, void* dX, int64_t ldx, void
 
 chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq, double* hRitz, void* dZpos,
                                     int64_t ldz, void* dT, int64_t ldt) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
     return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr: bad arguments"));
   return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt));
@@ -1424,7 +1743,7 @@ chase_ph_status chase_ph_oblique_rr(chase_ph_t h, int32_t k, const void* dQ, int
 
 chase_ph_status chase_ph_oblique_rr_backup(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq, double* hRitz,
                                            void* dZpos, int64_t ldz, void* dT, int64_t ldt) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
     return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr_backup: bad arguments"));
   return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt, false, 1));
@@ -1432,7 +1751,7 @@ chase_ph_status chase_ph_oblique_rr_backup(chase_ph_t h, int32_t k, const void* 
 
 chase_ph_status chase_ph_oblique_rr_general(chase_ph_t h, int32_t k, const void* dQ, int64_t ldq, double* hRitz,
                                             void* dZpos, int64_t ldz, void* dT, int64_t ldt) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   if (k <= 0 || k % 2 != 0 || k > h->kmax || !dQ || !hRitz || !dZpos || !dT || ldq < h->n || ldz < k || ldt < h->n)
     return finish(h, fail(CHASE_PH_ERR_ARG, "oblique_rr_general: bad arguments"));
   return finish(h, rr_impl(h, k, (const c128*)dQ, ldq, hRitz, (c128*)dZpos, ldz, (c128*)dT, ldt, false, 3));
@@ -1441,7 +1760,7 @@ chase_ph_status chase_ph_oblique_rr_general(chase_ph_t h, int32_t k, const void*
 chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const void* dQ, int64_t ldq, const void* dT,
                                    int64_t ldt, const void* dZpos, int64_t ldz, const double* hRitz, void* dV,
                                    int64_t ldv, double* hResid) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   if (k <= 0 || k > h->kmax || kk < 0 || kk > k / 2 || kk > h->nevex || !dQ || !dT || !dZpos || !hRitz || !dV ||
       !hResid || ldq < h->n || ldt < h->n || ldz < k || ldv < h->n)
     return finish(h, fail(CHASE_PH_ERR_ARG, "residuals: bad arguments"));
@@ -1452,10 +1771,14 @@ chase_ph_status chase_ph_residuals(chase_ph_t h, int32_t k, int32_t kk, const vo
 chase_ph_status chase_ph_solve(chase_ph_t h, const void* dW0, int64_t ldw0, const void* dLz, int64_t ldlz,
                                double* hEvals, void* dV, int64_t ldv, double* hResid, chase_ph_info* info) {
   CHECK_HANDLE(h);
-  if (!dW0 || !dLz || !hEvals || !dV || ldw0 < h->n || ldlz < h->n || ldv < h->n)
+  const int64_t rows = h->p.tda ? h->m : h->n;
+  if (!dW0 || !dLz || !hEvals || !dV || ldw0 < rows || ldlz < rows || ldv < rows)
     return finish(h, fail(CHASE_PH_ERR_ARG, "solve: bad arguments"));
   bool conv = false;
-  Err e = solve_impl(h, (const c128*)dW0, ldw0, (const c128*)dLz, ldlz, hEvals, (c128*)dV, ldv, hResid, info, &conv);
+  Err e = h->p.tda ? solve_tda_impl(h, (const c128*)dW0, ldw0, (const c128*)dLz, ldlz, hEvals, (c128*)dV, ldv,
+                                    hResid, info, &conv)
+                   : solve_impl(h, (const c128*)dW0, ldw0, (const c128*)dLz, ldlz, hEvals, (c128*)dV, ldv, hResid,
+                                info, &conv);
   if (e) return finish(h, e);
   if (!conv) return finish(h, fail(CHASE_PH_ERR_NO_CONVERGENCE, "max_iter reached before nev pairs converged"));
   return CHASE_PH_OK;
@@ -1463,7 +1786,7 @@ chase_ph_status chase_ph_solve(chase_ph_t h, const void* dW0, int64_t ldw0, cons
 
 chase_ph_status chase_ph_eigval_backward(chase_ph_t h, int32_t nev, const void* dV, int64_t ldv, const double* hG,
                                          void* dGA, void* dGB, int64_t ldg) {
-  CHECK_HANDLE(h);
+  CHECK_PH_HANDLE(h);
   if (nev <= 0 || !dV || !hG || !dGA || !dGB || ldv < h->n || ldg < h->m)
     return finish(h, fail(CHASE_PH_ERR_ARG, "eigval_backward: bad arguments"));
   return finish(h, backward_impl(h, nev, (const c128*)dV, ldv, hG, (c128*)dGA, (c128*)dGB, ldg));

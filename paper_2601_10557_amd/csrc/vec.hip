@@ -143,6 +143,11 @@ __global__ void trace_kernel(const c128* G, int64_t ld, int k, double* out) {
   if (threadIdx.x == 0) *out = r;
 }
 
+__global__ void diag_real_kernel(const c128* G, int64_t ld, int k, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) out[i] = G[(int64_t)i * ld + i].re;
+}
+
 __global__ void add_diag_kernel(c128* G, int64_t ld, int k, double s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) G[(int64_t)i * ld + i].re += s;
@@ -386,6 +391,13 @@ Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, in
 
 Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
   hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, s, G, ld, k, dout);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err diag_real(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
+  if (k == 0) return ok();
+  hipLaunchKernelGGL(diag_real_kernel, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, G, ld, k, dout);
   CHASE_LAUNCH_CHECK();
   return ok();
 }

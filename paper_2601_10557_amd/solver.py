@@ -115,6 +115,7 @@ class SolveInfo:
     householder_qr_used: int = 0
     backup_rr_used: int = 0
     general_rr_used: int = 0
+    nex_used: int = 0
 
 
 class PHSolver:
@@ -327,3 +328,85 @@ class PHSolver:
             self._h, nev, _ptr(V), _ld(V), g.ctypes.data_as(C.POINTER(C.c_double)),
             _ptr(GA), _ptr(GB), self.m))
         return GA, GB
+
+
+class TDASolver:
+    """Handle for Hermitian ChASE on A alone (Alg. 1; the B = 0 block of
+    Section 1.1): the nev smallest eigenvalues of the Hermitian A (m x m)
+    and their eigenvectors, on the same H X kernels (operand D = [A, iA])."""
+
+    def __init__(self, A: torch.Tensor, nev: int, nex: int, deg: int = 20, tol: float = 1e-10,
+                 max_iter: int = 25, nex_auto: bool = False, lanczos_steps: int = 26,
+                 lanczos_vecs: int = 4):
+        if A.dtype != torch.complex128:
+            raise TypeError("A must be complex128")
+        if not A.is_cuda:
+            raise ValueError("A must be a device tensor")
+        m = A.shape[0]
+        if A.shape != (m, m):
+            raise ValueError("A must be m x m")
+        self.A = A.contiguous()
+        self.m = m
+        self.nev, self.nex = nev, nex
+        p = default_params()
+        p.m, p.nev, p.nex, p.deg = m, nev, nex, deg
+        p.max_iter, p.tol, p.precision = max_iter, tol, _lib.FP64
+        p.lanczos_steps, p.lanczos_vecs = lanczos_steps, lanczos_vecs
+        p.a_conj = 1          # C-contiguous Hermitian A read column-major is conj(A)
+        p.tda, p.nex_auto = 1, int(nex_auto)
+        self.params = p
+        self.stream = torch.cuda.current_stream(A.device)
+        h = C.c_void_p()
+        st = lib().chase_ph_create(C.byref(p), _ptr(self.A), None, m,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != _lib.OK:
+            raise ChasePHError(st, "chase_ph_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().chase_ph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != _lib.OK:
+            msg = lib().chase_ph_last_error(self._h)
+            raise ChasePHError(st, msg.decode() if msg else "")
+
+    def apply_a(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, prec: int = _lib.FP64):
+        """Y = A X; X is m x k (c128 for FP64, c64 for FP32)."""
+        X = colmajor(X)
+        k = X.shape[1]
+        if Y is None:
+            Y = empty_cm(self.m, k, X.dtype, X.device)
+        self._check(lib().chase_ph_apply_h(self._h, k, _ptr(X), _ld(X), _ptr(Y), _ld(Y), prec))
+        return Y
+
+    def solve(self, W0: torch.Tensor, Lz: torch.Tensor, raise_on_noconv: bool = True):
+        """Alg. 1: returns (evals[nev], X m x nev, resid[nev], SolveInfo);
+        W0 is m x (nev + nex), Lz m x lanczos_vecs."""
+        W0, Lz = colmajor(W0), colmajor(Lz)
+        ev = np.zeros(self.nev)
+        res = np.zeros(self.nev)
+        V = empty_cm(self.m, self.nev, torch.complex128, W0.device)
+        hist = np.zeros(self.params.max_iter * (self.nev + self.nex))
+        info = _lib.Info()
+        info.resid_history = hist.ctypes.data_as(C.POINTER(C.c_double))
+        info.resid_history_len = len(hist)
+        st = lib().chase_ph_solve(self._h, _ptr(W0), _ld(W0), _ptr(Lz), _ld(Lz),
+                                  ev.ctypes.data_as(C.POINTER(C.c_double)), _ptr(V), _ld(V),
+                                  res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(info))
+        si = SolveInfo(**{f: getattr(info, f) for f, _ in _lib.Info._fields_
+                          if f not in ("resid_history", "resid_history_len")})
+        si.resid_history = hist
+        if st == _lib.ERR_NO_CONVERGENCE and not raise_on_noconv:
+            nl = si.locked
+            return ev[:nl], V[:, :nl], res[:nl], si
+        self._check(st)
+        return ev, V, res, si

@@ -99,3 +99,28 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert int(out[cname]) == ctypes.sizeof(pyt), cname
         for f, _ in pyt._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(pyt, f).offset, (cname, f)
+
+
+def test_create_rejects_invalid_tda_parameters():
+    """Argument checks of chase_ph_create that run before any device call:
+    the TDA mode (Alg. 1) is FP64 with a fixed degree, nex_auto needs it,
+    and dB may be NULL only in it."""
+    from paper_2601_10557_amd import _lib
+    lib = _lib.load()
+
+    def create(dB=1, **kw):
+        p = _lib.Params()
+        lib.chase_ph_default_params(ctypes.byref(p))
+        p.m, p.nev, p.nex = 100, 10, 8
+        for k, v in kw.items():
+            setattr(p, k, v)
+        h = ctypes.c_void_p()
+        return lib.chase_ph_create(ctypes.byref(p), ctypes.c_void_p(1), None if dB is None else ctypes.c_void_p(dB),
+                                   100, None, ctypes.byref(h))
+
+    assert create(tda=1, precision=_lib.MIXED) == _lib.ERR_ARG
+    assert create(tda=1, opt_deg=1) == _lib.ERR_ARG
+    assert create(nex_auto=1) == _lib.ERR_ARG                 # without tda
+    assert create(tda=1, nex_auto=1, nex=0) == _lib.ERR_ARG
+    assert create(dB=None) == _lib.ERR_ARG                   # dB NULL outside the TDA mode
+    assert create(tda=2) == _lib.ERR_ARG
