@@ -1072,3 +1072,34 @@ def test_auto_nex_minimises_the_estimated_filter_work():
         assert its == math.ceil(math.log(tol / 4.0) / math.log(ref))
         costs.append(its * (nev + nx))
     assert nex == cands[int(np.argmin(costs))]
+
+
+@pytest.mark.parametrize("m,coupling,seed", [(16, 0.4, 0), (40, 0.9, 1), (64, 0.3, 2)])
+def test_inertia_certificate_counts_eigenvalues(m, coupling, seed):
+    # the LDL^H (Bunch-Kaufman) count of nu_+(sigma S - S H) against the
+    # eigenvalues of the dense solver and the eigenvalues of the shifted
+    # matrix itself, at shifts between every few consecutive eigenvalues
+    from oracle import inertia
+    p = small_problem(m, coupling=coupling, seed=seed)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    for j in range(0, m - 1, 5):
+        sigma = 0.5 * (lam[j] + lam[j + 1])
+        M = inertia.shifted_pencil(p.A, p.B, sigma)
+        npos_eig = int(np.sum(np.linalg.eigvalsh(np.array(M)) > 0))
+        assert inertia.count_below(p.A, p.B, sigma) == j + 1 == npos_eig
+    assert inertia.count_below(p.A, p.B, 0.5 * lam[0]) == 0
+    assert inertia.count_below(p.A, p.B, 2 * lam[-1]) == m
+
+
+def test_inertia_count_uses_two_by_two_pivots():
+    # an S-indefinite shift makes Bunch-Kaufman take 2 x 2 pivots; the count
+    # must still match the eigenvalues of the matrix
+    from oracle import inertia
+    import scipy.linalg.lapack as lapack
+    p = small_problem(40, coupling=0.9, seed=4)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    sigma = 0.5 * (lam[20] + lam[21])
+    M = inertia.shifted_pencil(p.A, p.B, sigma)
+    _, ipiv, _ = lapack.zhetrf(np.array(M), lower=1)
+    assert np.any(ipiv < 0)
+    assert inertia.positive_inertia(M) == 21
