@@ -56,7 +56,10 @@ typedef enum {
   CHASE_PH_ERR_NOT_DEFINITE = 4,  /* Cholesky of Q^H S H Q failed: SH not HPD on range(Q)   */
   CHASE_PH_ERR_QR = 5,            /* CholeskyQR2 and its shifted fallback both failed       */
   CHASE_PH_ERR_SINGULAR_QSQ = 6,  /* Q^H S Q numerically singular (Section 4.4)             */
-  CHASE_PH_ERR_NO_CONVERGENCE = 7 /* max_iter reached; info->locked pairs are valid         */
+  CHASE_PH_ERR_NO_CONVERGENCE = 7, /* max_iter reached; info->locked pairs are valid        */
+  CHASE_PH_ERR_EIG = 8            /* the Jacobi eigensolver of the Rayleigh quotient (Alg. 2, */
+                                  /* eq. 2.2) left an off-diagonal entry above 1e-16 ||G||_F */
+                                  /* after rr_max_sweeps sweeps                               */
 } chase_ph_status;
 
 typedef enum {
@@ -111,6 +114,8 @@ typedef struct {
                         /* is 1 / |T_deg(t)| on the damped interval, and the iterations are */
                         /* those that take a residual of mu_m - mu_1 down to tol (p->nex is */
                         /* the largest candidate and sizes the workspace)                   */
+  int32_t rr_max_sweeps; /* sweep limit of the Jacobi eigensolver of the Rayleigh quotient  */
+                        /* (default 40); CHASE_PH_ERR_EIG when it is reached unconverged    */
 } chase_ph_params;
 
 typedef struct {
@@ -131,10 +136,11 @@ typedef struct {
   int32_t backup_rr_used;  /* iterations whose Rayleigh-Ritz used the back-up quotient      */
   int32_t general_rr_used; /* iterations whose Rayleigh-Ritz used the general quotient      */
   int32_t nex_used;        /* extra search vectors of the solve (p->nex unless nex_auto)     */
+  int32_t rr_sweeps_max;   /* most Jacobi sweeps one Rayleigh-Ritz step took                 */
 } chase_ph_info;
 
 /* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos
- * steps x 4 runs, FP64, tol 1e-10, opt_deg 0, definite 1. */
+ * steps x 4 runs, FP64, tol 1e-10, opt_deg 0, definite 1, rr_max_sweeps 40. */
 void chase_ph_default_params(chase_ph_params* p);
 
 /* Create a solver handle for H built from the m x m blocks at dA, dB

@@ -12,12 +12,12 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchase_ph.so")
 
-OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_DEFINITE, ERR_QR, ERR_SINGULAR_QSQ, ERR_NO_CONVERGENCE = range(8)
+OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_DEFINITE, ERR_QR, ERR_SINGULAR_QSQ, ERR_NO_CONVERGENCE, ERR_EIG = range(9)
 FP64, MIXED, FP32, FP64_KREAL = 0, 1, 2, 3
 
 STATUS_NAMES = {
     0: "OK", 1: "ERR_ARG", 2: "ERR_ALLOC", 3: "ERR_HIP", 4: "ERR_NOT_DEFINITE",
-    5: "ERR_QR", 6: "ERR_SINGULAR_QSQ", 7: "ERR_NO_CONVERGENCE",
+    5: "ERR_QR", 6: "ERR_SINGULAR_QSQ", 7: "ERR_NO_CONVERGENCE", 8: "ERR_EIG",
 }
 
 
@@ -29,6 +29,7 @@ class Params(C.Structure):
         ("switch_tol", C.c_double), ("gamma", C.c_double), ("lanczos_steps", C.c_int32),
         ("lanczos_vecs", C.c_int32), ("a_conj", C.c_int32), ("rr_backup", C.c_int32),
         ("definite", C.c_int32), ("tda", C.c_int32), ("nex_auto", C.c_int32),
+        ("rr_max_sweeps", C.c_int32),
     ]
 
 
@@ -42,6 +43,7 @@ class Info(C.Structure):
         ("filter_flops_fp32", C.c_double), ("resid_history", C.POINTER(C.c_double)),
         ("resid_history_len", C.c_int32), ("householder_qr_used", C.c_int32),
         ("backup_rr_used", C.c_int32), ("general_rr_used", C.c_int32), ("nex_used", C.c_int32),
+        ("rr_sweeps_max", C.c_int32),
     ]
 
 

@@ -91,6 +91,7 @@ struct chase_ph_s {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double last_ms = 0;
   int last_launches = 0;
+  int last_sweeps = 0;  // Jacobi sweeps of the last Alg. 2 Rayleigh-Ritz step
   std::string err;
   bool dead = false;
   std::vector<void*> allocs;
@@ -653,7 +654,8 @@ Err rr_impl(chase_ph_t h, int k, const c128* Q, int64_t ldq, double* ritz, c128*
   CHASE_TRY(gemm(h, 0, 0, kp, kp, kp, {1, 0}, h->Li, kp, h->Tk, kp, {0, 0}, h->G, kp, -1, false,
                  GEMM_A_LOWER));  // L^{-1} N L^{-H}
   int sweeps = 0;
-  CHASE_TRY(jacobi_eigh(h->G, h->Ev, kp, h->dws, h->st, 40, &sweeps));
+  CHASE_TRY(jacobi_eigh(h->G, h->Ev, kp, h->dws, h->st, h->p.rr_max_sweeps, &sweeps));
+  h->last_sweeps = sweeps;
   int npos = 0, nneg = 0;
   CHASE_TRY(select_positive(h->G, h->Ev, k, kp, h->Ys, h->dlam, h->dws, h->st, &npos, &nneg));
   if ((npos != k / 2 || nneg != k / 2) && backup == 0) {
@@ -1181,7 +1183,9 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     CHASE_TRY(tm.start());
     bool used_backup = false;
     const int rr_mode = p.rr_backup ? 1 : (definite ? 0 : 2);
+    h->last_sweeps = 0;
     CHASE_TRY(rr_impl(h, kq, Q, n, ritz.data(), h->Zp, h->kmax, h->Tq, n, true, rr_mode, &used_backup));
+    inf.rr_sweeps_max = std::max(inf.rr_sweeps_max, h->last_sweeps);
     inf.backup_rr_used += used_backup;
     inf.general_rr_used += rr_mode == 2 && !used_backup;
     CHASE_TRY(tm.stop(&inf.t_rr));
@@ -1407,7 +1411,8 @@ Err solve_tda_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, i
     CHASE_TRY(fill_padded(h->G, kt, kw, 0.0, 0.0, true, h->st));
     CHASE_TRY(gemm(h, 1, 0, kw, kw, m, {1, 0}, Q, m, h->Tq, m, {0, 0}, h->G, kt));
     int sweeps = 0;
-    CHASE_TRY(jacobi_eigh(h->G, h->Ev, kt, h->dws, h->st, 40, &sweeps));
+    CHASE_TRY(jacobi_eigh(h->G, h->Ev, kt, h->dws, h->st, p.rr_max_sweeps, &sweeps));
+    inf.rr_sweeps_max = std::max(inf.rr_sweeps_max, sweeps);
     CHASE_TRY(diag_real(h->G, kt, kw, h->dlam, h->st));
     std::vector<double> om(kw);
     CHASE_TRY(d2h_small(om.data(), h->dlam, sizeof(double) * kw, h->dws, h->st));
@@ -1603,6 +1608,7 @@ void chase_ph_default_params(chase_ph_params* p) {
   p->lanczos_vecs = 4;
   p->a_conj = 0;
   p->definite = 1;
+  p->rr_max_sweeps = 40;
 }
 
 chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const void* dB, int64_t ld, void* hip_stream,
@@ -1617,7 +1623,7 @@ chase_ph_status chase_ph_create(const chase_ph_params* p, const void* dA, const 
       p->deg < 1 || p->max_iter < 1 || !(p->tol > 0) || p->lanczos_steps < 2 || p->lanczos_steps % 2 != 0 ||
       p->lanczos_vecs < 1 || (p->precision != CHASE_PH_FP64 && p->precision != CHASE_PH_MIXED) ||
       (p->opt_deg && (p->deg_min < 1 || p->deg_max < p->deg_min)) || (p->rr_backup != 0 && p->rr_backup != 1) ||
-      (p->definite != 0 && p->definite != 1))
+      (p->definite != 0 && p->definite != 1) || p->rr_max_sweeps < 1)
     return CHASE_PH_ERR_ARG;
   chase_ph_t h = new (std::nothrow) chase_ph_s;
   if (!h) return CHASE_PH_ERR_ALLOC;

@@ -170,39 +170,50 @@ __device__ __forceinline__ double shfl1(double v) { return __shfl_xor(v, 1); }
 //           when k is odd, is zero); the same for the m-row x_j of a TDA
 //           product.
 template <typename R, typename C>
-__global__ void pack_kernel(const C* X, int64_t ldx, int64_t m, int k, int kreal, R* Y, int64_t ldyr,
-                            int64_t rows) {
-  const int kc = kreal ? (k + 1) / 2 * 2 : k;   // K-real: an even number of columns
-  const int64_t total = rows * kc;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(t % kc);
-    const int64_t p = t / kc;
-    R* y = Y + p * ldyr;
-    if (kreal) {
-      R re = 0, im = 0;
-      if (p < m && j < k) {
-        const C x = X[(int64_t)j * ldx + p];
-        re = x.re;
-        im = x.im;
-      }
-      y[2 * j] = re;
-      y[2 * j + 1] = im;
-      continue;
-    }
+__global__ __launch_bounds__(256) void pack_kernel(const C* X, int64_t ldx, int64_t m, int k, int kreal, R* Y,
+                                                   int64_t ldyr, int64_t rows) {
+  // A tile of 64 row pairs p and TJ columns j goes through LDS: the reads
+  // of X run along rows (coalesced), the writes along the row pair's
+  // CW * TJ = 64 contiguous reals of Y.
+  constexpr int TP = 64, NR = 64;
+  __shared__ R s[TP][NR + 1];
+  const int cw = kreal ? 2 : 4;          // reals per (row pair, column)
+  const int tj = NR / cw;                // columns per tile
+  const int kc = kreal ? (k + 1) / 2 * 2 : k;
+  const int64_t p0 = (int64_t)blockIdx.x * TP;
+  const int j0 = blockIdx.y * tj;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < TP * tj; t += 256) {
+    const int pp = t % TP, jj = t / TP;
+    const int64_t p = p0 + pp;
+    const int j = j0 + jj;
     R q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-    if (p < m) {
+    if (p < m && j < k) {
       const C x1 = X[(int64_t)j * ldx + p];
-      const C x2 = X[(int64_t)j * ldx + m + p];
-      q0 = R(0.5) * (x1.re + x2.re);   // Re a_u
-      q1 = R(0.5) * (x1.im - x2.im);   // Im a_u
-      q2 = R(0.5) * (x1.im + x2.im);   // Re a_v
-      q3 = R(0.5) * (x2.re - x1.re);   // Im a_v
+      if (kreal) {
+        q0 = x1.re;
+        q1 = x1.im;
+      } else {
+        const C x2 = X[(int64_t)j * ldx + m + p];
+        q0 = R(0.5) * (x1.re + x2.re);   // Re a_u
+        q1 = R(0.5) * (x1.im - x2.im);   // Im a_u
+        q2 = R(0.5) * (x1.im + x2.im);   // Re a_v
+        q3 = R(0.5) * (x2.re - x1.re);   // Im a_v
+      }
     }
-    R* g = y + 4 * j;
-    g[0] = q0;
-    g[1] = q1;
-    g[2] = q2;
-    g[3] = q3;
+    s[pp][cw * jj] = q0;
+    s[pp][cw * jj + 1] = q1;
+    if (!kreal) {
+      s[pp][cw * jj + 2] = q2;
+      s[pp][cw * jj + 3] = q3;
+    }
+  }
+  __syncthreads();
+  const int nreal = cw * (min(kc, j0 + tj) - j0);  // reals of this tile in one row pair
+  for (int t = tid; t < TP * NR; t += 256) {
+    const int pp = t / NR, c = t % NR;
+    const int64_t p = p0 + pp;
+    if (p < rows && c < nreal) Y[p * ldyr + (int64_t)cw * j0 + c] = s[pp][c];
   }
 }
 
@@ -593,30 +604,35 @@ Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipSt
 template <typename R>
 Err pack(const ApplyHArgs<R>& a, hipStream_t s) {
   using C = typename ApplyHArgs<R>::C;
-  const int64_t total = a.yrows * (int64_t)(a.k + 1);
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 8192));
-  hipLaunchKernelGGL((pack_kernel<R, C>), dim3(blocks), dim3(256), 0, s, a.X, a.ldx, a.m, a.k, a.kreal || a.tda,
-                     a.yr, a.ldyr, a.yrows);
+  const bool kr = a.kreal || a.tda;
+  const int kc = kr ? (a.k + 1) / 2 * 2 : a.k;
+  const int tj = kr ? 32 : 16;
+  const dim3 grid((unsigned)ceil_div(a.yrows, 64), (unsigned)ceil_div(kc, tj));
+  hipLaunchKernelGGL((pack_kernel<R, C>), grid, dim3(256), 0, s, a.X, a.ldx, a.m, a.k, kr ? 1 : 0, a.yr, a.ldyr,
+                     a.yrows);
   CHASE_LAUNCH_CHECK();
   return ok();
 }
 
-// When 2k is a few columns past a multiple of 64 (e.g. k = 260 or k = 73;
-// k >= 64), the tiles of the last tile column are mostly padding.  The
-// launch is then split by columns (H X is column-wise, and so is the fused
-// epilogue): the first k - r columns, 2(k - r) a multiple of 64, on the
-// caller's stream, and the last r <= 20 on the side stream, queued after the
-// main launch, so that its workgroups take the CU slots the main launch
-// frees in its last round and during its split-K reduction.  Event fork /
-// join keep the pair ordered with the caller's stream.  Y is packed for all
-// k columns before the fork.
+// When 2k is a few columns past a multiple of 128, the width of the widest
+// tiles (e.g. k = 260 or k = 73; k >= 64), the last tile column is mostly
+// padding.  The launch is then split by columns (H X is column-wise, and so
+// is the fused epilogue): the first k - r columns, 2(k - r) a multiple of
+// 128, on the caller's stream, and the last r <= 20 on the side stream,
+// queued after the main launch, so that its workgroups take the CU slots the
+// main launch frees in its last round and during its split-K reduction.
+// Event fork / join keep the pair ordered with the caller's stream.  Y is
+// packed for all k columns before the fork.  (A main part whose 2(k - r)
+// is not a multiple of 128 would keep a padded tile column and pay the side
+// launch on top: k = 228 split at 224 took 680 us on m = 4000, against 567
+// us for the whole k = 256.)
 template <typename R>
 Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side,
                  Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
-  constexpr int gran = 32;
+  constexpr int gran = 64;
   const int krem = a.k % gran;
   constexpr int rmax = 20;
-  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < 2 * gran || a.kreal || a.tda)
+  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < gran || a.kreal || a.tda)
     return one(a, ws, ws_bytes, s);
   ApplyHArgs<R> am = a, ar = a;
   am.k = a.k - krem;

@@ -657,6 +657,19 @@ Err tri_inverse_lower(const c128* L, c128* X, int kp, DenseWs& ws, hipStream_t s
   return ok();
 }
 
+// flag[0] = 1 if some off-diagonal entry of the kp x kp G has |g| > thr:
+// the condition under which a further Jacobi sweep would rotate at all.
+__global__ __launch_bounds__(256) void offdiag_above_kernel(const c128* G, int kp, double thr2, int* flag) {
+  const int64_t total = (int64_t)kp * kp;
+  int big = 0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / kp, i = t % kp;
+    const c128 g = G[t];
+    if (i != j && g.re * g.re + g.im * g.im > thr2) big = 1;
+  }
+  if (__syncthreads_or(big) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
 Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sweeps, int* sweeps_out) {
   const int nbj = kp / JB;  // even since kp % 64 == 0
   const int npair = nbj / 2;
@@ -669,8 +682,9 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
   // and a fraction of the inner work.
   const int inner_sweeps = 1;
   int sweep = 0;
+  bool converged = false;
   for (; sweep < max_sweeps; ++sweep) {
-    CHASE_HIP(hipMemsetAsync(ws.flag, 0, sizeof(int), s));
+    CHASE_HIP(hipMemsetAsync(ws.flag, 0, 2 * sizeof(int), s));
     for (int r = 0; r < nbj - 1; ++r) {
       hipLaunchKernelGGL(jacobi_sub_kernel, dim3(npair), dim3(256), 0, s, (const c128*)G, (int64_t)kp, nbj, r,
                          ws.U, thr, inner_sweeps, ws.flag, ws.pflag);
@@ -680,11 +694,23 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
                          (const c128*)ws.U, (const int*)ws.pflag);
       CHASE_LAUNCH_CHECK();
     }
-    int cnt = 0;
-    CHASE_TRY(d2h_small(&cnt, ws.flag, sizeof(int), ws, s));
-    if (cnt == 0) break;
+    // the sweep rotated: stop if no off-diagonal entry is left above thr
+    // (the next sweep would then leave G and V unchanged)
+    hipLaunchKernelGGL(offdiag_above_kernel, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)kp * kp, 256), 1024)),
+                       dim3(256), 0, s, (const c128*)G, kp, thr * thr, ws.flag + 1);
+    CHASE_LAUNCH_CHECK();
+    int cnt[2] = {0, 0};
+    CHASE_TRY(d2h_small(cnt, ws.flag, 2 * sizeof(int), ws, s));
+    if (cnt[0] == 0 || cnt[1] == 0) {
+      if (cnt[0] != 0) ++sweep;  // count the sweep that rotated
+      converged = true;
+      break;
+    }
   }
   if (sweeps_out) *sweeps_out = sweep;
+  if (!converged)
+    return fail(CHASE_PH_ERR_EIG, "Jacobi eigensolver: off-diagonal entries above 1e-16 ||G||_F after " +
+                                      std::to_string(max_sweeps) + " sweeps");
   return ok();
 }
 

@@ -1,7 +1,7 @@
 """One solve of a named synthetic workload, drawn on the device.
 
     python -m paper_2601_10557_amd.run_workload --config 4 [--precision mixed|fp64]
-        [--max-iter 30] [--backward] [--samples 6] [--rr-backup]
+        [--max-iter 30] [--backward] [--samples 6] [--rr-backup] [--nex N]
 
 Builds the workload with ``synth.gpu`` (seeded, seed 0 by default), runs
 ``chase_ph_solve`` and prints one JSON line: wall time, phase times, filter
@@ -34,11 +34,12 @@ def main(argv=None):
     ap.add_argument("--backward", action="store_true")
     ap.add_argument("--samples", type=int, default=6)
     ap.add_argument("--rr-backup", action="store_true")
+    ap.add_argument("--nex", type=int, default=None, help="override the workload's nex")
     args = ap.parse_args(argv)
     from synth.gpu import config_problem_device
 
     t0 = time.perf_counter()
-    p = config_problem_device(args.config, seed=args.seed)
+    p = config_problem_device(args.config, seed=args.seed, nex=args.nex)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     prec = MIXED if args.precision == "mixed" else FP64
@@ -67,7 +68,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         out["backward_s"] = round(tb, 3)
-        out["backward_tflops"] = round(2 * 8.0 * p.m * p.m * 2 * len(ev) / tb / 1e12, 1)
+        # the kernel forms the lower triangles of the Hermitian G_A and the
+        # symmetric G_B (m^2 / 2 entries each, 2 nev complex MACs per entry)
+        out["backward_tflops"] = round(16.0 * p.m * p.m * len(ev) / tb / 1e12, 1)
         del GA, GB
     if args.samples > 0 and len(ev):
         idx = np.unique(np.linspace(0, len(ev) - 1, args.samples).astype(int))

@@ -116,6 +116,7 @@ class SolveInfo:
     backup_rr_used: int = 0
     general_rr_used: int = 0
     nex_used: int = 0
+    rr_sweeps_max: int = 0
 
 
 class PHSolver:
@@ -125,7 +126,8 @@ class PHSolver:
                  tol: float = 1e-10, max_iter: int = 25, precision: int = _lib.FP64,
                  opt_deg: bool = False, deg_min: int = 8, deg_max: int = 20,
                  switch_tol: float = 0.0, gamma: float = 1e-3, lanczos_steps: int = 26,
-                 lanczos_vecs: int = 4, rr_backup: bool = False, definite: bool = True):
+                 lanczos_vecs: int = 4, rr_backup: bool = False, definite: bool = True,
+                 rr_max_sweeps: int = 40):
         if A.dtype != torch.complex128 or B.dtype != torch.complex128:
             raise TypeError("A and B must be complex128")
         if not A.is_cuda or not B.is_cuda:
@@ -147,6 +149,7 @@ class PHSolver:
         p.a_conj = 1          # C-contiguous Hermitian A read column-major is conj(A)
         p.rr_backup = int(rr_backup)
         p.definite = int(definite)
+        p.rr_max_sweeps = rr_max_sweeps
         self.params = p
         self.device = A.device
         self.stream = torch.cuda.current_stream(self.device)

@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from oracle import adjoint, dense, hamiltonian as ham, residuals as ores
+from oracle import adjoint, dense, hamiltonian as ham, residuals as ores, inertia
 from paper_2601_10557_amd import FP64, MIXED, ChasePHError, PHSolver, eigsh_ph
 from paper_2601_10557_amd import _lib
 from synth import config_problem, make_problem
@@ -189,6 +189,13 @@ def test_solve_config1_fp64_and_mixed():
         s.close()
     assert np.max(np.abs(out[(FP64, False)] - out[(MIXED, False)]) / out[(FP64, False)]) <= 1e-9
     assert np.max(np.abs(out[(MIXED, True)] - out[(MIXED, False)]) / out[(MIXED, False)]) <= 1e-9
+    # completeness by Sylvester's law of inertia (the certificate used where
+    # no dense reference exists): exactly nev eigenvalues below
+    # lambda_nev + delta and nev - 1 below lambda_nev - delta
+    ev = out[(MIXED, False)]
+    delta = 1e-3 * (ev[-1] - ev[-2])
+    assert inertia.count_below(p.A, p.B, ev[-1] + delta) == p.nev
+    assert inertia.count_below(p.A, p.B, ev[-1] - delta) == p.nev - 1
 
 
 def test_autograd_matches_dense_adjoint_and_fd():
@@ -218,3 +225,26 @@ def test_autograd_matches_dense_adjoint_and_fd():
         fd = (p.loss_w @ lp - p.loss_w @ lm) / (2 * h)
         an = np.real(np.vdot(GA, EA)) + np.real(np.vdot(GB, EB))
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_solve_clustered_spectrum_to_convergence(prec):
+    """Reduced clustered workload (80% of the eigenvalues of A in [1, 1.2],
+    the rest up to 20; m = 500, nev = 10, nex = 20), per-vector degrees
+    10..36, tol 1e-9, solved to convergence against the dense oracle.  The
+    filter on H^2 separates the cluster from the damped interval by little
+    per iteration: the oracle's own Alg. 3 takes 239 iterations here."""
+    p = config_problem(2, m=500, nev=10, nex=20)
+    print_case("solve_clustered", m=p.m, prec=prec)
+    lam, _ = dense.dense_ph_eig(p.A, p.B)
+    A, B = dev_blocks(p)
+    s = PHSolver(A, B, p.nev, p.nex, deg=p.deg, tol=p.tol, precision=prec, max_iter=400, opt_deg=True,
+                 deg_min=p.deg_min, deg_max=p.deg_max)
+    ev, V, res, info = s.solve(to_dev(p.w0_raw), to_dev(p.lanczos_raw))
+    s.close()
+    print_case("solve_clustered_done", iterations=info.iterations)
+    assert np.max(np.abs(ev - lam[: p.nev]) / lam[: p.nev]) <= 1e-9
+    assert np.all(res <= p.tol)
+    assert np.all(ores.residual_norms(p.A, p.B, to_host(V), ev) <= 1.5 * p.tol)
+    assert 150 <= info.iterations <= 320
+    assert 1 <= info.rr_sweeps_max < 40

@@ -107,8 +107,8 @@ def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
     assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-# 2k a few columns past a multiple of 64 (k % 32 <= 16, or <= 20 in c64;
-# k >= 64): the library splits the launch by columns over two streams
+# 2k a few columns past a multiple of 128 (k % 64 <= 20; k >= 64): the
+# library splits the launch by columns over two streams
 @pytest.mark.parametrize("k", [73, 84, 132, 145, 260])
 def test_apply_h_column_split(prob, solver, k):
     print_case("apply_h_column_split", m=prob.m, k=k)
@@ -341,6 +341,26 @@ def test_rr_exact_invariant_subspace(prob, solver):
     Q, _, _ = oqr.cholqr2(X)
     ritz, Z, T = solver.oblique_rr(to_dev(Q))
     assert np.allclose(ritz, lam[:6], rtol=1e-12)
+
+
+def test_rr_reports_an_unconverged_jacobi_eigensolver(prob):
+    # one sweep cannot diagonalise the quotient of a random block:
+    # CHASE_PH_ERR_EIG, not a silently inaccurate result; with the default
+    # limit the same call succeeds
+    print_case("rr_jacobi_sweep_limit", m=prob.m, k=40)
+    X = _search_block(prob, 20, seed=11)
+    Q, _, _ = oqr.cholqr2(X)
+    A, B = dev_blocks(prob)
+    s1 = PHSolver(A, B, prob.nev, prob.nex, rr_max_sweeps=1)
+    with pytest.raises(ChasePHError) as e:
+        s1.oblique_rr(to_dev(Q))
+    assert e.value.status == _lib.ERR_EIG
+    s1.close()
+    s40 = PHSolver(A, B, prob.nev, prob.nex)
+    ritz, _, _ = s40.oblique_rr(to_dev(Q))
+    lam_ref, _, _ = rayleigh_ritz.oblique_rr(prob.A, prob.B, Q)
+    assert np.allclose(ritz, lam_ref, rtol=1e-11, atol=0)
+    s40.close()
 
 
 def _unit_ritz(Q, Z):

@@ -124,3 +124,4 @@ def test_create_rejects_invalid_tda_parameters():
     assert create(tda=1, nex_auto=1, nex=0) == _lib.ERR_ARG
     assert create(dB=None) == _lib.ERR_ARG                   # dB NULL outside the TDA mode
     assert create(tda=2) == _lib.ERR_ARG
+    assert create(rr_max_sweeps=0) == _lib.ERR_ARG
