@@ -242,8 +242,9 @@ def main():
                           "source": "profiles/apply_h_c64_traffic_mixed_vs_fp64_m4000.json"}
     roofline = {
         "kernel": "hx_kernel (c64 real GEMM on D = [A+B, i(A-B)]) with its operand pack and the fused "
-                  "Chebyshev epilogue: one H X call (one launch, or a main launch plus a side-stream launch "
-                  "for the last k mod 32 columns); 4 n^2 k real flops per call",
+                  "Chebyshev epilogue: one H X call (pack, one GEMM launch, whose remainder tiles take the "
+                  "last k mod 64 columns of a split call, and the split-K reductions); 4 n^2 k real flops "
+                  "per call",
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_detail": traffic_detail,
         "measured_mfma_peak": round(probe32, 1), "frac_of_measured": round(achieved / probe32, 4) if probe32 > 0 else None,

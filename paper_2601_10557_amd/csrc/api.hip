@@ -25,7 +25,6 @@ struct chase_ph_s {
   const c128* B = nullptr;
   int64_t ld = 0;
   hipStream_t st = nullptr;
-  SideStream side;  // second stream for column-split H X launches
   int64_t m = 0, n = 0;
   int nevex = 0, kmax = 0, kp = 0;
   // D = [A + B, i (A - B)] column-interleaved (m x 2m, ldd): the real
@@ -245,7 +244,7 @@ Err apply64(chase_ph_t h, int k, const c128* X, int64_t ldx, c128* Y, int64_t ld
   a.alpha = alpha; a.beta = beta; a.gamma = gamma; a.kreal = kreal; a.tda = h->p.tda;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
-  CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st, &h->side));
+  CHASE_TRY(launch_apply_h_f64(a, h->ws, h->ws_bytes, h->st));
   return prof_end(h, CHASE_PH_FP64, k, sizeof(c128), P != nullptr, Q != nullptr, kreal != 0 || h->p.tda);
 }
 
@@ -262,7 +261,7 @@ Err apply32(chase_ph_t h, int k, const c64* X, int64_t ldx, c64* Y, int64_t ldy,
   a.S = S; a.lds = lds; a.dcol = dcol; a.tda = h->p.tda;
   if (k <= 0) return ok();
   CHASE_TRY(prof_begin(h));
-  CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st, &h->side));
+  CHASE_TRY(launch_apply_h_f32(a, h->ws, h->ws_bytes, h->st));
   return prof_end(h, CHASE_PH_FP32, k, sizeof(c64), P != nullptr, Q != nullptr, h->p.tda != 0);
 }
 
@@ -1510,9 +1509,6 @@ Err create_impl(const chase_ph_params* p, const void* dA, const void* dB, int64_
   h->kp = pad64(h->kmax);
   const int64_t n = h->n;
   const size_t kp2 = (size_t)h->kp * h->kp;
-  CHASE_HIP(hipStreamCreateWithFlags(&h->side.st, hipStreamNonBlocking));
-  CHASE_HIP(hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming));
-  CHASE_HIP(hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming));
   CHASE_HIP(hipEventCreate(&h->e0));
   CHASE_HIP(hipEventCreate(&h->e1));
   h->ldd = (h->m + 63) / 64 * 64;
@@ -1643,9 +1639,6 @@ chase_ph_status chase_ph_destroy(chase_ph_t h) {
   for (void* q : h->allocs) (void)hipFree(q);
   if (h->dws.hpin) (void)hipHostFree(h->dws.hpin);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
-  if (h->side.fork) (void)hipEventDestroy(h->side.fork);
-  if (h->side.join) (void)hipEventDestroy(h->side.join);
-  if (h->side.st) (void)hipStreamDestroy(h->side.st);
   if (h->e0) (void)hipEventDestroy(h->e0);
   if (h->e1) (void)hipEventDestroy(h->e1);
   delete h;

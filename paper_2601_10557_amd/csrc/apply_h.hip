@@ -305,15 +305,18 @@ __device__ __forceinline__ void step_schedule() {
   }
 }
 
-template <typename Tr, int BM, int BN, int BK, int NST, int WGM, int WGN, int SCHED = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void hx_kernel(
-    const ApplyHArgs<typename Tr::R> a, int splits, int kps, typename Tr::R* ws) {
+// One tile of the GEMM: workgroup bid of the T * splits workgroups of a
+// product (T tiles, K split `splits` ways, kps slabs each), on the LDS ring
+// at lds (NST stages of the M tile, then NST stages of the Y tile).
+template <typename Tr, int BM, int BN, int BK, int NST, int WGM, int WGN, int SCHED>
+__device__ __forceinline__ void hx_tile(const ApplyHArgs<typename Tr::R>& a, int splits, int kps,
+                                        typename Tr::R* ws, int bid, typename Tr::R* lds) {
   using CF = Cfg<Tr, BM, BN, BK, NST, WGM, WGN>;
   using R = typename Tr::R;
   using C = typename Tr::C;
   constexpr int V = CF::V, FM = CF::FM, FN = CF::FN, BNP = CF::BNP, SA = CF::SA;
-  __shared__ __attribute__((aligned(16))) R As[NST][CF::ASTAGE];
-  __shared__ __attribute__((aligned(16))) R Bs[NST][CF::BSTAGE];
+  R (*As)[CF::ASTAGE] = reinterpret_cast<R (*)[CF::ASTAGE]>(lds);
+  R (*Bs)[CF::BSTAGE] = reinterpret_cast<R (*)[CF::BSTAGE]>(lds + NST * CF::ASTAGE);
 
   const int64_t m = a.m;
   const int M2 = (int)(2 * m);                       // real rows and K
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int T = TM * TN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int nid = xcd_remap(blockIdx.x, T * splits);
+  const int nid = xcd_remap(bid, T * splits);
   const int sp = nid / T;
   const int t = nid - sp * T;
   const int m0 = (t / TN) * BM;
@@ -456,6 +459,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
 }
 
+template <typename Tr, int BM, int BN, int BK, int NST, int WGM, int WGN, int SCHED = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void hx_kernel(
+    const ApplyHArgs<typename Tr::R> a, int splits, int kps, typename Tr::R* ws) {
+  using CF = Cfg<Tr, BM, BN, BK, NST, WGM, WGN>;
+  using R = typename Tr::R;
+  __shared__ __attribute__((aligned(16))) R lds[CF::LDS / sizeof(R)];
+  hx_tile<Tr, BM, BN, BK, NST, WGM, WGN, SCHED>(a, splits, kps, ws, blockIdx.x, lds);
+}
+
+// A split product in one launch: the last few columns (their own tile shape
+// and K split, workgroups 0 .. nrem - 1, nrem a multiple of 8 so that the
+// XCD of a workgroup stays blockIdx mod 8 in both parts) ahead of the main
+// columns.  The short remainder workgroups are dispatched first and spread
+// over the CUs while the main tiles fill the rest, without a second stream.
+template <typename Tr, int BM, int BN, int BK, int NST, int WGM, int WGN, int SCHED, int BMR, int BNR, int BKR,
+          int NSTR, int WGMR, int WGNR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void hx_pair_kernel(
+    const ApplyHArgs<typename Tr::R> am, int splits_m, int kps_m, typename Tr::R* ws_m,
+    const ApplyHArgs<typename Tr::R> ar, int splits_r, int kps_r, typename Tr::R* ws_r, int nrem, int nrem_live) {
+  using R = typename Tr::R;
+  constexpr size_t LM = Cfg<Tr, BM, BN, BK, NST, WGM, WGN>::LDS;
+  constexpr size_t LR = Cfg<Tr, BMR, BNR, BKR, NSTR, WGMR, WGNR>::LDS;
+  __shared__ __attribute__((aligned(16))) R lds[(LM > LR ? LM : LR) / sizeof(R)];
+  const int bid = blockIdx.x;
+  if (bid < nrem) {
+    if (bid < nrem_live) hx_tile<Tr, BMR, BNR, BKR, NSTR, WGMR, WGNR, 0>(ar, splits_r, kps_r, ws_r, bid, lds);
+  } else {
+    hx_tile<Tr, BM, BN, BK, NST, WGM, WGN, SCHED>(am, splits_m, kps_m, ws_m, bid - nrem, lds);
+  }
+}
+
 // Sum the split-K partials in a fixed order and apply the epilogue: one
 // thread per complex row i and X column j.
 template <typename R, typename C>
@@ -544,6 +578,16 @@ void plan_override(Plan& p, int64_t m2, int64_t n2, const int (&bm)[NCFG], const
   p.tiles = ceil_div(m2, bm[c]) * ceil_div(n2, bn[c]);
 }
 
+template <typename R, typename C>
+Err launch_reduce(const ApplyHArgs<R>& a, int splits, const R* ws, hipStream_t s) {
+  if (splits <= 1) return ok();
+  const int64_t total = a.m * (int64_t)a.k;
+  const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 8192);
+  hipLaunchKernelGGL((hx_reduce<R, C>), dim3(blocks), dim3(256), 0, s, a, splits, ws);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
 template <typename Tr, int BM, int BN, int BK, int NST, int WGM, int WGN, int SCHED = 0>
 Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hipStream_t s) {
   using R = typename Tr::R;
@@ -552,13 +596,25 @@ Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hip
   hipLaunchKernelGGL((hx_kernel<Tr, BM, BN, BK, NST, WGM, WGN, SCHED>), dim3((unsigned)grid), dim3(256), 0, s, a, p.splits,
                      p.kps, (R*)ws);
   CHASE_LAUNCH_CHECK();
-  if (p.splits > 1) {
-    const int64_t total = a.m * (int64_t)a.k;
-    const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 8192);
-    hipLaunchKernelGGL((hx_reduce<R, C>), dim3(blocks), dim3(256), 0, s, a, p.splits, (const R*)ws);
-    CHASE_LAUNCH_CHECK();
-  }
-  return ok();
+  return launch_reduce<R, C>(a, p.splits, (const R*)ws, s);
+}
+
+// Main part on tile shape (BM, BN, ...), remainder on (BMR, BNR, ...).
+template <typename Tr, int BM, int BN, int BK, int NST, int WGM, int WGN, int SCHED, int BMR, int BNR, int BKR,
+          int NSTR, int WGMR, int WGNR>
+Err launch_pair_cfg(const ApplyHArgs<typename Tr::R>& am, const Plan& pm, void* wsm,
+                    const ApplyHArgs<typename Tr::R>& ar, const Plan& pr, void* wsr, hipStream_t s) {
+  using R = typename Tr::R;
+  using C = typename Tr::C;
+  const int live = (int)(pr.tiles * pr.splits);
+  const int nrem = (live + 7) / 8 * 8;
+  const int64_t grid = nrem + pm.tiles * pm.splits;
+  hipLaunchKernelGGL((hx_pair_kernel<Tr, BM, BN, BK, NST, WGM, WGN, SCHED, BMR, BNR, BKR, NSTR, WGMR, WGNR>),
+                     dim3((unsigned)grid), dim3(256), 0, s, am, pm.splits, pm.kps, (R*)wsm, ar, pr.splits, pr.kps,
+                     (R*)wsr, nrem, live);
+  CHASE_LAUNCH_CHECK();
+  CHASE_TRY((launch_reduce<R, C>(am, pm.splits, (const R*)wsm, s)));
+  return launch_reduce<R, C>(ar, pr.splits, (const R*)wsr, s);
 }
 
 // Tile shapes (BM x BN reals, K slab BK, NST ring stages), two workgroups
@@ -569,15 +625,37 @@ Err launch_cfg(const ApplyHArgs<typename Tr::R>& a, const Plan& p, void* ws, hip
 //  c128: 0  128 x 128, BK 8,  4 stages, 16x16x4 f64 (2 x 2 waves of 64 x 64), SCHED 3
 //        1  128 x 64,  BK 8,  4 stages (64 x 32)
 //        2  128 x 32,  BK 8,  4 stages, 4 x 1 waves (32 x 32; narrow launches)
-Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
-  if (a.k <= 0 || a.m <= 0) return ok();
-  static const int bm[3] = {256, 256, 256}, bn[3] = {128, 64, 32}, bk[3] = {16, 16, 16};
-  static const double eff[3] = {1.0, 0.95, 0.8};
-  static const int occ[3] = {2, 2, 2};
+struct F32Tiles {
+  static constexpr int bm[3] = {256, 256, 256}, bn[3] = {128, 64, 32}, bk[3] = {16, 16, 16};
+  static constexpr double eff[3] = {1.0, 0.95, 0.8};
+  static constexpr int occ[3] = {2, 2, 2};
+  static constexpr double split_penalty = 0.01;
+};
+struct F64Tiles {
+  static constexpr int bm[3] = {128, 128, 128}, bn[3] = {128, 64, 32}, bk[3] = {8, 8, 8};
+  static constexpr double eff[3] = {1.0, 0.95, 0.8};
+  static constexpr int occ[3] = {2, 2, 2};
+  static constexpr double split_penalty = 0.02;
+};
+
+// Plan over the first ncfg tile shapes (the narrow shape alone: ncfg = 1
+// starting at the last one).
+template <typename T, typename R>
+Plan plan_for(const ApplyHArgs<R>& a, size_t wsb, bool narrow_only) {
   const int64_t m2 = 2 * a.m, n2 = ((a.kreal || a.tda) ? 1 : 2) * (int64_t)a.k;
-  const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<3>(m2, n2, bm, bn, bk, eff, occ, 0.01, sizeof(float), wsb, 3);
-  plan_override<3>(p, m2, n2, bm, bn, bk, sizeof(float), wsb);
+  if (narrow_only) {
+    const int bm[1] = {T::bm[2]}, bn[1] = {T::bn[2]}, bk[1] = {T::bk[2]}, occ[1] = {T::occ[2]};
+    const double eff[1] = {T::eff[2]};
+    Plan p = make_plan<1>(m2, n2, bm, bn, bk, eff, occ, T::split_penalty, sizeof(R), wsb, 1);
+    p.cfg = 2;
+    return p;
+  }
+  Plan p = make_plan<3>(m2, n2, T::bm, T::bn, T::bk, T::eff, T::occ, T::split_penalty, sizeof(R), wsb, 3);
+  plan_override<3>(p, m2, n2, T::bm, T::bn, T::bk, sizeof(R), wsb);
+  return p;
+}
+
+Err launch_plan_f32(const ApplyHArgs<float>& a, const Plan& p, void* ws, hipStream_t s) {
   switch (p.cfg) {
     case 0: return launch_cfg<TF32, 256, 128, 16, 3, 4, 1, 1>(a, p, ws, s);
     case 1: return launch_cfg<TF32, 256, 64, 16, 3, 4, 1, 1>(a, p, ws, s);
@@ -585,19 +663,41 @@ Err launch_one_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStr
   }
 }
 
-Err launch_one_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
-  if (a.k <= 0 || a.m <= 0) return ok();
-  static const int bm[3] = {128, 128, 128}, bn[3] = {128, 64, 32}, bk[3] = {8, 8, 8};
-  static const double eff[3] = {1.0, 0.95, 0.8};
-  static const int occ[3] = {2, 2, 2};
-  const int64_t m2 = 2 * a.m, n2 = ((a.kreal || a.tda) ? 1 : 2) * (int64_t)a.k;
-  const size_t wsb = ws ? ws_bytes : 0;
-  Plan p = make_plan<3>(m2, n2, bm, bn, bk, eff, occ, 0.02, sizeof(double), wsb, 3);
-  plan_override<3>(p, m2, n2, bm, bn, bk, sizeof(double), wsb);
+Err launch_plan_f64(const ApplyHArgs<double>& a, const Plan& p, void* ws, hipStream_t s) {
   switch (p.cfg) {
     case 0: return launch_cfg<TF64, 128, 128, 8, 4, 2, 2, 3>(a, p, ws, s);
     case 1: return launch_cfg<TF64, 128, 64, 8, 4, 2, 2>(a, p, ws, s);
     default: return launch_cfg<TF64, 128, 32, 8, 4, 4, 1>(a, p, ws, s);
+  }
+}
+
+// the remainder always on the narrow shape (16 x 16 MFMA for c64)
+Err launch_pair_f32(const ApplyHArgs<float>& am, const Plan& pm, void* wsm, const ApplyHArgs<float>& ar,
+                    const Plan& pr, void* wsr, hipStream_t s) {
+  switch (pm.cfg) {
+    case 0:
+      return launch_pair_cfg<TF32, 256, 128, 16, 3, 4, 1, 1, 256, 32, 16, 3, 4, 1>(am, pm, wsm, ar, pr, wsr, s);
+    case 1:
+      return launch_pair_cfg<TF32, 256, 64, 16, 3, 4, 1, 1, 256, 32, 16, 3, 4, 1>(am, pm, wsm, ar, pr, wsr, s);
+    default: {
+      // both parts on the narrow shape: two plain launches in stream order
+      CHASE_TRY((launch_cfg<TF32S, 256, 32, 16, 3, 4, 1>(am, pm, wsm, s)));
+      return launch_cfg<TF32S, 256, 32, 16, 3, 4, 1>(ar, pr, wsr, s);
+    }
+  }
+}
+
+Err launch_pair_f64(const ApplyHArgs<double>& am, const Plan& pm, void* wsm, const ApplyHArgs<double>& ar,
+                    const Plan& pr, void* wsr, hipStream_t s) {
+  switch (pm.cfg) {
+    case 0:
+      return launch_pair_cfg<TF64, 128, 128, 8, 4, 2, 2, 3, 128, 32, 8, 4, 4, 1>(am, pm, wsm, ar, pr, wsr, s);
+    case 1:
+      return launch_pair_cfg<TF64, 128, 64, 8, 4, 2, 2, 0, 128, 32, 8, 4, 4, 1>(am, pm, wsm, ar, pr, wsr, s);
+    default: {
+      CHASE_TRY((launch_cfg<TF64, 128, 32, 8, 4, 4, 1>(am, pm, wsm, s)));
+      return launch_cfg<TF64, 128, 32, 8, 4, 4, 1>(ar, pr, wsr, s);
+    }
   }
 }
 
@@ -614,26 +714,48 @@ Err pack(const ApplyHArgs<R>& a, hipStream_t s) {
   return ok();
 }
 
-// When 2k is a few columns past a multiple of 128, the width of the widest
-// tiles (e.g. k = 260 or k = 73; k >= 64), the last tile column is mostly
-// padding.  The launch is then split by columns (H X is column-wise, and so
-// is the fused epilogue): the first k - r columns, 2(k - r) a multiple of
-// 128, on the caller's stream, and the last r <= 20 on the side stream,
-// queued after the main launch, so that its workgroups take the CU slots the
-// main launch frees in its last round and during its split-K reduction.
-// Event fork / join keep the pair ordered with the caller's stream.  Y is
-// packed for all k columns before the fork.  (A main part whose 2(k - r)
-// is not a multiple of 128 would keep a padded tile column and pay the side
-// launch on top: k = 228 split at 224 took 680 us on m = 4000, against 567
-// us for the whole k = 256.)
 template <typename R>
-Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side,
-                 Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
+struct PrecOps;
+template <>
+struct PrecOps<float> {
+  using Tiles = F32Tiles;
+  static Err one(const ApplyHArgs<float>& a, const Plan& p, void* ws, hipStream_t s) {
+    return launch_plan_f32(a, p, ws, s);
+  }
+  static Err pair(const ApplyHArgs<float>& am, const Plan& pm, void* wsm, const ApplyHArgs<float>& ar,
+                  const Plan& pr, void* wsr, hipStream_t s) {
+    return launch_pair_f32(am, pm, wsm, ar, pr, wsr, s);
+  }
+};
+template <>
+struct PrecOps<double> {
+  using Tiles = F64Tiles;
+  static Err one(const ApplyHArgs<double>& a, const Plan& p, void* ws, hipStream_t s) {
+    return launch_plan_f64(a, p, ws, s);
+  }
+  static Err pair(const ApplyHArgs<double>& am, const Plan& pm, void* wsm, const ApplyHArgs<double>& ar,
+                  const Plan& pr, void* wsr, hipStream_t s) {
+    return launch_pair_f64(am, pm, wsm, ar, pr, wsr, s);
+  }
+};
+
+// When 2k is a few columns past a multiple of 128, the width of the widest
+// tiles (e.g. k = 260 or k = 73; k >= 64), the last tile column of a plain
+// launch is mostly padding.  The product is then split by columns (H X is
+// column-wise, and so is the fused epilogue): the first k - r columns,
+// 2(k - r) a multiple of 128, on the widest tiles the plan picks, and the
+// last r <= 20 on the narrow tile with their own K split, both in one
+// launch (hx_pair_kernel, remainder workgroups first).  Y is packed for all
+// k columns before.  (A main part whose 2(k - r) is not a multiple of 128
+// would keep a padded tile column and pay the remainder on top.)
+template <typename R>
+Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t s) {
+  using Ops = PrecOps<R>;
   constexpr int gran = 64;
   const int krem = a.k % gran;
   constexpr int rmax = 20;
-  if (!side || !side->st || !ws || krem == 0 || krem > rmax || a.k < gran || a.kreal || a.tda)
-    return one(a, ws, ws_bytes, s);
+  if (!ws || krem == 0 || krem > rmax || a.k < gran || a.kreal || a.tda)
+    return Ops::one(a, plan_for<typename Ops::Tiles>(a, ws ? ws_bytes : 0, false), ws, s);
   ApplyHArgs<R> am = a, ar = a;
   am.k = a.k - krem;
   ar.k = krem;
@@ -649,19 +771,14 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
   size_t rem_bytes = (size_t)MAX_SPLITS * 2 * a.m * 2 * krem * sizeof(R);
   rem_bytes = std::min(ceil_div((int64_t)rem_bytes, (int64_t)256) * 256, (int64_t)(ws_bytes / 4));
   const size_t main_bytes = (ws_bytes - rem_bytes) / 256 * 256;
-  CHASE_HIP(hipEventRecord(side->fork, s));
-  CHASE_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
-  CHASE_TRY(one(am, ws, main_bytes, s));
-  CHASE_TRY(one(ar, static_cast<char*>(ws) + main_bytes, rem_bytes, side->st));
-  CHASE_HIP(hipEventRecord(side->join, side->st));
-  CHASE_HIP(hipStreamWaitEvent(s, side->join, 0));
-  return ok();
+  const Plan pm = plan_for<typename Ops::Tiles>(am, main_bytes, false);
+  const Plan pr = plan_for<typename Ops::Tiles>(ar, rem_bytes, true);
+  return Ops::pair(am, pm, ws, ar, pr, static_cast<char*>(ws) + main_bytes, s);
 }
 
 // Columns in chunks of at most kcap (the capacity of the packed buffer).
 template <typename R>
-Err launch_any(const ApplyHArgs<R>& a0, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side,
-               Err (*one)(const ApplyHArgs<R>&, void*, size_t, hipStream_t)) {
+Err launch_any(const ApplyHArgs<R>& a0, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a0.k <= 0 || a0.m <= 0) return ok();
   if (a0.kcap <= 0 || !a0.yr || !a0.D || a0.ldyr < 4 * (int64_t)a0.kcap + 4 || a0.ldyr % 8 != 0 ||
       a0.yrows < (a0.m + 31) / 32 * 32 || a0.ldd < a0.m || a0.ldd % 8 != 0)
@@ -676,7 +793,7 @@ Err launch_any(const ApplyHArgs<R>& a0, void* ws, size_t ws_bytes, hipStream_t s
     if (a0.S) a.S = a0.S + (int64_t)c0 * a0.lds;
     if (a0.dcol) a.dcol = a0.dcol + c0;
     CHASE_TRY(pack<R>(a, s));
-    CHASE_TRY(launch_split<R>(a, ws, ws_bytes, s, side, one));
+    CHASE_TRY(launch_split<R>(a, ws, ws_bytes, s));
   }
   return ok();
 }
@@ -706,13 +823,13 @@ __global__ void make_d_kernel(const c128* A, const c128* B, int64_t ld, int a_co
 
 }  // namespace
 
-Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side) {
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
   if (a.kreal) return fail(CHASE_PH_ERR_ARG, "apply_h: K-real columns are a c128 mode");
-  return launch_any<float>(a, ws, ws_bytes, s, side, launch_one_f32);
+  return launch_any<float>(a, ws, ws_bytes, s);
 }
 
-Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s, const SideStream* side) {
-  return launch_any<double>(a, ws, ws_bytes, s, side, launch_one_f64);
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s) {
+  return launch_any<double>(a, ws, ws_bytes, s);
 }
 
 template <typename C>

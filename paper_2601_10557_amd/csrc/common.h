@@ -122,17 +122,9 @@ template <typename C>
 Err make_d(const c128* A, const c128* B, int64_t ld, int a_conj, C* D, int64_t ldd, int64_t m, hipStream_t s);
 
 // ws: device workspace for split-K partial products (ws_bytes may be 0:
-// then the K range is never split).
-// Optional side stream with fork / join events for splitting a launch by
-// columns (see launch_split in apply_h.hip); null disables the split.
-struct SideStream {
-  hipStream_t st = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-};
-Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s,
-                       const SideStream* side = nullptr);
-Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s,
-                       const SideStream* side = nullptr);
+// then the K range is never split, nor the columns).
+Err launch_apply_h_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s);
+Err launch_apply_h_f64(const ApplyHArgs<double>& a, void* ws, size_t ws_bytes, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Generic complex FP64 GEMM (zgemm.hip):
