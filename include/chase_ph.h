@@ -137,6 +137,8 @@ typedef struct {
   int32_t general_rr_used; /* iterations whose Rayleigh-Ritz used the general quotient      */
   int32_t nex_used;        /* extra search vectors of the solve (p->nex unless nex_auto)     */
   int32_t rr_sweeps_max;   /* most Jacobi sweeps one Rayleigh-Ritz step took                 */
+  int32_t qr_one_pass;     /* iterations whose Cholesky QR stopped after one pass (Q^H Q     */
+                           /* within 1e-13 of I after it: a well-conditioned block)          */
 } chase_ph_info;
 
 /* Defaults: deg 20, deg range 8..20, max_iter 25, gamma 1e-3, 26 Lanczos

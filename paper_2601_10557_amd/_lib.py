@@ -43,7 +43,7 @@ class Info(C.Structure):
         ("filter_flops_fp32", C.c_double), ("resid_history", C.POINTER(C.c_double)),
         ("resid_history_len", C.c_int32), ("householder_qr_used", C.c_int32),
         ("backup_rr_used", C.c_int32), ("general_rr_used", C.c_int32), ("nex_used", C.c_int32),
-        ("rr_sweeps_max", C.c_int32),
+        ("rr_sweeps_max", C.c_int32), ("qr_one_pass", C.c_int32),
     ]
 
 

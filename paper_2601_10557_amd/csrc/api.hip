@@ -91,6 +91,7 @@ struct chase_ph_s {
   double last_ms = 0;
   int last_launches = 0;
   int last_sweeps = 0;  // Jacobi sweeps of the last Alg. 2 Rayleigh-Ritz step
+  bool qr_one_pass = false;  // the last qr_impl stopped after one Cholesky QR pass
   std::string err;
   bool dead = false;
   std::vector<void*> allocs;
@@ -107,6 +108,9 @@ struct chase_ph_s {
 namespace {
 
 constexpr double U_ROUND = 1.1102230246251565e-16;
+// Largest deviation of Q^H Q from I after one Cholesky QR pass at which the
+// solver skips the second pass (the Rayleigh-Ritz step uses Q^H Q = I).
+constexpr double QR_ONE_PASS = 1e-13;
 // Indefinite S H: a Ritz pair with residual above this fraction of
 // |lambda~| is spurious and holds no place in the locking prefix.
 constexpr double SPURIOUS_REL = 0.1;
@@ -442,14 +446,19 @@ Err filter_any(chase_ph_t h, int k, void* dW, int64_t ldw, const std::vector<int
 
 // One Cholesky-QR pass: Xout = Xin L^{-H} with L L^H = Xin^H Xin + shift I.
 // real: Xin is real (held in c128), and so are the Gram matrix, L and Xout.
+// Lower triangle of the Gram matrix X^H X in Lbuf (padded with I).
+Err gram_lower(chase_ph_t h, int k, int kp, const c128* X, int64_t ldx, c128* Lbuf, bool real, int64_t nr) {
+  CHASE_TRY(fill_padded(Lbuf, kp, k, 0.0, 1.0, true, h->st));
+  return gemm(h, 1, 0, k, k, nr, {1, 0}, X, ldx, X, ldx, {0, 0}, Lbuf, kp, -1, true,
+              GEMM_LOWER_ONLY | (real ? GEMM_REAL : 0));
+}
+
 Err cholqr_pass(chase_ph_t h, int k, int kp, const c128* Xin, int64_t ldin, c128* Xout, int64_t ldout, c128* Lbuf,
-                double shift, bool* failed, bool real = false, int64_t rows = 0) {
+                double shift, bool* failed, bool real = false, int64_t rows = 0, bool gram_ready = false) {
   const int rf = real ? GEMM_REAL : 0;
   const int64_t nr = rows > 0 ? rows : h->n;
-  CHASE_TRY(fill_padded(Lbuf, kp, k, 0.0, 1.0, true, h->st));
   // Gram matrix: the Cholesky reads its lower triangle only
-  CHASE_TRY(gemm(h, 1, 0, k, k, nr, {1, 0}, Xin, ldin, Xin, ldin, {0, 0}, Lbuf, kp, -1, true,
-                 GEMM_LOWER_ONLY | rf));
+  if (!gram_ready) CHASE_TRY(gram_lower(h, k, kp, Xin, ldin, Lbuf, real, nr));
   if (shift != 0.0) CHASE_TRY(add_diag(Lbuf, kp, k, shift, h->st));
   CHASE_TRY(cholesky_lower(Lbuf, kp, h->dws, h->st, failed));
   if (*failed) return ok();
@@ -484,13 +493,33 @@ Err householder_fallback(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int
 Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int* used_shift,
             bool householder = true, bool real = false, int64_t rows = 0) {
   if (used_shift) *used_shift = 0;
+  h->qr_one_pass = false;
   if (k == 0) return ok();
   const int kp = pad64(k);
   const int64_t n = rows > 0 ? rows : h->n;
   bool failed = false;
   CHASE_TRY(cholqr_pass(h, k, kp, X, ldx, h->Xt, n, h->L1, 0.0, &failed, real, n));
   int nf = 2;
-  if (!failed) {
+  if (!failed && !R) {
+    // Section 2 chooses the orthonormalisation by condition number: when
+    // the first pass already left Q^H Q within QR_ONE_PASS of I (a
+    // well-conditioned block), the second pass is skipped
+    CHASE_TRY(gram_lower(h, k, kp, h->Xt, n, h->L2, real, n));
+    CHASE_TRY(gram_deviation(h->L2, kp, k, h->dws.dscalar, h->st));
+    double dev = 0;
+    CHASE_TRY(d2h_small(&dev, h->dws.dscalar, sizeof(double), h->dws, h->st));
+    if (dev <= QR_ONE_PASS) {
+      h->qr_one_pass = true;
+      CHASE_HIP(hipMemcpy2DAsync(X, ldx * sizeof(c128), h->Xt, n * sizeof(c128), n * sizeof(c128), k,
+                                 hipMemcpyDeviceToDevice, h->st));
+      return ok();
+    }
+    CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real, n, true));
+    if (failed) {
+      if (used_shift) *used_shift = 2;
+      return householder ? householder_fallback(h, k, X, ldx, R, ldr, 0, n) : ok();
+    }
+  } else if (!failed) {
     CHASE_TRY(cholqr_pass(h, k, kp, h->Xt, n, X, ldx, h->L2, 0.0, &failed, real, n));
     if (failed) {
       if (used_shift) *used_shift = 2;
@@ -1175,6 +1204,7 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     lq = locked;
     inf.shifted_qr_used += used == 1;
     inf.householder_qr_used += used == 2;
+    inf.qr_one_pass += h->qr_one_pass;
     CHASE_TRY(tm.stop(&inf.t_qr));
     // oblique RR on the non-locked part (Alg. 2)
     const c128* Q = h->Xs + (int64_t)2 * locked * n;
@@ -1402,6 +1432,7 @@ Err solve_tda_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, i
     CHASE_TRY(qr_impl(h, nevex, h->Xs, m, nullptr, 0, &used, true, false, m));
     inf.shifted_qr_used += used == 1;
     inf.householder_qr_used += used == 2;
+    inf.qr_one_pass += h->qr_one_pass;
     CHASE_TRY(tm.stop(&inf.t_qr));
     const c128* Q = h->Xs + (int64_t)locked * m;
     // Rayleigh-Ritz: G = Q^H (A Q), G Z = Z Omega, ascending

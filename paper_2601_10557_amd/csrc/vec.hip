@@ -143,6 +143,28 @@ __global__ void trace_kernel(const c128* G, int64_t ld, int k, double* out) {
   if (threadIdx.x == 0) *out = r;
 }
 
+// out = max over the lower triangle (i >= j, both < k) of |G_ij - delta_ij|
+// (one workgroup of 256).
+__global__ __launch_bounds__(256) void gram_deviation_kernel(const c128* G, int64_t ld, int k, double* out) {
+  __shared__ double red[256];
+  double v = 0;
+  const int64_t total = (int64_t)k * k;
+  for (int64_t t = threadIdx.x; t < total; t += 256) {
+    const int64_t j = t / k, i = t % k;
+    if (i < j) continue;
+    c128 g = G[j * ld + i];
+    if (i == j) g.re -= 1.0;
+    v = fmax(v, sqrt(g.re * g.re + g.im * g.im));
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
 __global__ void diag_real_kernel(const c128* G, int64_t ld, int k, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) out[i] = G[(int64_t)i * ld + i].re;
@@ -391,6 +413,12 @@ Err lanczos_advance(c128* vp, c128* v, c128* w, const c128* r, const c128* z, in
 
 Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
   hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, s, G, ld, k, dout);
+  CHASE_LAUNCH_CHECK();
+  return ok();
+}
+
+Err gram_deviation(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
+  hipLaunchKernelGGL(gram_deviation_kernel, dim3(1), dim3(256), 0, s, G, ld, k, dout);
   CHASE_LAUNCH_CHECK();
   return ok();
 }

@@ -117,6 +117,7 @@ class SolveInfo:
     general_rr_used: int = 0
     nex_used: int = 0
     rr_sweeps_max: int = 0
+    qr_one_pass: int = 0
 
 
 class PHSolver:
