@@ -122,6 +122,24 @@ def test_apply_h_column_split(prob, solver, k):
     assert np.max(np.abs(Y32 - ref32)) <= 1e-5 * np.max(np.abs(ref32))
 
 
+# the split launch with every main tile shape (the remainder keeps the
+# narrow one): one pair kernel per main shape, or two plain launches when
+# the main part is on the narrow shape too
+@pytest.mark.parametrize("plan", ["0,1", "0,3", "1,2", "2,4"])
+@pytest.mark.parametrize("k", [73, 145])
+def test_apply_h_column_split_every_main_plan(prob, solver, plan, k, monkeypatch):
+    print_case("apply_h_column_split_plan", m=prob.m, k=k, plan=plan)
+    monkeypatch.setenv("CHASE_PH_APPLY_PLAN", plan)
+    rng = np.random.default_rng(500 + k)
+    X = complex_normal(rng, (prob.n, k))
+    Y64 = to_host(solver.apply_h(to_dev(X)))
+    ref = ham.apply_h(prob.A, prob.B, X)
+    assert np.max(np.abs(Y64 - ref)) <= 1e-12 * np.max(np.abs(ref))
+    Y32 = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
+    ref32 = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
+    assert np.max(np.abs(Y32 - ref32)) <= 1e-5 * np.max(np.abs(ref32))
+
+
 def test_apply_h_more_columns_than_the_packed_buffer(prob, solver):
     # the packed operand holds 512 columns: k = 530 runs as 512 + 18
     print_case("apply_h_chunks", m=prob.m, k=530)
