@@ -505,7 +505,7 @@ Err qr_impl(chase_ph_t h, int k, c128* X, int64_t ldx, c128* R, int64_t ldr, int
     // the first pass already left Q^H Q within QR_ONE_PASS of I (a
     // well-conditioned block), the second pass is skipped
     CHASE_TRY(gram_lower(h, k, kp, h->Xt, n, h->L2, real, n));
-    CHASE_TRY(gram_deviation(h->L2, kp, k, h->dws.dscalar, h->st));
+    CHASE_TRY(gram_deviation(h->L2, kp, k, h->dres, h->dws.dscalar, h->st));
     double dev = 0;
     CHASE_TRY(d2h_small(&dev, h->dws.dscalar, sizeof(double), h->dws, h->st));
     if (dev <= QR_ONE_PASS) {

@@ -46,8 +46,9 @@ Err adjoint_contract(const c128* V, int64_t ldv, int64_t m, int nev, const doubl
 // host thread (adjoint.hip).
 const char* noalloc_last_error();
 Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s);
-// *dout = max |G_ij - delta_ij| over the lower triangle of the first k x k.
-Err gram_deviation(const c128* G, int64_t ld, int k, double* dout, hipStream_t s);
+// *dout = max |G_ij - delta_ij| over the lower triangle of the first k x k
+// (colmax: k doubles of device scratch).
+Err gram_deviation(const c128* G, int64_t ld, int k, double* colmax, double* dout, hipStream_t s);
 // dout[i] = Re G[i, i], i < k.
 Err diag_real(const c128* G, int64_t ld, int k, double* dout, hipStream_t s);
 Err add_diag(c128* G, int64_t ld, int k, double v, hipStream_t s);

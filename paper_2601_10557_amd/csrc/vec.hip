@@ -143,19 +143,30 @@ __global__ void trace_kernel(const c128* G, int64_t ld, int k, double* out) {
   if (threadIdx.x == 0) *out = r;
 }
 
-// out = max over the lower triangle (i >= j, both < k) of |G_ij - delta_ij|
-// (one workgroup of 256).
-__global__ __launch_bounds__(256) void gram_deviation_kernel(const c128* G, int64_t ld, int k, double* out) {
+// colmax[j] = max over i in [j, k) of |G_ij - delta_ij| (one workgroup per
+// column j < k); then out = max_j colmax[j] (one workgroup).
+__global__ __launch_bounds__(256) void gram_colmax_kernel(const c128* G, int64_t ld, int k, double* colmax) {
   __shared__ double red[256];
+  const int j = blockIdx.x;
   double v = 0;
-  const int64_t total = (int64_t)k * k;
-  for (int64_t t = threadIdx.x; t < total; t += 256) {
-    const int64_t j = t / k, i = t % k;
-    if (i < j) continue;
-    c128 g = G[j * ld + i];
+  for (int i = j + threadIdx.x; i < k; i += 256) {
+    c128 g = G[(int64_t)j * ld + i];
     if (i == j) g.re -= 1.0;
     v = fmax(v, sqrt(g.re * g.re + g.im * g.im));
   }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) colmax[j] = red[0];
+}
+
+__global__ __launch_bounds__(256) void max_reduce_kernel(const double* x, int k, double* out) {
+  __shared__ double red[256];
+  double v = 0;
+  for (int i = threadIdx.x; i < k; i += 256) v = fmax(v, x[i]);
   red[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -417,8 +428,11 @@ Err trace(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
   return ok();
 }
 
-Err gram_deviation(const c128* G, int64_t ld, int k, double* dout, hipStream_t s) {
-  hipLaunchKernelGGL(gram_deviation_kernel, dim3(1), dim3(256), 0, s, G, ld, k, dout);
+Err gram_deviation(const c128* G, int64_t ld, int k, double* colmax, double* dout, hipStream_t s) {
+  if (k <= 0) return ok();
+  hipLaunchKernelGGL(gram_colmax_kernel, dim3(k), dim3(256), 0, s, G, ld, k, colmax);
+  CHASE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, (const double*)colmax, k, dout);
   CHASE_LAUNCH_CHECK();
   return ok();
 }
