@@ -1266,9 +1266,9 @@ Err solve_impl(chase_ph_t h, const c128* W0, int64_t ldw0, const c128* Lz, int64
     if (verbose) {
       std::fprintf(stderr,
                    "[chase_ph] it=%d locked=%d kw=%d prec=%s n_fp64=%d nlock=%d ritz[0]=%.12g ritz[kw-1]=%.8g "
-                   "res[0]=%.3e res[nev-1]=%.3e res[kw-1]=%.3e mu_nevex=%.8g shifted=%d\n",
+                   "res[0]=%.3e res[nev-1]=%.3e res[kw-1]=%.3e mu_nevex=%.8g shifted=%d sweeps=%d\n",
                    it, locked, kw, g0 == kw ? "fp64" : (g1 ? "corr" : "fp32"), g0, nlock, ritz[0], ritz[kw - 1],
-                   res[0], res[std::min(nev - locked, kw) - 1], res[kw - 1], mu_nevex, used);
+                   res[0], res[std::min(nev - locked, kw) - 1], res[kw - 1], mu_nevex, used, h->last_sweeps);
     }
     locked += nlock;
     inf.iterations = it + 1;

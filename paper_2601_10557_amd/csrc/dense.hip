@@ -282,17 +282,25 @@ __device__ __forceinline__ int rr_player(int pos, int r, int n) {
   return ((pos - 1 + r) % (n - 1)) + 1;
 }
 
-// One cyclic Jacobi sweep on the 32 x 32 subproblem [[G_pp, G_pq],
-// [G_qp, G_qq]] of pair `pair` in round `round`: 31 steps of 16 disjoint
-// rotations (round-robin pairing).  Thread (a, b) = (tid % 16, tid / 16)
-// owns the 2 x 2 block of rotation a's rows and rotation b's columns and
-// rows b, b + 16 of rotation a's two columns of the accumulated unitary.
-// Every lane computes rotation a = lane % 16 from the step's input matrix
-// and takes rotation b from lane b of its own wave by a lane shuffle; the
-// matrix is double-buffered in LDS, so a step needs one barrier.  Writes U (32 x 32, column-major) to
-// Uw[pair] and flags the pair in pflag when it rotated; *count counts the
-// pairs that rotated.  A subproblem whose off-diagonal entries are all at or
-// below thr is left alone (U = I is implied by pflag = 0).
+// One Jacobi sweep on the 32 x 32 subproblem [[G_pp, G_pq], [G_qp, G_qq]]
+// of pair `pair` in round `round`, in steps of 16 disjoint rotations.
+// Round 0 of an outer sweep holds every block of G in exactly one pair, so
+// there the subproblem gets a full cyclic sweep (31 steps, round-robin
+// pairing) and every index pair inside a block is rotated once; the later
+// rounds (cross = 1) rotate only the 256 index pairs across the two blocks
+// (16 steps; step r pairs row i of block p with row (i + r) mod 16 of block
+// q).  The outer sweep thus meets every index pair of G once, as a cyclic
+// Jacobi sweep does.  Thread (a, b) = (tid % 16, tid / 16) owns the 2 x 2
+// block of rotation a's rows and rotation b's columns and rows b, b + 16 of
+// rotation a's two columns of the accumulated unitary.  Every lane computes
+// rotation a = lane % 16 from the step's input matrix and takes rotation b
+// from lane b of its own wave by a lane shuffle; the matrix is
+// double-buffered in LDS, so a step needs one barrier.  The unitary takes a
+// step's rotation one step late, while the next step's operands are read.
+// Writes U (32 x 32, column-major) to Uw[pair] and flags the pair in pflag
+// when it rotated; *count counts the pairs that rotated.  A subproblem whose
+// off-diagonal entries are all at or below thr is left alone (U = I is
+// implied by pflag = 0).
 __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t ld, int nbj, int round, c128* Uw,
                                                          double thr, int max_sweeps, int* count, int* pflag) {
   __shared__ c128 S[2][SP][SP + 1];
@@ -313,24 +321,53 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
   }
   const bool needed = __syncthreads_or(big);
   const int a = tid % (SP / 2), b = tid / (SP / 2);
+  const bool cross = round > 0;
+  const int nsteps = cross ? JB : SP - 1;
   int total = 0;
+  // U <- U J on the columns (up, uq) of a rotation (c, s), rows b and b + 16
+  auto rotate_u = [&](int up_col, int uq_col, double c, c128 sr) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int i = b + (SP / 2) * v;
+      const c128 up = U[i][up_col], uq = U[i][uq_col];
+      U[i][up_col] = csub(cscale(c, up), cmul(cconj(sr), uq));
+      U[i][uq_col] = cadd(cmul(sr, up), cscale(c, uq));
+    }
+  };
   for (int sweep = 0; needed && sweep < max_sweeps; ++sweep) {
     int did_any = 0;
-    for (int r = 0; r < SP - 1; ++r) {
+    int lp = 0, lq = 0;  // the previous step's rotation a, not yet applied to U
+    double lc = 1.0;
+    c128 ls{0.0, 0.0};
+    for (int r = 0; r < nsteps; ++r) {
       const c128 (*cur)[SP + 1] = S[r & 1];
       c128 (*nxt)[SP + 1] = S[(r + 1) & 1];
-      const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
-      const int pb0 = rr_player(b, r, SP), qb0 = rr_player(SP - 1 - b, r, SP);
-      const int pa = min(pa0, qa0), qa = max(pa0, qa0), pb = min(pb0, qb0), qb = max(pb0, qb0);
+      int pa, qa, pb, qb;
+      if (cross) {
+        pa = a;
+        qa = JB + ((a + r) & (JB - 1));
+        pb = b;
+        qb = JB + ((b + r) & (JB - 1));
+      } else {
+        const int pa0 = rr_player(a, r, SP), qa0 = rr_player(SP - 1 - a, r, SP);
+        const int pb0 = rr_player(b, r, SP), qb0 = rr_player(SP - 1 - b, r, SP);
+        pa = min(pa0, qa0);
+        qa = max(pa0, qa0);
+        pb = min(pb0, qb0);
+        qb = max(pb0, qb0);
+      }
+      const double app = cur[pa][pa].re, aqq = cur[qa][qa].re;
+      const c128 apq = cur[pa][qa];
+      const c128 x00 = cur[pa][pb], x01 = cur[pa][qb], x10 = cur[qa][pb], x11 = cur[qa][qb];
+      if (r > 0) rotate_u(lp, lq, lc, ls);
       double ca, ta;
       c128 sa;
       int da;
-      jacobi_rot(cur[pa][pa].re, cur[qa][qa].re, cur[pa][qa], thr, ca, sa, ta, da);
+      jacobi_rot(app, aqq, apq, thr, ca, sa, ta, da);
       did_any |= da;
       // rotation b was computed by lane b of this wave (lane % 16 == b)
       const double cb = __shfl(ca, b);
       const c128 sb{__shfl(sa.re, b), __shfl(sa.im, b)};
-      const c128 x00 = cur[pa][pb], x01 = cur[pa][qb], x10 = cur[qa][pb], x11 = cur[qa][qb];
       // rows: row_p' = c row_p - s row_q ; row_q' = conj(s) row_p + c row_q
       const c128 y00 = csub(cscale(ca, x00), cmul(sa, x10));
       const c128 y01 = csub(cscale(ca, x01), cmul(sa, x11));
@@ -356,15 +393,16 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
       nxt[pa][qb] = z01;
       nxt[qa][pb] = z10;
       nxt[qa][qb] = z11;
-      // U <- U J on the columns of rotation a
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int i = b + (SP / 2) * v;
-        const c128 up = U[i][pa], uq = U[i][qa];
-        U[i][pa] = csub(cscale(ca, up), cmul(cconj(sa), uq));
-        U[i][qa] = cadd(cmul(sa, up), cscale(ca, uq));
-      }
+      lp = pa;
+      lq = qa;
+      lc = ca;
+      ls = sa;
       __syncthreads();
+    }
+    rotate_u(lp, lq, lc, ls);
+    // the sweep's result is in S[nsteps & 1]; a further sweep starts from S[0]
+    if ((nsteps & 1) && sweep + 1 < max_sweeps) {
+      for (int t = tid; t < SP * SP; t += 256) S[0][t % SP][t / SP] = S[1][t % SP][t / SP];
     }
     if (!__syncthreads_or(did_any)) break;
     ++total;
