@@ -448,10 +448,13 @@ __device__ __forceinline__ void cgemm_tile32(int lane, FA a, FB b, doublex4& cr,
 }
 
 // G <- J^H G J with J block-diagonal (one 32 x 32 U per pair, in the pair's
-// index set); block (a, b) of pairs is U_a^H G_ab U_b.  Also V <- V J on
-// row chunks of 32.  blockIdx.x < npair^2: G blocks; the rest: V blocks.
-// The data block and the rotation blocks are staged in LDS; each of the four
-// waves computes one 16 x 16 quarter of each 32 x 32 product on MFMA.
+// index set); block (a, b) of pairs is U_a^H G_ab U_b.  G stays Hermitian,
+// so only the blocks a <= b are formed and each is also written, conjugate
+// transposed, to (b, a) (a diagonal block from its upper triangle).  Also
+// V <- V J on row chunks of 32.  blockIdx.x < npair (npair + 1) / 2: G
+// blocks; the rest: V blocks.  The data block and the rotation blocks are
+// staged in LDS; each of the four waves computes one 16 x 16 quarter of each
+// 32 x 32 product on MFMA.
 __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int64_t ld, int kp, int nbj, int round,
                                                            const c128* Uw, const int* pflag) {
   __shared__ c128 X[SP][SP + 1];
@@ -463,8 +466,15 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
   const int r0 = (wave >> 1) * 16, c0 = (wave & 1) * 16;  // this wave's quarter
   int blk = blockIdx.x;
   doublex4 cr, ci;
-  if (blk < npair * npair) {
-    const int a = blk / npair, b = blk % npair;
+  const int ntri = npair * (npair + 1) / 2;
+  if (blk < ntri) {
+    // blk -> (a, b), a <= b, row by row of the upper triangle
+    int a = 0, rest = blk;
+    while (rest >= npair - a) {
+      rest -= npair - a;
+      ++a;
+    }
+    const int b = a + rest;
     const bool ua = pflag[a], ub = pflag[b];
     if (!ua && !ub) return;  // both rotations are the identity
     const c128* Ua = Uw + (int64_t)a * SP * SP;
@@ -505,11 +515,19 @@ __global__ __launch_bounds__(256) void jacobi_apply_kernel(c128* G, c128* V, int
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = r0 + (lane >> 4) + 4 * r, j = c0 + (lane & 15);
-      const c128 v{cr[r], (a == b && i == j) ? 0.0 : ci[r]};
-      G[(int64_t)sub_index(b, round, nbj, j) * ld + sub_index(a, round, nbj, i)] = v;
+      const int gi = sub_index(a, round, nbj, i), gj = sub_index(b, round, nbj, j);
+      if (a != b) {
+        G[(int64_t)gj * ld + gi] = c128{cr[r], ci[r]};
+        G[(int64_t)gi * ld + gj] = c128{cr[r], -ci[r]};
+      } else if (i < j) {
+        G[(int64_t)gj * ld + gi] = c128{cr[r], ci[r]};
+        G[(int64_t)gi * ld + gj] = c128{cr[r], -ci[r]};
+      } else if (i == j) {
+        G[(int64_t)gj * ld + gi] = c128{cr[r], 0.0};
+      }
     }
   } else {
-    blk -= npair * npair;
+    blk -= ntri;
     const int a = blk % npair, rb = blk / npair;  // pair, row chunk
     if (!pflag[a]) return;
     const c128* Ua = Uw + (int64_t)a * SP * SP;
@@ -727,7 +745,7 @@ Err jacobi_eigh(c128* G, c128* V, int kp, DenseWs& ws, hipStream_t s, int max_sw
       hipLaunchKernelGGL(jacobi_sub_kernel, dim3(npair), dim3(256), 0, s, (const c128*)G, (int64_t)kp, nbj, r,
                          ws.U, thr, inner_sweeps, ws.flag, ws.pflag);
       CHASE_LAUNCH_CHECK();
-      const int blocks = npair * npair + npair * (kp / SP);
+      const int blocks = npair * (npair + 1) / 2 + npair * (kp / SP);
       hipLaunchKernelGGL(jacobi_apply_kernel, dim3(blocks), dim3(256), 0, s, G, V, (int64_t)kp, kp, nbj, r,
                          (const c128*)ws.U, (const int*)ws.pflag);
       CHASE_LAUNCH_CHECK();
