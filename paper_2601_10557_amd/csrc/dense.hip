@@ -134,6 +134,10 @@ __device__ __forceinline__ void chol64(c128 (*S)[NB + 1], double* piv, int* fail
 template <int L>
 __device__ __forceinline__ double row_share(double x) { return dpp_swap<0x150 + L>(x); }
 
+// Lane l of each row of 16 lanes takes the value of lane (l + 1) mod 16
+// (DPP row_ror:15).
+__device__ __forceinline__ double row_next(double x) { return dpp_swap<0x12F>(x); }
+
 // f(std::integral_constant<int, B>), ..., f(std::integral_constant<int, E - 1>)
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -296,7 +300,8 @@ __device__ __forceinline__ int rr_player(int pos, int r, int n) {
 // rotation a = lane % 16 from the step's input matrix and takes rotation b
 // from lane b of its own wave by a lane shuffle; the matrix is
 // double-buffered in LDS, so a step needs one barrier.  The unitary takes a
-// step's rotation one step late, while the next step's operands are read.
+// step's rotation one step late, while the next step's operands are read
+// (round 0), or holds it in registers (the cross rounds, below).
 // Writes U (32 x 32, column-major) to Uw[pair] and flags the pair in pflag
 // when it rotated; *count counts the pairs that rotated.  A subproblem whose
 // off-diagonal entries are all at or below thr is left alone (U = I is
@@ -334,6 +339,12 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
       U[i][uq_col] = cadd(cmul(sr, up), cscale(c, uq));
     }
   };
+  // In the cross rounds U stays in registers: thread (a, b) holds U[b][a]
+  // and U[b + 16][a] (its rotation's fixed column) and U[b][q], U[b + 16][q]
+  // for the step's partner column q = 16 + (a + r) mod 16, which passes one
+  // lane down the row of 16 lanes (DPP row rotation) after each step; after
+  // the 16 steps q is 16 + a again.
+  c128 up0{a == b ? 1.0 : 0.0, 0.0}, up1{0.0, 0.0}, uq0{0.0, 0.0}, uq1{a == b ? 1.0 : 0.0, 0.0};
   for (int sweep = 0; needed && sweep < max_sweeps; ++sweep) {
     int did_any = 0;
     int lp = 0, lq = 0;  // the previous step's rotation a, not yet applied to U
@@ -359,7 +370,7 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
       const double app = cur[pa][pa].re, aqq = cur[qa][qa].re;
       const c128 apq = cur[pa][qa];
       const c128 x00 = cur[pa][pb], x01 = cur[pa][qb], x10 = cur[qa][pb], x11 = cur[qa][qb];
-      if (r > 0) rotate_u(lp, lq, lc, ls);
+      if (!cross && r > 0) rotate_u(lp, lq, lc, ls);
       double ca, ta;
       c128 sa;
       int da;
@@ -393,13 +404,25 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
       nxt[pa][qb] = z01;
       nxt[qa][pb] = z10;
       nxt[qa][qb] = z11;
+      if (cross) {
+        // U <- U J on columns a and q: col_a' = c col_a - conj(s) col_q,
+        // col_q' = s col_a + c col_q; then q moves on (lane a takes lane a + 1's)
+        const c128 n0 = csub(cscale(ca, up0), cmul(cconj(sa), uq0));
+        const c128 m0 = cadd(cmul(sa, up0), cscale(ca, uq0));
+        const c128 n1 = csub(cscale(ca, up1), cmul(cconj(sa), uq1));
+        const c128 m1 = cadd(cmul(sa, up1), cscale(ca, uq1));
+        up0 = n0;
+        up1 = n1;
+        uq0 = c128{row_next(m0.re), row_next(m0.im)};
+        uq1 = c128{row_next(m1.re), row_next(m1.im)};
+      }
       lp = pa;
       lq = qa;
       lc = ca;
       ls = sa;
       __syncthreads();
     }
-    rotate_u(lp, lq, lc, ls);
+    if (!cross) rotate_u(lp, lq, lc, ls);
     // the sweep's result is in S[nsteps & 1]; a further sweep starts from S[0]
     if ((nsteps & 1) && sweep + 1 < max_sweeps) {
       for (int t = tid; t < SP * SP; t += 256) S[0][t % SP][t / SP] = S[1][t % SP][t / SP];
@@ -413,6 +436,13 @@ __global__ __launch_bounds__(256) void jacobi_sub_kernel(const c128* G, int64_t 
   }
   if (total == 0) return;
   c128* Uo = Uw + (int64_t)pair * SP * SP;
+  if (cross) {
+    Uo[a * SP + b] = up0;
+    Uo[a * SP + b + JB] = up1;
+    Uo[(JB + a) * SP + b] = uq0;
+    Uo[(JB + a) * SP + b + JB] = uq1;
+    return;
+  }
   for (int t = tid; t < SP * SP; t += 256) {
     const int j = t / SP, i = t % SP;
     Uo[(int64_t)j * SP + i] = U[i][j];
