@@ -12,8 +12,7 @@
 namespace chase {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-constexpr int LDS_A = BM + 2, LDS_B = BN + 2;
+constexpr int BK = 16, NT = 256;
 
 typedef double doublex2 __attribute__((ext_vector_type(2)));
 
@@ -35,12 +34,18 @@ struct ZgemmDev {
   int lower_only, a_lower, b_upper;
   int real_data;
   int splits;
+  int tb;          // square tile of the launch (64 or 32)
   int64_t kchunk;  // K range per split (multiple of BK)
   c128* ws;        // splits * batch * M * N partials (split-K only)
 };
 
-template <bool REAL>
+// TB x TB output tiles (64, or 32 for products too small to fill the CUs
+// with 64 x 64 tiles); each of the four waves owns a TB/2 x TB/2 quarter of
+// FR x FR MFMA tiles of 16 x 16.
+template <bool REAL, int TB>
 __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
+  constexpr int BM = TB, BN = TB, FR = TB / 32;
+  constexpr int LDS_A = BM + 2, LDS_B = BN + 2;
   __shared__ double As[2][2][BK][LDS_A];
   __shared__ double Bs[2][2][BK][LDS_B];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -59,9 +64,9 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
   const int64_t kbeg = (int64_t)sp * g.kchunk;
   const int64_t kend = min(klim, kbeg + g.kchunk);
   const int KT = (int)((kend - kbeg + BK - 1) / BK);
-  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+  const int wm0 = (wave >> 1) * (TB / 2), wn0 = (wave & 1) * (TB / 2);
 
-  constexpr int PER = BM * BK / NT;  // 4 elements of each operand per thread
+  constexpr int PER = BM * BK / NT;  // 4 (TB 64) or 2 elements of each operand per thread
   // raw loads (clamped addresses) plus validity bits; conj / sign are applied
   // when the tile is written to LDS, after the MFMAs of the previous slab
   doublex2 ra[PER], rb[PER];
@@ -117,11 +122,11 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
     }
   };
 
-  doublex4 cr[2][2], ci[2][2];
+  doublex4 cr[FR][FR], ci[FR][FR];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FR; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FR; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { cr[i][j][r] = 0; ci[i][j][r] = 0; }
 
@@ -136,35 +141,35 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
     if (kt + 1 < KT) load(kt + 1);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double fa_r[2], fa_i[2], fb_r[2], fb_i[2], fb_n[2];
+      double fa_r[FR], fa_i[FR], fb_r[FR], fb_i[FR], fb_n[FR];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < FR; ++i) {
         fa_r[i] = As[buf][0][ks + lk][wm0 + 16 * i + lr];
         fa_i[i] = As[buf][1][ks + lk][wm0 + 16 * i + lr];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < FR; ++j) {
         fb_r[j] = Bs[buf][0][ks + lk][wn0 + 16 * j + lr];
         fb_i[j] = Bs[buf][1][ks + lk][wn0 + 16 * j + lr];
         fb_n[j] = -fb_i[j];
       }
       if constexpr (REAL) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FR; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
+          for (int j = 0; j < FR; ++j) cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
       } else {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FR; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < FR; ++j) {
             cr[i][j] = mfma64(fa_r[i], fb_r[j], cr[i][j]);
             ci[i][j] = mfma64(fa_r[i], fb_i[j], ci[i][j]);
           }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FR; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < FR; ++j) {
             cr[i][j] = mfma64(fa_i[i], fb_n[j], cr[i][j]);
             ci[i][j] = mfma64(fa_i[i], fb_r[j], ci[i][j]);
           }
@@ -176,9 +181,9 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZgemmDev g) {
 
   const int batch = gridDim.y;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FR; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FR; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = m0 + wm0 + 16 * i + (lane >> 4) + 4 * r;
@@ -209,7 +214,7 @@ __global__ void zgemm_reduce(const ZgemmDev g, int batch) {
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t bt = t / (g.M * g.N), rem = t % (g.M * g.N);
     const int64_t gj = rem / g.M, gi = rem % g.M;
-    if (g.lower_only && gi / BM < gj / BN) continue;  // tile not computed
+    if (g.lower_only && gi / g.tb < gj / g.tb) continue;  // tile not computed
     double sr = 0, si = 0;
     for (int s = 0; s < g.splits; ++s) {
       c128 w = g.ws[((int64_t)s * batch + bt) * g.M * g.N + rem];
@@ -240,8 +245,14 @@ Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   g.kneg = a.kneg;
   g.lower_only = a.lower_only; g.a_lower = a.a_lower; g.b_upper = a.b_upper;
   g.real_data = a.real_data;
-  const int64_t tiles = ceil_div(a.M, BM) * ceil_div(a.N, BN);
-  const int64_t tm = ceil_div(a.M, BM);
+  // 32 x 32 tiles when 64 x 64 ones would leave most CUs idle and K is too
+  // short for a split: a 64 x 64 x 64 complex tile is about 7 us of one CU's
+  // FP64 MFMA, a 32 x 32 one a quarter of that
+  const int64_t t64 = ceil_div(a.M, (int64_t)64) * ceil_div(a.N, (int64_t)64) * a.batch;
+  const int tb = (t64 < 128 && a.K <= 256) ? 32 : 64;
+  g.tb = tb;
+  const int64_t tiles = ceil_div(a.M, (int64_t)tb) * ceil_div(a.N, (int64_t)tb);
+  const int64_t tm = ceil_div(a.M, (int64_t)tb);
   const int64_t work_tiles = a.lower_only ? tm * (tm + 1) / 2 : tiles;  // tiles that compute
   int splits = 1;
   if (a.K > 0 && ws && work_tiles * a.batch < 512) {
@@ -257,12 +268,14 @@ Err zgemm(const ZgemmArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
   splits = (int)ceil_div(std::max<int64_t>(a.K, 1), g.kchunk);
   g.splits = splits;
   g.ws = (c128*)ws;
-  if (a.real_data)
-    hipLaunchKernelGGL(zgemm_kernel<true>, dim3((unsigned)tiles, (unsigned)a.batch, (unsigned)splits), dim3(NT), 0,
-                       s, g);
-  else
-    hipLaunchKernelGGL(zgemm_kernel<false>, dim3((unsigned)tiles, (unsigned)a.batch, (unsigned)splits), dim3(NT), 0,
-                       s, g);
+  const dim3 grid((unsigned)tiles, (unsigned)a.batch, (unsigned)splits);
+  if (a.real_data) {
+    if (tb == 32) hipLaunchKernelGGL((zgemm_kernel<true, 32>), grid, dim3(NT), 0, s, g);
+    else hipLaunchKernelGGL((zgemm_kernel<true, 64>), grid, dim3(NT), 0, s, g);
+  } else {
+    if (tb == 32) hipLaunchKernelGGL((zgemm_kernel<false, 32>), grid, dim3(NT), 0, s, g);
+    else hipLaunchKernelGGL((zgemm_kernel<false, 64>), grid, dim3(NT), 0, s, g);
+  }
   CHASE_LAUNCH_CHECK();
   if (splits > 1) {
     const int64_t total = (int64_t)a.batch * a.M * a.N;
