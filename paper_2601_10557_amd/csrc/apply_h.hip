@@ -259,7 +259,7 @@ struct Cfg {
   static constexpr int WTM = BM / WGM, WTN = BN / WGN;   // wave tile
   static constexpr int FM = WTM / Tr::MB, FN = WTN / Tr::NB;
   static constexpr int CW = 64 * V / 2;                  // Y columns per copy (one row pair)
-  static constexpr int BNP = BN < CW ? CW : BN;           // Y columns per LDS row pair
+  static constexpr int BNP = (BN + CW - 1) / CW * CW;     // Y columns per LDS row pair
   // k-row pitch of the M stage: a 32-lane half of a wave reads 32 words of
   // one k row and the other half the next k row (f32); half a pitch of 32
   // words puts the two halves on disjoint banks (f64: 16 doubles)
@@ -755,6 +755,25 @@ struct PrecOps<double> {
   }
 };
 
+// c64 products with 64 < k <= 80 (2k = 130 .. 160 real columns) run on one
+// column of wide tiles (256 x 160, 5 MFMA column blocks per wave, K slab 8 so
+// that the ring stays within two workgroups per CU), which streams M once,
+// instead of a 128-wide main column and a narrow remainder that streams M
+// again (k = 73: 226 -> 211 us on m = 4000).  For larger k the same wide
+// column after the main tiles was slower than the narrow remainder (k = 260:
+// 642 against 595 us, also with a 16-deep slab and two stages), so those keep
+// the split below.
+constexpr int WIDE_REM = 16;
+constexpr int WIDE_BN = 160, WIDE_BK = 8;
+
+Err launch_wide_f32(const ApplyHArgs<float>& a, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int bm[1] = {256}, bn[1] = {WIDE_BN}, bk[1] = {WIDE_BK}, occ[1] = {2};
+  const double eff[1] = {1.0};
+  const Plan p = make_plan<1>(2 * a.m, 2 * (int64_t)a.k, bm, bn, bk, eff, occ, F32Tiles::split_penalty,
+                              sizeof(float), ws_bytes, 1);
+  return launch_cfg<TF32, 256, WIDE_BN, WIDE_BK, 3, 4, 1, 1>(a, p, ws, s);
+}
+
 // When 2k is a few columns past a multiple of 128, the width of the widest
 // tiles (e.g. k = 260 or k = 73; k >= 64), the last tile column of a plain
 // launch is mostly padding.  The product is then split by columns (H X is
@@ -770,6 +789,10 @@ Err launch_split(const ApplyHArgs<R>& a, void* ws, size_t ws_bytes, hipStream_t 
   constexpr int gran = 64;
   const int krem = a.k % gran;
   constexpr int rmax = 20;
+  if constexpr (sizeof(R) == 4) {
+    if (a.k > gran && a.k <= gran + WIDE_REM && !a.kreal && !a.tda)
+      return launch_wide_f32(a, ws, ws ? ws_bytes : 0, s);
+  }
   if (!ws || krem == 0 || krem > rmax || a.k < gran || a.kreal || a.tda)
     return Ops::one(a, plan_for<typename Ops::Tiles>(a, ws ? ws_bytes : 0, false), ws, s);
   ApplyHArgs<R> am = a, ar = a;

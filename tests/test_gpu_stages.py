@@ -108,7 +108,8 @@ def test_apply_h_fp64_every_tile_plan(prob, solver, plan, k, monkeypatch):
 
 
 # 2k a few columns past a multiple of 128 (k % 64 <= 20; k >= 64): the
-# library splits the launch by columns over two streams
+# library splits the launch by columns, in one launch (c64 with 64 < k <= 80:
+# one column of wide tiles instead)
 @pytest.mark.parametrize("k", [73, 84, 132, 145, 260])
 def test_apply_h_column_split(prob, solver, k):
     print_case("apply_h_column_split", m=prob.m, k=k)
@@ -117,6 +118,19 @@ def test_apply_h_column_split(prob, solver, k):
     Y64 = to_host(solver.apply_h(to_dev(X)))
     ref = ham.apply_h(prob.A, prob.B, X)
     assert np.max(np.abs(Y64 - ref)) <= 1e-12 * np.max(np.abs(ref))
+    Y32 = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
+    ref32 = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
+    assert np.max(np.abs(Y32 - ref32)) <= 1e-5 * np.max(np.abs(ref32))
+
+
+# c64 products with 64 < k <= 80 on one column of wide tiles (256 x 160): 2k
+# up to exactly the tile width (k = 80) and ragged (k = 65, 73); k = 81 and
+# k = 132 take the split launch beside them
+@pytest.mark.parametrize("k", [65, 73, 80, 81, 132])
+def test_apply_h_fp32_wide_last_column(prob, solver, k):
+    print_case("apply_h_fp32_wide", m=prob.m, k=k)
+    rng = np.random.default_rng(450 + k)
+    X = complex_normal(rng, (prob.n, k))
     Y32 = to_host(solver.apply_h(to_dev(X, torch.complex64), prec=FP32)).astype(np.complex128)
     ref32 = ham.apply_h(prob.A, prob.B, X.astype(np.complex64).astype(np.complex128))
     assert np.max(np.abs(Y32 - ref32)) <= 1e-5 * np.max(np.abs(ref32))
