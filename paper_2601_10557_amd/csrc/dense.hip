@@ -55,15 +55,16 @@ __global__ void zero_upper_kernel(c128* M, int64_t ld, int kp) {
 }
 
 // ------------------------------------------------------- Cholesky block
-// 64 x 64 blocks held in LDS, 1024 threads: each row (Cholesky) or column
-// (inverse) has a row of 16 lanes, which split its dot products and combine
-// them with DPP lane swaps.
-constexpr int PT = 16;          // lanes per row / column
-constexpr int PTHREADS = NB * PT;
+// 64 x 64 diagonal blocks, 256 threads.  Lane i of every wave holds row i
+// (Cholesky) or column i (inverse), and wave w the 16 columns (rows)
+// w, w + 4, ..., w + 60 in registers: interleaved, so that the four waves
+// share the shrinking trailing part evenly.  A step publishes one column
+// (row) through LDS, double-buffered, so it takes one barrier, and every
+// other operand of the step is a broadcast LDS read.
+constexpr int CT = 256;     // threads of the block kernels
+constexpr int CW = NB / 4;  // columns (rows) per wave
 
-// Lane exchange inside a row of 16 lanes by DPP (no LDS round trip):
-// quad_perm 0xB1 swaps lanes 0<->1 and 2<->3 of each quad, 0x4E swaps
-// 0<->2 and 1<->3, 0x141 mirrors each half row of 8, 0x140 mirrors the row.
+// Lane exchange inside a row of 16 lanes by DPP (no LDS round trip).
 template <int CTRL>
 __device__ __forceinline__ double dpp_swap(double x) {
   const long long b = __double_as_longlong(x);
@@ -71,68 +72,6 @@ __device__ __forceinline__ double dpp_swap(double x) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-
-// Sum over the 16 lanes of a row.  Each stage adds a value and its exact
-// partner (x + y and y + x round alike), so all 16 lanes end with the same
-// bits.
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_swap<0xB1>(v);
-  v += dpp_swap<0x4E>(v);
-  v += dpp_swap<0x141>(v);
-  v += dpp_swap<0x140>(v);
-  return v;
-}
-
-__device__ __forceinline__ c128 row16_sum(c128 v) { return c128{row16_sum(v.re), row16_sum(v.im)}; }
-
-// In place lower Cholesky S = L L^H, right-looking in LDL^H form: step j
-// takes the pivot d_j = S[j][j] and applies the rank-1 update
-// S[i][l] -= S[i][j] conj(S[l][j]) / d_j to the lower trailing block, so a
-// step needs one barrier and no cross-lane reduction; the columns are scaled
-// by 1 / sqrt(d_j) at the end.  Row i is updated by the 16 lanes of row
-// group i, four columns each.  A non-positive or non-finite pivot sets
-// *fail and is replaced by 1 so that the block stays finite (the host then
-// discards the result).
-__device__ __forceinline__ void chol64(c128 (*S)[NB + 1], double* piv, int* fail) {
-  const int tid = threadIdx.x, i = tid / PT, part = tid % PT;
-  for (int j = 0; j < NB; ++j) {
-    double d = S[j][j].re;
-    if (!(d > 0.0) || !isfinite(d)) d = 1.0;
-    const double inv = 1.0 / d;
-    if (i > j) {
-      const c128 sij = cscale(inv, S[i][j]);
-      c128 lj[NB / PT], sil[NB / PT];
-#pragma unroll
-      for (int t = 0; t < NB / PT; ++t) {
-        const int l = min(j + 1 + part + PT * t, NB - 1);
-        lj[t] = S[l][j];
-        sil[t] = S[i][l];
-      }
-#pragma unroll
-      for (int t = 0; t < NB / PT; ++t) {
-        const int l = j + 1 + part + PT * t;
-        if (l <= i) S[i][l] = csub(sil[t], cmul(sij, cconj(lj[t])));
-      }
-    }
-    __syncthreads();
-  }
-  if (tid < NB) {
-    const double d = S[tid][tid].re;
-    if (!(d > 0.0) || !isfinite(d)) atomicOr(fail, 1);
-    piv[tid] = (d > 0.0 && isfinite(d)) ? sqrt(d) : 1.0;
-  }
-  __syncthreads();
-  for (int t = tid; t < NB * NB; t += PTHREADS) {
-    const int jj = t / NB, ii = t % NB;
-    if (ii > jj) S[ii][jj] = cscale(1.0 / piv[jj], S[ii][jj]);
-    else if (ii == jj) S[ii][jj] = c128{piv[jj], 0.0};
-  }
-  __syncthreads();
-}
-
-// Broadcast lane L of each row of 16 lanes to the whole row (DPP row_share).
-template <int L>
-__device__ __forceinline__ double row_share(double x) { return dpp_swap<0x150 + L>(x); }
 
 // Lane l of each row of 16 lanes takes the value of lane (l + 1) mod 16
 // (DPP row_ror:15).
@@ -147,98 +86,6 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// I = L^{-1} for the lower-triangular L in S, by column sweeps: the 16 lanes
-// of column c hold its right-hand side (rows part + 16 t); at step i the
-// lane holding row i forms x_i = b_i / L[i][i], shares it across the row of
-// lanes by DPP, and every lane updates b_r -= L[r][i] x_i for its rows
-// r > i.  No barrier and no LDS round trip inside the sweep.  The rows are
-// swept in blocks of 16; after each block the registers shift down one block
-// so that the current block is always b[0] (no dynamic register index).
-// Needs the reciprocal pivots in rpiv (1 / L[i][i]).
-__device__ __forceinline__ void trinv64(const c128 (*S)[NB + 1], const double* rpiv, c128 (*I)[NB + 1]) {
-  constexpr int NT = NB / PT;
-  const int tid = threadIdx.x, c = tid / PT, part = tid % PT;
-  c128 b[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) b[t] = (part + PT * t == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
-#pragma unroll 1
-  for (int t0 = 0; t0 < NT; ++t0) {
-    static_for<0, PT>([&](auto U) {
-      constexpr int u = decltype(U)::value;
-      const int i = PT * t0 + u;
-      // x_i on the lane that holds row i (lane u of the row); shared to all
-      const c128 xl = cscale(rpiv[i], b[0]);
-      const c128 x{row_share<u>(xl.re), row_share<u>(xl.im)};
-      if (part == 0) I[i][c] = x;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int r = part + PT * (t0 + t);
-        const c128 l = S[min(r, NB - 1)][i];
-        if (r > i && r < NB) b[t] = csub(b[t], cmul(l, x));
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    });
-#pragma unroll
-    for (int t = 0; t + 1 < NT; ++t) b[t] = b[t + 1];
-  }
-}
-
-// Factor the 64 x 64 diagonal block at (p, p): writes L_pp (lower, upper
-// zeroed) in place and L_pp^{-1} into inv (64 x 64, ld 64).
-__global__ __launch_bounds__(PTHREADS) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
-  __shared__ c128 S[NB][NB + 1];
-  __shared__ c128 I[NB][NB + 1];
-  __shared__ double piv[NB];
-  const int tid = threadIdx.x;
-  for (int t = tid; t < NB * NB; t += PTHREADS) {
-    const int j = t / NB, i = t % NB;
-    S[i][j] = M[(int64_t)(p + j) * ld + p + i];
-  }
-  __syncthreads();
-  chol64(S, piv, fail);
-  if (tid < NB) piv[tid] = 1.0 / piv[tid];
-  __syncthreads();
-  trinv64(S, piv, I);
-  __syncthreads();
-  for (int t = tid; t < NB * NB; t += PTHREADS) {
-    const int j = t / NB, i = t % NB;
-    M[(int64_t)(p + j) * ld + p + i] = (i >= j) ? S[i][j] : c128{0.0, 0.0};
-    inv[(int64_t)j * NB + i] = (i >= j) ? I[i][j] : c128{0.0, 0.0};
-  }
-}
-
-__global__ void copy_block_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int rows, int cols) {
-  const int64_t total = (int64_t)rows * cols;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = t / rows, i = t % rows;
-    dst[j * ldd + i] = src[j * lds + i];
-  }
-}
-
-// Invert each 64 x 64 diagonal block of a lower-triangular L (padded) and
-// write it into the diagonal of Linv.
-__global__ __launch_bounds__(PTHREADS) void trinv_diag_kernel(const c128* L, c128* X, int64_t ld) {
-  __shared__ c128 S[NB][NB + 1];
-  __shared__ c128 I[NB][NB + 1];
-  __shared__ double rpiv[NB];
-  const int p = blockIdx.x * NB;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < NB * NB; t += PTHREADS) {
-    const int j = t / NB, i = t % NB;
-    S[i][j] = L[(int64_t)(p + j) * ld + p + i];
-  }
-  __syncthreads();
-  if (tid < NB) rpiv[tid] = 1.0 / S[tid][tid].re;
-  __syncthreads();
-  trinv64(S, rpiv, I);
-  __syncthreads();
-  for (int t = tid; t < NB * NB; t += PTHREADS) {
-    const int j = t / NB, i = t % NB;
-    X[(int64_t)(p + j) * ld + p + i] = (i >= j) ? I[i][j] : c128{0.0, 0.0};
-  }
-}
-
-// ------------------------------------------------------------- Jacobi
 // 1 / sqrt(y) and 1 / d for normal positive y and nonzero d: hardware
 // estimates refined by two Newton steps each (r <- r (3 - y r^2) / 2 and
 // q <- q (2 - d q)), which take the estimate to within about an ulp.
@@ -255,6 +102,155 @@ __device__ __forceinline__ double rcp_nr(double d) {
   q = q * (2.0 - d * q);
   return q;
 }
+
+// In place lower Cholesky A = L L^H of the block, right-looking in LDL^H
+// form: step j takes the pivot d_j = A[j][j] and applies the rank-1 update
+// A[i][l] -= A[i][j] conj(A[l][j]) / d_j for j < l <= i; the columns are
+// scaled by 1 / sqrt(d_j) at the end.  Thread (w, i) holds A[i][4 t + w] in
+// r[t]; the raw pivots go to dpiv.  A non-positive or non-finite pivot is
+// replaced by 1 in the update so that the block stays finite (the caller
+// flags it and discards the result).
+__device__ __forceinline__ void chol64(c128 (&r)[CW], c128 (*colb)[NB], double* dpiv) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // slot tj unrolled (register indices stay static), owner wave wj not
+#pragma unroll
+  for (int tj = 0; tj < CW; ++tj) {
+#pragma unroll 1
+    for (int wj = 0; wj < 4; ++wj) {
+      const int j = 4 * tj + wj;
+      c128* col = colb[j & 1];
+      if (w == wj) col[lane] = r[tj];  // column j, final since step j - 1
+      __syncthreads();
+      const double draw = col[j].re;
+      if (threadIdx.x == 0) dpiv[j] = draw;
+      const double d = (draw > 0.0 && isfinite(draw)) ? draw : 1.0;
+      const c128 s = cscale(rcp_nr(d), col[lane]);
+      // all reads of the step first, so that their latencies overlap
+      c128 c[CW];
+#pragma unroll
+      for (int t = tj; t < CW; ++t) c[t] = col[4 * t + w];
+#pragma unroll
+      for (int t = tj; t < CW; ++t) {
+        const int l = 4 * t + w;
+        if ((t > tj || w > wj) && l <= lane) r[t] = csub(r[t], cmul(s, cconj(c[t])));
+      }
+    }
+  }
+}
+
+// X = L^{-1} by forward substitution on the 64 unit right-hand sides at
+// once: thread (w, c) holds X[4 t + w][c] in b[t]; step k finishes row k
+// (x_k = b_k / L[k][k]) on wave k mod 4, which publishes it, and every
+// wave updates its rows r > k by b_r -= L[r][k] x_k.  L (lower) is read
+// from S, its reciprocal diagonal from rpiv.
+__device__ __forceinline__ void trinv64(const c128 (*S)[NB + 1], const double* rpiv, c128 (*xb)[NB],
+                                        c128 (&b)[CW]) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+  for (int t = 0; t < CW; ++t) b[t] = (4 * t + w == lane) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+#pragma unroll
+  for (int tk = 0; tk < CW; ++tk) {
+#pragma unroll 1
+    for (int wk = 0; wk < 4; ++wk) {
+      const int k = 4 * tk + wk;
+      c128* xr = xb[k & 1];
+      if (w == wk) {
+        b[tk] = cscale(rpiv[k], b[tk]);
+        xr[lane] = b[tk];
+      }
+      __syncthreads();
+      const c128 x = xr[lane];
+      c128 l[CW];
+#pragma unroll
+      for (int t = tk; t < CW; ++t) l[t] = S[4 * t + w][k];
+#pragma unroll
+      for (int t = tk; t < CW; ++t)
+        if (t > tk || w > wk) b[t] = csub(b[t], cmul(l[t], x));
+    }
+  }
+}
+
+// Factor the 64 x 64 diagonal block at (p, p): writes L_pp (lower, upper
+// zeroed) in place and L_pp^{-1} into inv (64 x 64, ld 64).
+__global__ __launch_bounds__(CT) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
+  __shared__ c128 S[NB][NB + 1];
+  __shared__ c128 xb[2][NB];
+  __shared__ double dpiv[NB];
+  __shared__ double rpiv[NB];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  c128 r[CW];
+#pragma unroll
+  for (int t = 0; t < CW; ++t) r[t] = M[(int64_t)(p + 4 * t + w) * ld + p + lane];
+  chol64(r, xb, dpiv);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < CW; ++t) {
+    const int l = 4 * t + w;
+    const double dl = dpiv[l];
+    const double pv = (dl > 0.0 && isfinite(dl)) ? sqrt(dl) : 1.0;
+    const c128 v = lane > l ? cscale(1.0 / pv, r[t]) : (lane == l ? c128{pv, 0.0} : c128{0.0, 0.0});
+    S[lane][l] = v;
+    M[(int64_t)(p + l) * ld + p + lane] = v;
+    if (lane == l) {
+      rpiv[l] = 1.0 / pv;
+      if (!(dl > 0.0 && isfinite(dl))) atomicOr(fail, 1);
+    }
+  }
+  __syncthreads();
+  c128 b[CW];
+  trinv64(S, rpiv, xb, b);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < CW; ++t) S[4 * t + w][lane] = b[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < NB * NB; t += CT) {
+    const int j = t / NB, i = t % NB;
+    inv[(int64_t)j * NB + i] = (i >= j) ? S[i][j] : c128{0.0, 0.0};
+  }
+}
+
+__global__ void copy_block_kernel(const c128* src, int64_t lds, c128* dst, int64_t ldd, int rows, int cols) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = t / rows, i = t % rows;
+    dst[j * ldd + i] = src[j * lds + i];
+  }
+}
+
+// Invert each 64 x 64 diagonal block of a lower-triangular L (padded) and
+// write it into the diagonal of Linv.
+__global__ __launch_bounds__(CT) void trinv_diag_kernel(const c128* L, c128* X, int64_t ld) {
+  __shared__ c128 S[NB][NB + 1];
+  __shared__ c128 xb[2][NB];
+  __shared__ double rpiv[NB];
+  const int p = blockIdx.x * NB;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int t = threadIdx.x; t < NB * NB; t += CT) {
+    const int j = t / NB, i = t % NB;
+    S[i][j] = L[(int64_t)(p + j) * ld + p + i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) rpiv[threadIdx.x] = 1.0 / S[threadIdx.x][threadIdx.x].re;
+  __syncthreads();
+  c128 b[CW];
+  trinv64(S, rpiv, xb, b);
+  __syncthreads();
+  static_for<0, CW>([&](auto U) {
+    constexpr int t = decltype(U)::value;
+    S[4 * t + w][lane] = b[t];
+  });
+  __syncthreads();
+  for (int t = threadIdx.x; t < NB * NB; t += CT) {
+    const int j = t / NB, i = t % NB;
+    X[(int64_t)(p + j) * ld + p + i] = (i >= j) ? S[i][j] : c128{0.0, 0.0};
+  }
+}
+
+// ------------------------------------------------------------- Jacobi
 
 // Rotation annihilating b in [[a, b], [conj(b), d]] (a, d real).  With
 // x = d - a and the classical t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
@@ -676,7 +672,7 @@ Err cholesky_lower(c128* M, int kp, DenseWs& ws, hipStream_t s, bool* failed) {
   const int nblk = kp / NB;
   for (int b = 0; b < nblk; ++b) {
     const int p = b * NB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(PTHREADS), 0, s, M, (int64_t)kp, p, ws.small, ws.flag);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(CT), 0, s, M, (int64_t)kp, p, ws.small, ws.flag);
     CHASE_LAUNCH_CHECK();
     const int rest = kp - p - NB;
     if (rest <= 0) break;
@@ -714,7 +710,7 @@ Err cholesky_lower(c128* M, int kp, DenseWs& ws, hipStream_t s, bool* failed) {
 Err tri_inverse_lower(const c128* L, c128* X, int kp, DenseWs& ws, hipStream_t s) {
   const int nblk = kp / NB;
   CHASE_TRY(fill_padded(X, kp, kp, 0.0, 0.0, true, s));
-  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(PTHREADS), 0, s, L, X, (int64_t)kp);
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3(nblk), dim3(CT), 0, s, L, X, (int64_t)kp);
   CHASE_LAUNCH_CHECK();
   const int64_t stride = (int64_t)NB * (kp + 1);
   for (int d = 1; d < nblk; ++d) {
