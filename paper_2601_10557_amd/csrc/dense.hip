@@ -29,6 +29,13 @@ __device__ __forceinline__ c128 cconj(c128 a) { return {a.re, -a.im}; }
 __device__ __forceinline__ c128 cadd(c128 a, c128 b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ c128 csub(c128 a, c128 b) { return {a.re - b.re, a.im - b.im}; }
 __device__ __forceinline__ c128 cscale(double s, c128 a) { return {s * a.re, s * a.im}; }
+// r - a b and r - a conj(b), as four fused multiply-adds each
+__device__ __forceinline__ c128 cfms(c128 r, c128 a, c128 b) {
+  return {fma(-a.re, b.re, fma(a.im, b.im, r.re)), fma(-a.re, b.im, fma(-a.im, b.re, r.im))};
+}
+__device__ __forceinline__ c128 cfms_conj(c128 r, c128 a, c128 b) {
+  return {fma(-a.re, b.re, fma(-a.im, b.im, r.re)), fma(a.re, b.im, fma(-a.im, b.re, r.im))};
+}
 
 // ---------------------------------------------------------------- fills
 __global__ void fill_diag_kernel(c128* M, int64_t ld, int kp, int k, double inner, double pad, int zero_all) {
@@ -59,8 +66,8 @@ __global__ void zero_upper_kernel(c128* M, int64_t ld, int kp) {
 // (Cholesky) or column i (inverse), and wave w the 16 columns (rows)
 // w, w + 4, ..., w + 60 in registers: interleaved, so that the four waves
 // share the shrinking trailing part evenly.  A step publishes one column
-// (row) through LDS, double-buffered, so it takes one barrier, and every
-// other operand of the step is a broadcast LDS read.
+// (row) through LDS, on rotating buffers, so it takes one barrier, and
+// every other operand of the step is a broadcast LDS read.
 constexpr int CT = 256;     // threads of the block kernels
 constexpr int CW = NB / 4;  // columns (rows) per wave
 
@@ -103,40 +110,84 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return q;
 }
 
-// In place lower Cholesky A = L L^H of the block, right-looking in LDL^H
-// form: step j takes the pivot d_j = A[j][j] and applies the rank-1 update
-// A[i][l] -= A[i][j] conj(A[l][j]) / d_j for j < l <= i; the columns are
-// scaled by 1 / sqrt(d_j) at the end.  Thread (w, i) holds A[i][4 t + w] in
-// r[t]; the raw pivots go to dpiv.  A non-positive or non-finite pivot is
-// replaced by 1 in the update so that the block stays finite (the caller
-// flags it and discards the result).
-__device__ __forceinline__ void chol64(c128 (&r)[CW], c128 (*colb)[NB], double* dpiv) {
+// Lower Cholesky A = L L^H of the block and its inverse X = L^{-1}, run as
+// one sweep of 64 column steps with one barrier each.
+//  * Cholesky, right-looking in LDL^H form: step j takes the pivot
+//    d_j = A[j][j] and applies A[i][l] -= A[i][j] conj(A[l][j]) / d_j for
+//    j < l <= i; thread (w, i) holds A[i][4 t + w] in r[t], and the columns
+//    are scaled by 1 / sqrt(d_j) at the end.
+//  * Inverse, forward substitution on the 64 unit right-hand sides one step
+//    behind: step j finishes row j - 1 of X (x = b / L[j-1][j-1], on wave
+//    (j - 1) mod 4) and every wave updates its rows r > j - 1 by
+//    b_r -= L[r][j-1] x with column j - 1 of L (published the step before);
+//    thread (w, c) holds X[4 t + w][c] in b[t].
+// A step publishes column j (and row j - 1 of X) through LDS, the columns
+// triple-buffered since a step reads the last two.  A non-positive or
+// non-finite pivot is replaced by 1 so that the block stays finite (the
+// caller flags it and discards the result).  On return r holds the
+// unscaled columns, b the inverse, dpiv the raw pivots and rsq[j] =
+// 1 / sqrt(d_j) (1 for a replaced pivot).
+__device__ __forceinline__ void chol_inv64(c128 (&r)[CW], c128 (&b)[CW], c128 (*colb)[NB], c128 (*xb)[NB],
+                                           double* dpiv, double* rsq) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+  for (int t = 0; t < CW; ++t) b[t] = (4 * t + w == lane) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+  double rs_prev = 1.0;  // 1 / sqrt(d_{j-1})
   // slot tj unrolled (register indices stay static), owner wave wj not
 #pragma unroll
   for (int tj = 0; tj < CW; ++tj) {
 #pragma unroll 1
     for (int wj = 0; wj < 4; ++wj) {
       const int j = 4 * tj + wj;
-      c128* col = colb[j & 1];
+      const int k = j - 1;                  // row of X finished in this step
+      const int tk0 = tj > 0 ? tj - 1 : 0;  // its slot: tk0 (wj = 0) or tj
+      c128* col = colb[j % 3];
       if (w == wj) col[lane] = r[tj];  // column j, final since step j - 1
+      if (k >= 0 && w == (k & 3)) {
+        if (wj == 0) {
+          b[tk0] = cscale(rs_prev, b[tk0]);
+          xb[k & 1][lane] = b[tk0];
+        } else {
+          b[tj] = cscale(rs_prev, b[tj]);
+          xb[k & 1][lane] = b[tj];
+        }
+      }
       __syncthreads();
       const double draw = col[j].re;
-      if (threadIdx.x == 0) dpiv[j] = draw;
       const double d = (draw > 0.0 && isfinite(draw)) ? draw : 1.0;
+      if (threadIdx.x == 0) {
+        dpiv[j] = draw;
+        rsq[j] = rsqrt_nr(d);
+      }
       const c128 s = cscale(rcp_nr(d), col[lane]);
       // all reads of the step first, so that their latencies overlap
-      c128 c[CW];
+      c128 c[CW], l[CW];
 #pragma unroll
       for (int t = tj; t < CW; ++t) c[t] = col[4 * t + w];
+      c128 x{0.0, 0.0};
+      if (k >= 0) {
+        // x_{j-1} times the column scale of L[:, j-1]
+        x = cscale(rs_prev, xb[k & 1][lane]);
+        const c128* colk = colb[(j + 2) % 3];
 #pragma unroll
-      for (int t = tj; t < CW; ++t) {
-        const int l = 4 * t + w;
-        if ((t > tj || w > wj) && l <= lane) r[t] = csub(r[t], cmul(s, cconj(c[t])));
+        for (int t = tk0; t < CW; ++t) l[t] = colk[4 * t + w];
       }
+      // columns l > j, all rows: the entries above the diagonal (l > i) take
+      // updates too but are never read for an entry on or below it
+#pragma unroll
+      for (int t = tj; t < CW; ++t)
+        if (t > tj || w > wj) r[t] = cfms_conj(r[t], s, c[t]);
+      if (k >= 0) {
+#pragma unroll
+        for (int t = tk0; t < CW; ++t)
+          if (4 * t + w > k) b[t] = cfms(b[t], l[t], x);
+      }
+      rs_prev = rsqrt_nr(d);
     }
   }
+  // row 63 of X: its last update came with step 63
+  if (w == 3) b[CW - 1] = cscale(rs_prev, b[CW - 1]);
 }
 
 // X = L^{-1} by forward substitution on the 64 unit right-hand sides at
@@ -167,7 +218,7 @@ __device__ __forceinline__ void trinv64(const c128 (*S)[NB + 1], const double* r
       for (int t = tk; t < CW; ++t) l[t] = S[4 * t + w][k];
 #pragma unroll
       for (int t = tk; t < CW; ++t)
-        if (t > tk || w > wk) b[t] = csub(b[t], cmul(l[t], x));
+        if (t > tk || w > wk) b[t] = cfms(b[t], l[t], x);
     }
   }
 }
@@ -176,35 +227,27 @@ __device__ __forceinline__ void trinv64(const c128 (*S)[NB + 1], const double* r
 // zeroed) in place and L_pp^{-1} into inv (64 x 64, ld 64).
 __global__ __launch_bounds__(CT) void potrf_diag_kernel(c128* M, int64_t ld, int p, c128* inv, int* fail) {
   __shared__ c128 S[NB][NB + 1];
+  __shared__ c128 colb[3][NB];
   __shared__ c128 xb[2][NB];
   __shared__ double dpiv[NB];
-  __shared__ double rpiv[NB];
+  __shared__ double rsq[NB];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  c128 r[CW];
+  c128 r[CW], b[CW];
 #pragma unroll
   for (int t = 0; t < CW; ++t) r[t] = M[(int64_t)(p + 4 * t + w) * ld + p + lane];
-  chol64(r, xb, dpiv);
+  chol_inv64(r, b, colb, xb, dpiv, rsq);
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < CW; ++t) {
     const int l = 4 * t + w;
     const double dl = dpiv[l];
-    const double pv = (dl > 0.0 && isfinite(dl)) ? sqrt(dl) : 1.0;
-    const c128 v = lane > l ? cscale(1.0 / pv, r[t]) : (lane == l ? c128{pv, 0.0} : c128{0.0, 0.0});
-    S[lane][l] = v;
+    const bool ok = dl > 0.0 && isfinite(dl);
+    const c128 v = lane > l ? cscale(rsq[l], r[t]) : (lane == l ? c128{ok ? sqrt(dl) : 1.0, 0.0} : c128{0.0, 0.0});
     M[(int64_t)(p + l) * ld + p + lane] = v;
-    if (lane == l) {
-      rpiv[l] = 1.0 / pv;
-      if (!(dl > 0.0 && isfinite(dl))) atomicOr(fail, 1);
-    }
+    if (lane == l && !ok) atomicOr(fail, 1);
+    S[l][lane] = b[t];
   }
-  __syncthreads();
-  c128 b[CW];
-  trinv64(S, rpiv, xb, b);
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < CW; ++t) S[4 * t + w][lane] = b[t];
   __syncthreads();
   for (int t = threadIdx.x; t < NB * NB; t += CT) {
     const int j = t / NB, i = t % NB;
