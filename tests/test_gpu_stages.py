@@ -344,6 +344,26 @@ def test_qr_householder_fallback_rank_deficient(solver80, prob):
     assert np.max(np.abs(Q[:, :3] - Qo[:, :3])) < 1e-12
 
 
+def test_qr_many_cholesky_blocks(prob, solver260):
+    # k = 260: the Gram matrix is padded to 320, five 64-column blocks of the
+    # blocked Cholesky (diagonal-block factor and inverse, panel, update) and
+    # of the blocked inverse; Q and R are unique, so they match the oracle's
+    print_case("qr_many_blocks", m=prob.m, k=260)
+    rng = np.random.default_rng(41)
+    X = complex_normal(rng, (prob.n, 260))
+    Xd = to_dev(X)
+    R, shifted = solver260.qr(Xd)
+    Q, R = to_host(Xd), to_host(R)
+    Qr, Rr, sh = oqr.cholqr2(X)
+    assert not shifted and not sh
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(260))) < 1e-12
+    assert np.max(np.abs(Q @ R - X)) < 1e-12 * np.max(np.abs(X))
+    assert np.max(np.abs(np.tril(R, -1))) == 0.0
+    assert np.allclose(np.diag(R).imag, 0) and np.all(np.diag(R).real > 0)
+    assert np.max(np.abs(Q - Qr)) < 1e-10
+    assert np.max(np.abs(R - Rr)) < 1e-10 * np.max(np.abs(Rr))
+
+
 @pytest.mark.parametrize("kh", [2, 20])
 def test_oblique_rr_and_residuals(prob, solver, kh):
     print_case("oblique_rr", m=prob.m, k=2 * kh)
